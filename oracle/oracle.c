@@ -1,0 +1,931 @@
+/*
+ * FP64 CPU oracle of the PD-NOMA H-CRAN energy-efficiency allocator.
+ *
+ * TEST INFRASTRUCTURE ONLY (see oracle.h).  Plain loops in double precision,
+ * one step of the method after another, in the order the paper gives them.
+ * Parallelism is limited to an OpenMP loop over subcarriers for work that the
+ * method defines per subcarrier; every sum across subcarriers is taken
+ * afterwards, serially, in increasing subcarrier order.
+ *
+ * Notation (Table I): m RRH (0 = HPN), n subcarrier, k user, Gamma channel
+ * gain, sigma noise, p power, A RRH association, rho subcarrier allocation
+ * (held here as the list "sel" of at most l users per (m,n)), xi' (C12),
+ * zeta' (C13), zeta~' (C14) Lagrange multipliers, alpha/beta SCALE
+ * coefficients, E the Dinkelbach energy-efficiency parameter.
+ *
+ * Readings where the paper is silent or ambiguous (each listed with its
+ * reason in the design notes):
+ *  - decoding order on (m,n) is by normalised gain Gamma/(sigma+ICI),
+ *    descending, ties to the lower user index; with it, C14 holds exactly
+ *    when raw-gain order and decoding order agree;
+ *  - interference prices use the full gradient over all victims, each victim
+ *    weighted by mu = 1 (elastic) or zeta'_k (streaming);
+ *  - C14 is used as the scale-free margin Omega/nu with
+ *    nu = Gamma_w(sigma+ICI_s) + Gamma_s(sigma+ICI_w) taken at the state;
+ *  - the binary constraints are met by selection: per (m,n) the l users of
+ *    RRH m with the largest positive per-triple Lagrangian maximum H; per user
+ *    the RRH with the largest sum of H over subcarriers, applied from the next
+ *    sweep;
+ *  - subgradient step step0/sqrt(1+v); xi' scaled by N*l/(ln2*pmax_m);
+ *    the relative C13 violation clipped to [-1, 1];
+ *  - churn cap: within one Dinkelbach step the selected set of an (m,n) and
+ *    the RRH of a user may change at most churn_limit times, after which
+ *    they are frozen (simultaneous discrete updates can cycle); all
+ *    sweeps are Jacobi (every quantity of a sweep is read from the state the
+ *    sweep starts from).
+ */
+#include "oracle.h"
+
+#include <float.h>
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_API __attribute__((visibility("default")))
+#define LN2 0.69314718055994530942
+#define MAXL 8
+
+/* ------------------------------------------------------------------ basics */
+
+/* log2(1+x) */
+static double log2_1p(double x) { return log1p(x) / LN2; }
+
+/* Sec. II-B, constraint C9: Psi = Psi_hat / B_n with
+ * Psi_hat = 2 lambda zbar / ((2 + 2 lambda T) - sqrt((2 + 2 lambda T)^2 - 8 lambda T)).
+ * With x = lambda T the discriminant is 4(1+x^2), so the denominator is
+ * 2(1 - 1/(x + sqrt(1+x^2))), the cancellation-free form used here. */
+ORC_API double orc_min_rate(double arrival_bps, double delay_s, double packet_bits,
+                            double bw_hz) {
+  const double lambda = arrival_bps / packet_bits; /* packets/s */
+  const double x = lambda * delay_s;
+  const double den = 1.0 - 1.0 / (x + sqrt(1.0 + x * x));
+  return (lambda * packet_bits / den) / bw_hz;
+}
+
+/* Sec. IV-A, SCALE bound alpha log2 z + beta <= log2(1+z), tight at z0. */
+ORC_API void orc_scale_coeffs(double z0, double* alpha, double* beta) {
+  *alpha = z0 / (1.0 + z0);
+  *beta = log2_1p(z0) - (*alpha) * log2(z0);
+}
+
+/* Eq. (SIC_linear) with sigma_k = sigma_k' = sigma: for raw-stronger s and
+ * weaker w, Omega = Gamma_w sigma - Gamma_s sigma + Gamma_w ICI_s - Gamma_s ICI_w,
+ * and C8/C14 ask Omega <= 0.  Returned divided by the positive scale
+ * nu = Gamma_w (sigma + ICI_s) + Gamma_s (sigma + ICI_w). */
+ORC_API double orc_sic_margin(double g_s, double g_w, double ici_s, double ici_w,
+                              double sigma) {
+  const double omega = g_w * sigma - g_s * sigma + g_w * ici_s - g_s * ici_w;
+  const double nu = g_w * (sigma + ici_s) + g_s * (sigma + ici_w);
+  return omega / nu;
+}
+
+/* ------------------------------------------------------------------- state */
+
+struct orc_state {
+  int M, N, K, L;
+  double* G; /* [M][N][K] */
+  int* elastic;
+  double* psi;
+  double *pmax, *eta, *pmask;
+  double* w; /* [M][K] */
+  double sigma, pstatic;
+  orc_params prm;
+  double E;
+  int* A;                     /* [K] */
+  int* sel;                   /* [M][N][L] user or -1, in selection-rank order */
+  double *p, *al, *be;        /* [M][N][L] */
+  double* zs;                 /* [M][N][L][L] multiplier of C14 per slot pair */
+  double *xi, *zeta;          /* [M], [K] */
+  double* H;                  /* [M][N][K] per-triple Lagrangian maximum */
+  double *part_psum, *part_pel; /* [N][M] */
+  double *part_r, *part_rh;   /* [N][K] */
+  double* part_delta;         /* [N] */
+  int64_t* part_ties;         /* [N] */
+  double* part_margin;        /* [N] */
+  int64_t ties;
+  double min_margin;
+  int first_tie;
+  int sweeps_done;
+  int assoc_changed; /* users whose RRH changed in the last sweep */
+  int* churn_sel;    /* [M][N] selection changes in this Dinkelbach step */
+  int* churn_A;      /* [K] association changes in this Dinkelbach step */
+};
+
+#define IDX3(st, m, n, k) (((size_t)(m) * (st)->N + (n)) * (st)->K + (k))
+#define SLOT(st, m, n, s) (((size_t)(m) * (st)->N + (n)) * (st)->L + (s))
+#define PAIR(st, m, n, a, b) ((((size_t)(m) * (st)->N + (n)) * (st)->L + (a)) * (st)->L + (b))
+
+static double mu_of(const orc_state* st, int k) { return st->elastic[k] ? 1.0 : st->zeta[k]; }
+
+static void note_margin(double margin, double tie_rel, int64_t* ties, double* minm) {
+  if (margin < *minm) *minm = margin;
+  if (margin <= tie_rel) (*ties)++;
+}
+
+static int validate(const orc_problem* pb) {
+  if (!pb || pb->M < 1 || pb->N < 1 || pb->K < 1 || pb->l < 1 || pb->l > MAXL ||
+      pb->l > pb->K || pb->M > 64 || pb->K > 4096)
+    return -22;
+  if (!pb->gain || !pb->user_type || !pb->pmax_w || !pb->eta) return -22;
+  if (!(pb->noise_w > 0) || !(pb->bw_hz > 0) || !(pb->packet_bits > 0)) return -22;
+  const size_t n3 = (size_t)pb->M * pb->N * pb->K;
+  for (size_t i = 0; i < n3; ++i)
+    if (!(pb->gain[i] > 0.0f) || !isfinite(pb->gain[i])) return -22;
+  for (int m = 0; m < pb->M; ++m) {
+    if (!(pb->pmax_w[m] > 0) || !isfinite(pb->pmax_w[m]) || !(pb->eta[m] > 0)) return -22;
+    if (pb->pmask_w && !(pb->pmask_w[m] > 0)) return -22;
+  }
+  for (int k = 0; k < pb->K; ++k) {
+    if (pb->user_type[k] > 1) return -22;
+    if (pb->user_type[k] == 1) {
+      if (!pb->arrival_bps || !pb->delay_s) return -22;
+      if (!(pb->arrival_bps[k] > 0) || !(pb->delay_s[k] > 0)) return -22;
+    }
+  }
+  if (pb->weight)
+    for (int i = 0; i < pb->M * pb->K; ++i)
+      if (!(pb->weight[i] >= 0) || !isfinite(pb->weight[i])) return -22;
+  return 0;
+}
+
+/* Top-l of users by key desc, ties to the lower user index. */
+static void top_by_key(const double* key, const int* users, int cnt, int l, int* out,
+                       int* nout) {
+  int idx[4096];
+  int c = cnt < 4096 ? cnt : 4096;
+  for (int i = 0; i < c; ++i) idx[i] = i;
+  /* insertion sort: fine for the short lists of one (m,n) */
+  for (int i = 1; i < c; ++i) {
+    int t = idx[i], j = i - 1;
+    while (j >= 0 && (key[idx[j]] < key[t] ||
+                      (key[idx[j]] == key[t] && users[idx[j]] > users[t]))) {
+      idx[j + 1] = idx[j];
+      --j;
+    }
+    idx[j + 1] = t;
+  }
+  *nout = c < l ? c : l;
+  for (int i = 0; i < *nout; ++i) out[i] = idx[i];
+}
+
+/* Cold start (initial feasible point of the Dinkelbach iteration, Sec. IV):
+ * max-SNR association, strongest l users per (m,n), equal split of pmax. */
+static void cold_start(orc_state* st) {
+  const int M = st->M, N = st->N, K = st->K, L = st->L;
+  for (int k = 0; k < K; ++k) {
+    int best = 0;
+    double bestv = -1.0;
+    for (int m = 0; m < M; ++m) {
+      double s = 0.0;
+      for (int n = 0; n < N; ++n) s += log2_1p(st->G[IDX3(st, m, n, k)] * st->pmask[m] / st->sigma);
+      if (s > bestv) {
+        bestv = s;
+        best = m;
+      }
+    }
+    st->A[k] = best;
+  }
+  for (int m = 0; m < M; ++m)
+    for (int n = 0; n < N; ++n) {
+      double key[4096];
+      int users[4096], cnt = 0, pick[MAXL], np;
+      for (int k = 0; k < K; ++k)
+        if (st->A[k] == m) {
+          key[cnt] = st->G[IDX3(st, m, n, k)];
+          users[cnt++] = k;
+        }
+      top_by_key(key, users, cnt, L, pick, &np);
+      for (int s = 0; s < L; ++s) {
+        const size_t i = SLOT(st, m, n, s);
+        st->sel[i] = (s < np) ? users[pick[s]] : -1;
+        st->p[i] = (s < np) ? st->pmax[m] / ((double)N * L) : 0.0;
+        st->al[i] = 1.0;
+        st->be[i] = 0.0;
+      }
+    }
+  for (int m = 0; m < M; ++m) st->xi[m] = 0.0;
+  for (int k = 0; k < K; ++k) st->zeta[k] = st->elastic[k] ? 0.0 : 1.0;
+  memset(st->zs, 0, sizeof(double) * (size_t)M * N * L * L);
+}
+
+/* Warm start: association by the largest total initial power, the l users of
+ * largest positive initial power per (m,n), powers clipped to the mask. */
+static void warm_start(orc_state* st, const orc_warm* wm) {
+  const int M = st->M, N = st->N, K = st->K, L = st->L;
+  if (wm->p0) {
+    for (int k = 0; k < K; ++k) {
+      int best = -1;
+      double bestv = 0.0;
+      for (int m = 0; m < M; ++m) {
+        double s = 0.0;
+        for (int n = 0; n < N; ++n) s += wm->p0[IDX3(st, m, n, k)];
+        if (s > bestv) {
+          bestv = s;
+          best = m;
+        }
+      }
+      if (best >= 0) st->A[k] = best; /* else keep the cold-start association */
+    }
+    for (int m = 0; m < M; ++m)
+      for (int n = 0; n < N; ++n) {
+        double key[4096];
+        int users[4096], cnt = 0, pick[MAXL], np;
+        for (int k = 0; k < K; ++k)
+          if (st->A[k] == m && wm->p0[IDX3(st, m, n, k)] > 0.0) {
+            key[cnt] = wm->p0[IDX3(st, m, n, k)];
+            users[cnt++] = k;
+          }
+        top_by_key(key, users, cnt, L, pick, &np);
+        for (int s = 0; s < L; ++s) {
+          const size_t i = SLOT(st, m, n, s);
+          st->sel[i] = (s < np) ? users[pick[s]] : -1;
+          st->p[i] = (s < np) ? fmin(key[pick[s]], st->pmask[m]) : 0.0;
+          st->al[i] = 1.0;
+          st->be[i] = 0.0;
+        }
+      }
+  }
+  if (wm->xi0)
+    for (int m = 0; m < M; ++m) st->xi[m] = fmax(wm->xi0[m], 0.0);
+  if (wm->zeta0)
+    for (int k = 0; k < K; ++k) st->zeta[k] = st->elastic[k] ? 0.0 : fmax(wm->zeta0[k], 0.0);
+}
+
+ORC_API orc_state* orc_state_create(const orc_problem* pb, const orc_params* prm,
+                                    const orc_warm* warm) {
+  if (validate(pb) != 0) return NULL;
+  orc_state* st = (orc_state*)calloc(1, sizeof(orc_state));
+  const int M = pb->M, N = pb->N, K = pb->K, L = pb->l;
+  const size_t n3 = (size_t)M * N * K, ns = (size_t)M * N * L;
+  st->M = M;
+  st->N = N;
+  st->K = K;
+  st->L = L;
+  st->prm = *prm;
+  st->G = (double*)malloc(sizeof(double) * n3);
+  for (size_t i = 0; i < n3; ++i) st->G[i] = (double)pb->gain[i];
+  st->elastic = (int*)malloc(sizeof(int) * K);
+  st->psi = (double*)malloc(sizeof(double) * K);
+  for (int k = 0; k < K; ++k) {
+    st->elastic[k] = pb->user_type[k] == 0;
+    st->psi[k] = st->elastic[k] ? 0.0
+                                : orc_min_rate(pb->arrival_bps[k], pb->delay_s[k],
+                                               pb->packet_bits, pb->bw_hz);
+  }
+  st->pmax = (double*)malloc(sizeof(double) * M);
+  st->eta = (double*)malloc(sizeof(double) * M);
+  st->pmask = (double*)malloc(sizeof(double) * M);
+  for (int m = 0; m < M; ++m) {
+    st->pmax[m] = pb->pmax_w[m];
+    st->eta[m] = pb->eta[m];
+    st->pmask[m] = pb->pmask_w ? pb->pmask_w[m] : pb->pmax_w[m] / N; /* Sec. VIII */
+  }
+  st->w = (double*)malloc(sizeof(double) * M * K);
+  for (int i = 0; i < M * K; ++i) st->w[i] = pb->weight ? pb->weight[i] : 1.0;
+  st->sigma = pb->noise_w;
+  /* Power model (Sec. II-A): P = P_f^H + M_f P_f^L + sum eta p + M_f P_c^L + P_c^H. */
+  st->pstatic = pb->p_fiber_hpn + (M - 1) * pb->p_fiber_lpn + (M - 1) * pb->p_circuit_lpn +
+                pb->p_circuit_hpn;
+  st->E = 0.0;
+  st->A = (int*)malloc(sizeof(int) * K);
+  st->sel = (int*)malloc(sizeof(int) * ns);
+  st->p = (double*)malloc(sizeof(double) * ns);
+  st->al = (double*)malloc(sizeof(double) * ns);
+  st->be = (double*)malloc(sizeof(double) * ns);
+  st->zs = (double*)calloc(ns * L, sizeof(double));
+  st->xi = (double*)malloc(sizeof(double) * M);
+  st->zeta = (double*)malloc(sizeof(double) * K);
+  st->H = (double*)malloc(sizeof(double) * n3);
+  st->part_psum = (double*)malloc(sizeof(double) * N * M);
+  st->part_pel = (double*)malloc(sizeof(double) * N * M);
+  st->part_r = (double*)malloc(sizeof(double) * (size_t)N * K);
+  st->part_rh = (double*)malloc(sizeof(double) * (size_t)N * K);
+  st->part_delta = (double*)malloc(sizeof(double) * N);
+  st->part_ties = (int64_t*)malloc(sizeof(int64_t) * N);
+  st->part_margin = (double*)malloc(sizeof(double) * N);
+  st->churn_sel = (int*)calloc((size_t)M * N, sizeof(int));
+  st->churn_A = (int*)calloc(K, sizeof(int));
+  st->min_margin = INFINITY;
+  st->first_tie = -1;
+  cold_start(st);
+  if (warm) warm_start(st, warm);
+  return st;
+}
+
+ORC_API void orc_state_destroy(orc_state* st) {
+  if (!st) return;
+  free(st->G); free(st->elastic); free(st->psi); free(st->pmax); free(st->eta);
+  free(st->pmask); free(st->w); free(st->A); free(st->sel); free(st->p); free(st->al);
+  free(st->be); free(st->zs); free(st->xi); free(st->zeta); free(st->H);
+  free(st->part_psum); free(st->part_pel); free(st->part_r); free(st->part_rh);
+  free(st->part_delta); free(st->part_ties); free(st->part_margin);
+  free(st->churn_sel); free(st->churn_A);
+  free(st);
+}
+
+ORC_API void orc_state_set_E(orc_state* st, double E) { st->E = E; }
+
+/* Start of a Dinkelbach step: the churn counters restart. */
+ORC_API void orc_state_reset_churn(orc_state* st) {
+  memset(st->churn_sel, 0, sizeof(int) * (size_t)st->M * st->N);
+  memset(st->churn_A, 0, sizeof(int) * st->K);
+}
+
+/* Alg. 1 initialisation: alpha = 1, beta = 0 (high-SIR approximation). */
+ORC_API void orc_state_reset_scale(orc_state* st) {
+  const size_t ns = (size_t)st->M * st->N * st->L;
+  for (size_t i = 0; i < ns; ++i) {
+    st->al[i] = 1.0;
+    st->be[i] = 0.0;
+  }
+}
+
+/* ------------------------------------------------------- one subcarrier */
+
+/* Evaluation of RRH m's selected users on subcarrier n at the state. */
+typedef struct {
+  int cnt;
+  int slot[MAXL];    /* storage slot at decoding position q */
+  int user[MAXL];
+  double gt[MAXL];   /* normalised gain Gamma/(sigma+ICI) */
+  double pre[MAXL + 1]; /* power of the users decoded before position q */
+  double I[MAXL];    /* interference after SIC (Sec. II-A) */
+  double gam[MAXL];  /* SINR gamma'' */
+  double r[MAXL];    /* log2(1+gamma) */
+  double rh[MAXL];   /* SCALE surrogate beta + alpha log2 gamma */
+  double c[MAXL];    /* w mu alpha / (ln2 (sigma + I)) */
+  double cg[MAXL];   /* c * Gamma_{m,n,user}: price of interference on this user */
+} mview;
+
+/* ICI and per-RRH evaluation on subcarrier n; optionally refits SCALE. */
+static void eval_subcarrier(orc_state* st, int n, int refit, double* ici, mview* vw,
+                            int64_t* ties, double* minm) {
+  const int M = st->M, K = st->K, L = st->L;
+  const double sg = st->sigma;
+  double Ptot[64];
+  for (int m = 0; m < M; ++m) {
+    Ptot[m] = 0.0;
+    for (int s = 0; s < L; ++s)
+      if (st->sel[SLOT(st, m, n, s)] >= 0) Ptot[m] += st->p[SLOT(st, m, n, s)];
+  }
+  /* Inter-cell interference: sum over the other RRHs of their total power on n. */
+  for (int m = 0; m < M; ++m)
+    for (int k = 0; k < K; ++k) {
+      double acc = 0.0;
+      for (int j = 0; j < M; ++j)
+        if (j != m) acc += Ptot[j] * st->G[IDX3(st, j, n, k)];
+      ici[(size_t)m * K + k] = acc;
+    }
+  for (int m = 0; m < M; ++m) {
+    mview* v = &vw[m];
+    v->cnt = 0;
+    for (int s = 0; s < L; ++s) {
+      const int k = st->sel[SLOT(st, m, n, s)];
+      if (k < 0) continue;
+      v->slot[v->cnt] = s;
+      v->user[v->cnt] = k;
+      v->gt[v->cnt] = st->G[IDX3(st, m, n, k)] / (sg + ici[(size_t)m * K + k]);
+      v->cnt++;
+    }
+    /* decoding order: normalised gain descending, ties to the lower user */
+    for (int i = 1; i < v->cnt; ++i) {
+      int j = i;
+      while (j > 0 && (v->gt[j - 1] < v->gt[j] ||
+                       (v->gt[j - 1] == v->gt[j] && v->user[j - 1] > v->user[j]))) {
+        int ts = v->slot[j]; v->slot[j] = v->slot[j - 1]; v->slot[j - 1] = ts;
+        int tu = v->user[j]; v->user[j] = v->user[j - 1]; v->user[j - 1] = tu;
+        double tg = v->gt[j]; v->gt[j] = v->gt[j - 1]; v->gt[j - 1] = tg;
+        --j;
+      }
+    }
+    for (int q = 0; q + 1 < v->cnt; ++q)
+      note_margin((v->gt[q] - v->gt[q + 1]) / v->gt[q], st->prm.tie_rel, ties, minm);
+    v->pre[0] = 0.0;
+    for (int q = 0; q < v->cnt; ++q) v->pre[q + 1] = v->pre[q] + st->p[SLOT(st, m, n, v->slot[q])];
+    for (int q = 0; q < v->cnt; ++q) {
+      const int k = v->user[q];
+      const size_t si = SLOT(st, m, n, v->slot[q]);
+      const double g = st->G[IDX3(st, m, n, k)];
+      /* users decoded earlier (stronger) interfere; weaker ones are cancelled */
+      v->I[q] = ici[(size_t)m * K + k] + g * v->pre[q];
+      v->gam[q] = st->p[si] * g / (sg + v->I[q]);
+      v->r[q] = log2_1p(v->gam[q]);
+      if (refit && st->p[si] > 0.0) orc_scale_coeffs(v->gam[q], &st->al[si], &st->be[si]);
+      v->rh[q] = (st->p[si] > 0.0) ? st->be[si] + st->al[si] * log2(v->gam[q]) : 0.0;
+      v->c[q] = st->w[(size_t)m * K + k] * mu_of(st, k) * st->al[si] / (LN2 * (sg + v->I[q]));
+      v->cg[q] = v->c[q] * g;
+    }
+  }
+}
+
+/* Per-subcarrier part of one dual sweep (Alg. 1 inner loop body). */
+static void sweep_subcarrier(orc_state* st, int n, double delta_v, int refit) {
+  const int M = st->M, K = st->K, L = st->L;
+  const double sg = st->sigma, tr = st->prm.tie_rel;
+  int64_t ties = 0;
+  double minm = INFINITY;
+  double* ici = (double*)malloc(sizeof(double) * (size_t)M * K);
+  mview* vw = (mview*)malloc(sizeof(mview) * M);
+  eval_subcarrier(st, n, refit, ici, vw, &ties, &minm);
+
+  /* Partial sums at the state: power per RRH, rates per user. */
+  for (int m = 0; m < M; ++m) {
+    double ps = 0.0, pe = 0.0;
+    for (int q = 0; q < vw[m].cnt; ++q) {
+      const double pq = st->p[SLOT(st, m, n, vw[m].slot[q])];
+      ps += pq;
+      if (st->elastic[vw[m].user[q]]) pe += pq;
+    }
+    st->part_psum[(size_t)n * M + m] = ps;
+    st->part_pel[(size_t)n * M + m] = pe;
+  }
+  for (int k = 0; k < K; ++k) {
+    st->part_r[(size_t)n * K + k] = 0.0;
+    st->part_rh[(size_t)n * K + k] = 0.0;
+  }
+  for (int m = 0; m < M; ++m)
+    for (int q = 0; q < vw[m].cnt; ++q) {
+      const int k = vw[m].user[q];
+      st->part_r[(size_t)n * K + k] += st->w[(size_t)m * K + k] * vw[m].r[q];
+      st->part_rh[(size_t)n * K + k] += st->w[(size_t)m * K + k] * vw[m].rh[q];
+    }
+
+  /* Inter-cell price: psi-bar' of the closed forms, the marginal rate loss of
+   * the users of the other RRHs per watt transmitted by RRH m on n. */
+  double pinter[64], psic[64];
+  for (int m = 0; m < M; ++m) {
+    double acc = 0.0;
+    for (int j = 0; j < M; ++j) {
+      if (j == m) continue;
+      for (int q = 0; q < vw[j].cnt; ++q) acc += vw[j].c[q] * st->G[IDX3(st, m, n, vw[j].user[q])];
+    }
+    pinter[m] = acc;
+    psic[m] = 0.0;
+  }
+
+  /* SIC constraint C14 (DC-linearised, affine in the other RRHs' powers):
+   * the multiplier of each co-scheduled pair adds zeta~ dOmega/dp_j to the
+   * price of RRH j on n; then the pair's subgradient step. */
+  double zs_new[64][MAXL][MAXL];
+  for (int m = 0; m < M; ++m) {
+    const mview* v = &vw[m];
+    for (int a = 0; a < v->cnt; ++a)
+      for (int b = a + 1; b < v->cnt; ++b) {
+        int ka = v->user[a], kb = v->user[b];
+        const double ga = st->G[IDX3(st, m, n, ka)], gb = st->G[IDX3(st, m, n, kb)];
+        /* strong = larger raw gain, ties to the lower user index */
+        int ks = ka, kw = kb;
+        if (gb > ga || (gb == ga && kb < ka)) {
+          ks = kb;
+          kw = ka;
+        }
+        const double gs = st->G[IDX3(st, m, n, ks)], gw = st->G[IDX3(st, m, n, kw)];
+        const double is = ici[(size_t)m * K + ks], iw = ici[(size_t)m * K + kw];
+        const double om = orc_sic_margin(gs, gw, is, iw, sg);
+        const double nu = gw * (sg + is) + gs * (sg + iw);
+        const int sa = v->slot[a], sb = v->slot[b];
+        const double z = st->zs[PAIR(st, m, n, sa, sb)];
+        for (int j = 0; j < M; ++j) {
+          if (j == m) continue;
+          const double dj = (gw * st->G[IDX3(st, j, n, ks)] - gs * st->G[IDX3(st, j, n, kw)]) / nu;
+          psic[j] += z * dj;
+        }
+        const double zn = fmax(z + delta_v * om, 0.0);
+        zs_new[m][sa][sb] = zn;
+        zs_new[m][sb][sa] = zn;
+      }
+  }
+
+  /* Per-triple Lagrangian maximum H and candidate lists. */
+  double* cand_Hbuf = (double*)malloc(sizeof(double) * (size_t)M * K);
+  int* cand_kbuf = (int*)malloc(sizeof(int) * (size_t)M * K);
+  double* cand_pintra = (double*)malloc(sizeof(double) * K); /* intra price on A_k */
+#define cand_H(m) (cand_Hbuf + (size_t)(m) * K)
+#define cand_k(m) (cand_kbuf + (size_t)(m) * K)
+  int ncand[64], nbdry[64];
+  for (int m = 0; m < M; ++m) {
+    ncand[m] = 0;
+    nbdry[m] = 0;
+  }
+  for (int m = 0; m < M; ++m) {
+    const mview* v = &vw[m];
+    for (int k = 0; k < K; ++k) {
+      const double g = st->G[IDX3(st, m, n, k)];
+      const double ik = ici[(size_t)m * K + k];
+      int q = -1;
+      for (int t = 0; t < v->cnt; ++t)
+        if (v->user[t] == k) q = t;
+      double Sb, pintra = 0.0;
+      if (q >= 0) {
+        Sb = v->pre[q];
+        for (int t = q + 1; t < v->cnt; ++t) pintra += v->cg[t];
+      } else {
+        const double gk = g / (sg + ik);
+        int pos = 0;
+        for (int t = 0; t < v->cnt; ++t) {
+          if (v->gt[t] > gk || (v->gt[t] == gk && v->user[t] < k)) pos++;
+          note_margin(fabs(v->gt[t] - gk) / fmax(v->gt[t], gk), tr, &ties, &minm);
+        }
+        Sb = v->pre[pos];
+        for (int t = pos; t < v->cnt; ++t) pintra += v->cg[t];
+      }
+      const double a = g / (sg + ik + g * Sb);
+      const double wmu = st->w[(size_t)m * K + k] * mu_of(st, k);
+      const double c = (st->elastic[k] ? st->E * st->eta[m] : 0.0) + st->xi[m] + pintra +
+                       pinter[m] + psic[m];
+      double H = 0.0;
+      if (wmu > 0.0) {
+        double pt;
+        if (c <= 0.0) {
+          pt = st->pmask[m];
+        } else {
+          const double Wl = wmu / (c * LN2);
+          const double d = Wl - 1.0 / a;
+          if (st->A[k] == m && fabs(d) <= tr * Wl) nbdry[m]++;
+          pt = fmin(fmax(d, 0.0), st->pmask[m]);
+        }
+        if (pt > 0.0) H = wmu * log2_1p(a * pt) - c * pt;
+      }
+      st->H[IDX3(st, m, n, k)] = H;
+      if (st->A[k] == m) {
+        cand_pintra[k] = pintra;
+        if (H > 0.0) {
+          cand_H(m)[ncand[m]] = H;
+          cand_k(m)[ncand[m]] = k;
+          ncand[m]++;
+        }
+      }
+    }
+  }
+
+  /* Selection and closed-form powers for the new selection. */
+  double dmax = 0.0;
+  for (int m = 0; m < M; ++m) {
+    const mview* v = &vw[m];
+    int pick[MAXL], np;
+    const int lim = st->prm.churn_limit;
+    const int frozen = lim > 0 && st->churn_sel[(size_t)m * st->N + n] >= lim;
+    top_by_key(cand_H(m), cand_k(m), ncand[m], L, pick, &np);
+    if (!frozen && ncand[m] > L) {
+      /* margin between the l-th and the (l+1)-th candidate */
+      int ord[MAXL + 1], no;
+      top_by_key(cand_H(m), cand_k(m), ncand[m], L + 1, ord, &no);
+      const double hl = cand_H(m)[ord[L - 1]], hn = cand_H(m)[ord[L]];
+      note_margin((hl - hn) / hl, tr, &ties, &minm);
+    }
+    if (nbdry[m] > 0 && ncand[m] <= L + nbdry[m]) ties += nbdry[m];
+
+    int new_user[MAXL];
+    double new_p[MAXL], new_al[MAXL], new_be[MAXL];
+    int chosen[MAXL];
+    if (frozen) {
+      /* churn cap reached: keep the incumbents still associated with m */
+      np = 0;
+      for (int t = 0; t < v->cnt; ++t)
+        if (st->A[v->user[t]] == m) chosen[np++] = v->user[t];
+    } else {
+      for (int s = 0; s < np; ++s) chosen[s] = cand_k(m)[pick[s]];
+      /* count a change of the selected set */
+      int same = (np == v->cnt);
+      for (int s = 0; s < np && same; ++s) {
+        int found = 0;
+        for (int t = 0; t < v->cnt; ++t)
+          if (v->user[t] == chosen[s]) found = 1;
+        same = found;
+      }
+      if (!same) st->churn_sel[(size_t)m * st->N + n]++;
+    }
+    for (int s = 0; s < L; ++s) new_user[s] = -1;
+    for (int s = 0; s < np; ++s) {
+      const int k = chosen[s];
+      int old = -1;
+      for (int t = 0; t < v->cnt; ++t)
+        if (v->user[t] == k) old = v->slot[t];
+      double p_old = 0.0, alph = 1.0, bet = 0.0;
+      if (old >= 0) {
+        const size_t si = SLOT(st, m, n, old);
+        p_old = st->p[si];
+        alph = st->al[si];
+        bet = st->be[si];
+      }
+      const double wmu = st->w[(size_t)m * K + k] * mu_of(st, k);
+      const double pplus = fmax(psic[m], 0.0), pminus = fmax(-psic[m], 0.0);
+      const double cp = (st->elastic[k] ? st->E * st->eta[m] : 0.0) + st->xi[m] +
+                        cand_pintra[k] + pinter[m] + pplus;
+      const double num = wmu * alph / LN2 + p_old * pminus;
+      const double pn = (cp > 0.0) ? fmin(fmax(num / cp, 0.0), st->pmask[m]) : st->pmask[m];
+      new_user[s] = k;
+      new_p[s] = pn;
+      new_al[s] = alph;
+      new_be[s] = bet;
+    }
+    /* max |p_new - p_old| / pmask over the old and new slots of (m,n) */
+    for (int s = 0; s < np; ++s) {
+      double p_old = 0.0;
+      for (int t = 0; t < v->cnt; ++t)
+        if (v->user[t] == new_user[s]) p_old = st->p[SLOT(st, m, n, v->slot[t])];
+      dmax = fmax(dmax, fabs(new_p[s] - p_old) / st->pmask[m]);
+    }
+    for (int t = 0; t < v->cnt; ++t) {
+      int kept = 0;
+      for (int s = 0; s < np; ++s)
+        if (new_user[s] == v->user[t]) kept = 1;
+      if (!kept) dmax = fmax(dmax, st->p[SLOT(st, m, n, v->slot[t])] / st->pmask[m]);
+    }
+    /* C14 multipliers follow their user pair into the new slots. */
+    double zmap[MAXL][MAXL];
+    for (int a = 0; a < L; ++a)
+      for (int b = 0; b < L; ++b) zmap[a][b] = 0.0;
+    for (int a = 0; a < np; ++a)
+      for (int b = 0; b < np; ++b) {
+        if (a == b) continue;
+        int oa = -1, ob = -1;
+        for (int t = 0; t < v->cnt; ++t) {
+          if (v->user[t] == new_user[a]) oa = v->slot[t];
+          if (v->user[t] == new_user[b]) ob = v->slot[t];
+        }
+        if (oa >= 0 && ob >= 0) zmap[a][b] = zs_new[m][oa][ob];
+      }
+    for (int s = 0; s < L; ++s) {
+      const size_t si = SLOT(st, m, n, s);
+      st->sel[si] = new_user[s];
+      st->p[si] = (s < np) ? new_p[s] : 0.0;
+      st->al[si] = (s < np) ? new_al[s] : 1.0;
+      st->be[si] = (s < np) ? new_be[s] : 0.0;
+      for (int b = 0; b < L; ++b) st->zs[PAIR(st, m, n, s, b)] = zmap[s][b];
+    }
+  }
+  st->part_delta[n] = dmax;
+  st->part_ties[n] = ties;
+  st->part_margin[n] = minm;
+#undef cand_H
+#undef cand_k
+  free(cand_Hbuf);
+  free(cand_kbuf);
+  free(cand_pintra);
+  free(ici);
+  free(vw);
+}
+
+/* ------------------------------------------------------------ the sweep */
+
+ORC_API double orc_state_sweep(orc_state* st, int32_t v, int32_t refit) {
+  const int M = st->M, N = st->N, K = st->K, L = st->L;
+  const double delta_v = st->prm.step0 / sqrt(1.0 + (double)v);
+  st->assoc_changed = 0;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int n = 0; n < N; ++n) sweep_subcarrier(st, n, delta_v, refit);
+
+  /* Sums over subcarriers, serially in increasing n. */
+  double delta = 0.0;
+  int64_t ties = 0;
+  for (int n = 0; n < N; ++n) {
+    delta = fmax(delta, st->part_delta[n]);
+    ties += st->part_ties[n];
+    if (st->part_margin[n] < st->min_margin) st->min_margin = st->part_margin[n];
+  }
+  /* C12 subgradient: xi'_m <- [xi'_m + delta (sum p - pmax)/pmax * N l/(ln2 pmax)]^+ */
+  for (int m = 0; m < M; ++m) {
+    double ps = 0.0;
+    for (int n = 0; n < N; ++n) ps += st->part_psum[(size_t)n * M + m];
+    const double scale = (double)N * L / (LN2 * st->pmax[m]);
+    st->xi[m] = fmax(st->xi[m] + delta_v * scale * (ps - st->pmax[m]) / st->pmax[m], 0.0);
+  }
+  /* C13 subgradient on the SCALE surrogate rate of each streaming user; the
+   * relative violation (Psi - r_hat)/Psi is clipped to [-1, 1]. */
+  for (int k = 0; k < K; ++k) {
+    if (st->elastic[k]) continue;
+    double rh = 0.0;
+    for (int n = 0; n < N; ++n) rh += st->part_rh[(size_t)n * K + k];
+    const double viol = fmin(fmax((st->psi[k] - rh) / st->psi[k], -1.0), 1.0);
+    st->zeta[k] = fmax(st->zeta[k] + delta_v * viol, 0.0);
+  }
+  /* RRH association from the summed per-triple Lagrangian maxima. */
+  for (int k = 0; k < K; ++k) {
+    double best = -INFINITY, second = -INFINITY;
+    int bm = 0;
+    for (int m = 0; m < M; ++m) {
+      double s = 0.0;
+      for (int n = 0; n < N; ++n) s += st->H[IDX3(st, m, n, k)];
+      if (s > best) {
+        second = best;
+        best = s;
+        bm = m;
+      } else if (s > second) {
+        second = s;
+      }
+    }
+    const int before = st->A[k];
+    if (st->prm.churn_limit > 0 && st->churn_A[k] >= st->prm.churn_limit) continue;
+    if (best > 0.0) {
+      if (M > 1 && second > 0.0) note_margin((best - second) / best, st->prm.tie_rel, &ties, &st->min_margin);
+      st->A[k] = bm;
+    } else if (st->elastic[k]) {
+      st->A[k] = -1;
+    }
+    if (st->A[k] != before) {
+      st->assoc_changed++;
+      st->churn_A[k]++;
+    }
+  }
+  if (ties > 0) {
+    if (st->first_tie < 0) st->first_tie = st->sweeps_done;
+    st->ties += ties;
+  }
+  st->sweeps_done++;
+  /* a sweep that moved any user to another RRH has not converged */
+  return st->assoc_changed ? INFINITY : delta;
+}
+
+ORC_API void orc_state_eval(orc_state* st, double* R, double* P, double* R_hat,
+                            double* user_rate) {
+  const int M = st->M, N = st->N, K = st->K;
+  double* rk = (double*)calloc((size_t)N * K, sizeof(double));
+  double* rhk = (double*)calloc((size_t)N * K, sizeof(double));
+  double* pe = (double*)calloc((size_t)N * M, sizeof(double));
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int n = 0; n < N; ++n) {
+    int64_t t = 0;
+    double mm = INFINITY;
+    double* ici = (double*)malloc(sizeof(double) * (size_t)M * K);
+    mview* vw = (mview*)malloc(sizeof(mview) * M);
+    eval_subcarrier(st, n, 0, ici, vw, &t, &mm);
+    for (int m = 0; m < M; ++m)
+      for (int q = 0; q < vw[m].cnt; ++q) {
+        const int k = vw[m].user[q];
+        rk[(size_t)n * K + k] += st->w[(size_t)m * K + k] * vw[m].r[q];
+        rhk[(size_t)n * K + k] += st->w[(size_t)m * K + k] * vw[m].rh[q];
+        if (st->elastic[k]) pe[(size_t)n * M + m] += st->p[SLOT(st, m, n, vw[m].slot[q])];
+      }
+    free(ici);
+    free(vw);
+  }
+  double Rs = 0.0, Rh = 0.0, Ps = st->pstatic;
+  for (int k = 0; k < K; ++k) {
+    double r = 0.0, h = 0.0;
+    for (int n = 0; n < N; ++n) {
+      r += rk[(size_t)n * K + k];
+      h += rhk[(size_t)n * K + k];
+    }
+    if (user_rate) user_rate[k] = r;
+    if (st->elastic[k]) {
+      Rs += r;
+      Rh += h;
+    }
+  }
+  for (int m = 0; m < M; ++m) {
+    double s = 0.0;
+    for (int n = 0; n < N; ++n) s += pe[(size_t)n * M + m];
+    Ps += st->eta[m] * s;
+  }
+  *R = Rs;
+  *P = Ps;
+  if (R_hat) *R_hat = Rh;
+  free(rk);
+  free(rhk);
+  free(pe);
+}
+
+/* Final state in the output layout: slots in decoding order. */
+ORC_API void orc_state_export(orc_state* st, orc_result* res) {
+  const int M = st->M, N = st->N, K = st->K, L = st->L;
+  const int NP = L * (L - 1) / 2;
+  double* ici = (double*)malloc(sizeof(double) * (size_t)M * K);
+  mview* vw = (mview*)malloc(sizeof(mview) * M);
+  for (int n = 0; n < N; ++n) {
+    int64_t t = 0;
+    double mm = INFINITY;
+    eval_subcarrier(st, n, 0, ici, vw, &t, &mm);
+    for (int m = 0; m < M; ++m) {
+      const mview* v = &vw[m];
+      for (int q = 0; q < L; ++q) {
+        const size_t o = SLOT(st, m, n, q);
+        if (res->sel) res->sel[o] = (q < v->cnt) ? v->user[q] : -1;
+        if (res->slot_power) res->slot_power[o] = (q < v->cnt) ? st->p[SLOT(st, m, n, v->slot[q])] : 0.0;
+      }
+      if (res->zeta_sic && NP > 0) {
+        int pi = 0;
+        for (int a = 0; a < L; ++a)
+          for (int b = a + 1; b < L; ++b, ++pi) {
+            double z = 0.0;
+            if (b < v->cnt) z = st->zs[PAIR(st, m, n, v->slot[a], v->slot[b])];
+            res->zeta_sic[((size_t)m * N + n) * NP + pi] = z;
+          }
+      }
+    }
+  }
+  free(ici);
+  free(vw);
+  if (res->rrh_of_user)
+    for (int k = 0; k < K; ++k) res->rrh_of_user[k] = st->A[k];
+  if (res->xi)
+    for (int m = 0; m < M; ++m) res->xi[m] = st->xi[m];
+  if (res->zeta)
+    for (int k = 0; k < K; ++k) res->zeta[k] = st->zeta[k];
+}
+
+ORC_API void orc_state_get_slots(orc_state* st, int32_t* sel, double* power, double* xi,
+                                 double* zeta, double* zs) {
+  const size_t ns = (size_t)st->M * st->N * st->L;
+  for (size_t i = 0; i < ns; ++i) {
+    if (sel) sel[i] = st->sel[i];
+    if (power) power[i] = st->p[i];
+  }
+  if (zs)
+    for (size_t i = 0; i < ns * st->L; ++i) zs[i] = st->zs[i];
+  if (xi)
+    for (int m = 0; m < st->M; ++m) xi[m] = st->xi[m];
+  if (zeta)
+    for (int k = 0; k < st->K; ++k) zeta[k] = st->zeta[k];
+}
+
+ORC_API void orc_state_set_multipliers(orc_state* st, const double* xi, const double* zeta,
+                                       const double* zs) {
+  if (xi)
+    for (int m = 0; m < st->M; ++m) st->xi[m] = xi[m];
+  if (zeta)
+    for (int k = 0; k < st->K; ++k) st->zeta[k] = zeta[k];
+  if (zs) memcpy(st->zs, zs, sizeof(double) * (size_t)st->M * st->N * st->L * st->L);
+}
+
+ORC_API void orc_state_get_H(orc_state* st, double* H) {
+  memcpy(H, st->H, sizeof(double) * (size_t)st->M * st->N * st->K);
+}
+
+ORC_API void orc_state_set_powers(orc_state* st, const double* power) {
+  const size_t ns = (size_t)st->M * st->N * st->L;
+  for (size_t i = 0; i < ns; ++i)
+    if (st->sel[i] >= 0) st->p[i] = power[i];
+}
+
+/* ---------------------------------------------------------- full solve */
+
+/* Dinkelbach outer loop (Sec. IV) around the dual sweeps of Alg. 1. */
+ORC_API int orc_solve(const orc_problem* pb, const orc_params* prm, const orc_warm* warm,
+                      orc_result* res) {
+  const int rc = validate(pb);
+  if (rc != 0) return rc;
+  orc_state* st = orc_state_create(pb, prm, warm);
+  if (!st) return -12;
+  const int K = st->K;
+  uint32_t flags = 0;
+  double R = 0.0, P = st->pstatic;
+  int i = 0, total = 0;
+  double* rate = (double*)malloc(sizeof(double) * K);
+  st->E = 0.0; /* E^0 = 0 */
+  for (;;) {
+    orc_state_reset_scale(st);
+    orc_state_reset_churn(st);
+    int v = 0;
+    for (;;) {
+      const int refit = prm->refit_period > 0 && (v % prm->refit_period) == 0;
+      const double d = orc_state_sweep(st, v, refit);
+      ++v;
+      ++total;
+      if (isnan(d)) {
+        flags |= ORC_NONFINITE;
+        break;
+      }
+      if (v >= prm->sweeps_per_dinkelbach) break;
+      if (!prm->fixed_count) {
+        if (fabs(d - prm->tol_dual) <= 1e-6 * prm->tol_dual) st->ties++;
+        if (d < prm->tol_dual) break;
+      }
+    }
+    orc_state_eval(st, &R, &P, NULL, rate);
+    const double F = R - st->E * P;
+    if (res->trace_E) res->trace_E[i] = st->E;
+    if (res->trace_F) res->trace_F[i] = F;
+    if (res->trace_R) res->trace_R[i] = R;
+    if (res->trace_P) res->trace_P[i] = P;
+    if (res->trace_sweeps) res->trace_sweeps[i] = v;
+    ++i;
+    if (flags & ORC_NONFINITE) break;
+    if (fabs(F - prm->tol_dinkelbach * R) <= 1e-6 * prm->tol_dinkelbach * fabs(R)) st->ties++;
+    if (F <= prm->tol_dinkelbach * R) break;
+    if (i >= prm->max_dinkelbach) {
+      flags |= ORC_NOT_CONVERGED;
+      break;
+    }
+    st->E = R / P; /* E^{i+1} = R(p^i)/P(p^i) */
+  }
+  orc_state_export(st, res);
+  for (int k = 0; k < K; ++k) {
+    if (res->user_rate) res->user_rate[k] = rate[k];
+    if (!st->elastic[k] && rate[k] < st->psi[k] * (1.0 - 1e-6)) flags |= ORC_QOS_INFEASIBLE;
+    if (!isfinite(rate[k])) flags |= ORC_NONFINITE;
+  }
+  if (st->ties > 0) flags |= ORC_NEAR_TIE;
+  res->ee = (P > 0.0) ? R / P : 0.0;
+  res->rate_sum = R;
+  res->power_sum = P;
+  res->dinkelbach_iters = i;
+  res->sweeps = total;
+  res->status_flags = flags;
+  res->near_ties = st->ties;
+  res->min_margin = st->min_margin;
+  res->first_tie_sweep = st->first_tie;
+  free(rate);
+  orc_state_destroy(st);
+  return 0;
+}
