@@ -1,0 +1,150 @@
+/*
+ * alloc.h -- C ABI of the MI355X energy-efficiency resource allocator for
+ * PD-NOMA heterogeneous cloud RANs.
+ *
+ * The operation is the suboptimal solver of "Cross-Layer Energy Efficient
+ * Resource Allocation in PD-NOMA based H-CRANs: Implementation via GPU":
+ * maximise E = R/P (Sec. II-A; R the weighted sum rate of elastic users, P the
+ * fibre, circuit and amplifier power) subject to at most l users per RRH and
+ * subcarrier (C1/C2), the RRH power budget (C3/C12), the spectral mask (C4),
+ * one RRH per user (C5/C6), the streaming users' minimum rate derived from
+ * their M/G/1 delay target (C7 -> C9/C13, Sec. II-B) and SIC decodability
+ * (C8/C14).  It runs the Dinkelbach iteration (Sec. III-IV) around Jacobi
+ * sweeps of the SCALE-approximated Lagrangian dual (Sec. IV-A, Alg. 1):
+ * SIC-ordered SINRs, SCALE refit, closed-form elastic/streaming powers,
+ * selection of users and RRHs from the per-triple Lagrangian maximum, and
+ * subgradient steps on the multipliers xi' (C12), zeta' (C13), zeta~' (C14).
+ *
+ * Conventions
+ *  - Index sets: m in [0,M) RRHs (0 = HPN), n in [0,N) subcarriers,
+ *    k in [0,K) users.  Three-index arrays are [M][N][K], k fastest.
+ *  - All pointers are owned by the caller; the library never frees them.
+ *    A context owns its device workspace and releases it in
+ *    alloc_ctx_destroy.
+ *  - Arithmetic is IEEE double precision on the device; gains are read as
+ *    the given float32 values.
+ *  - Return codes: 0 success; negative = error, outputs untouched:
+ *      ALLOC_EINVAL  bad sizes, l < 1 or l > K, non-positive or non-finite
+ *                    gain, budget or noise, streaming user with arrival
+ *                    rate or delay target <= 0, NULL required pointer;
+ *      ALLOC_ETOOBIG the problem exceeds a kernel limit (see below);
+ *      ALLOC_ENOMEM  device allocation failed;
+ *      ALLOC_EDEVICE a HIP runtime call failed.
+ *    Non-fatal conditions are reported in alloc_result.status_flags.
+ *  - Limits: M <= 32, l <= 4, K <= 1024, M*K <= 4608 (one subcarrier's gain
+ *    slab and its state must fit one workgroup's LDS).
+ *  - Threading: one context per stream; calls on one context must not
+ *    overlap.
+ */
+#ifndef ALLOC_H
+#define ALLOC_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ALLOC_API __attribute__((visibility("default")))
+
+#define ALLOC_OK 0
+#define ALLOC_EINVAL (-22)
+#define ALLOC_ENOMEM (-12)
+#define ALLOC_EDEVICE (-5)
+#define ALLOC_ETOOBIG (-27)
+
+/* alloc_params.flags */
+#define ALLOC_GAIN_ON_DEVICE 1u /* problem.gain is a device pointer */
+#define ALLOC_OUT_ON_DEVICE 2u  /* array outputs of alloc_result are device pointers */
+
+/* alloc_result.status_flags */
+#define ALLOC_NOT_CONVERGED 1u  /* Dinkelbach stopped at max_dinkelbach */
+#define ALLOC_QOS_INFEASIBLE 2u /* a streaming user ends below (1-1e-6) of its minimum rate */
+#define ALLOC_NONFINITE 8u      /* a non-finite rate or power appeared */
+
+typedef struct alloc_ctx alloc_ctx;
+
+/* Create a context on HIP device `device` that enqueues on `hip_stream`
+ * (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream; NULL = the
+ * null stream).  Returns 0 and sets *out, or a negative code. */
+ALLOC_API int alloc_ctx_create(int device, void* hip_stream, alloc_ctx** out);
+ALLOC_API void alloc_ctx_destroy(alloc_ctx* ctx);
+
+/* One drop (Table I symbols). */
+typedef struct {
+  int32_t M, N, K, l;
+  const float* gain;          /* [M][N][K] Gamma = |h|^2 (host or device, see flags) */
+  const uint8_t* user_type;   /* [K] host: 0 elastic, 1 streaming */
+  const double* arrival_bps;  /* [K] host: lambda_k * zbar (bits/s), streaming users */
+  const double* delay_s;      /* [K] host: delay target T_k (s), streaming users */
+  const double* pmax_w;       /* [M] host: RRH budget p_m^max (W) */
+  const double* eta;          /* [M] host: amplifier factor eta_m */
+  const double* pmask_w;      /* [M] host: spectral mask per RRH, NULL -> pmax/N */
+  const double* weight;       /* [M][K] host: priority weight w_{m,k}, NULL -> 1 */
+  double noise_w;             /* noise power per subcarrier sigma (W) */
+  double bw_hz;               /* subcarrier bandwidth B_n (Hz) */
+  double packet_bits;         /* packet size zbar (bits) */
+  double p_fiber_hpn, p_fiber_lpn, p_circuit_hpn, p_circuit_lpn; /* static power (W) */
+} alloc_problem;
+
+/* Solver schedule.  alloc_params_default fills the defaults shown. */
+typedef struct {
+  int32_t max_dinkelbach;        /* 20: cap on Dinkelbach steps */
+  int32_t sweeps_per_dinkelbach; /* 200: dual sweeps per step (cap, or exact count) */
+  int32_t refit_period;          /* 1: SCALE refit every this many sweeps (<=0 never) */
+  int32_t fixed_count;           /* 1: run exactly sweeps_per_dinkelbach sweeps */
+  int32_t churn_limit;           /* 8: selection/association changes per (m,n)/user
+                                    and Dinkelbach step before freezing (<=0 no cap) */
+  double tol_dinkelbach;         /* 1e-6: stop when R - E P <= tol * R */
+  double tol_dual;               /* 1e-7: dual loop stops when max|dp|/pmask < tol
+                                    and no association changed (fixed_count = 0) */
+  double step0;                  /* 0.1: subgradient step step0/sqrt(1+v) */
+  uint32_t flags;                /* ALLOC_GAIN_ON_DEVICE | ALLOC_OUT_ON_DEVICE */
+  int32_t max_groups;            /* 0: cap on the workgroups of the solve grid
+                                    (0 = as many as can be co-resident, <= N) */
+} alloc_params;
+
+ALLOC_API void alloc_params_default(alloc_params* p);
+
+/* Optional warm start: any pointer may be NULL (host, double). */
+typedef struct {
+  const double* p0;    /* [M][N][K] initial powers */
+  const double* xi0;   /* [M] */
+  const double* zeta0; /* [K] */
+} alloc_warm;
+
+/* Outputs: arrays are caller-allocated (host, or device with
+ * ALLOC_OUT_ON_DEVICE); any array pointer may be NULL to skip it.  Scalars
+ * are always written to this host struct. */
+typedef struct {
+  int32_t* sel;        /* [M][N][l] users of (m,n) in SIC decoding order, -1 = empty */
+  double* slot_power;  /* [M][N][l] power of those users (W) */
+  float* power;        /* [M][N][K] dense powers (W) */
+  int32_t* rrh_of_user; /* [K] serving RRH, -1 = unserved */
+  double* xi;          /* [M] */
+  double* zeta;        /* [K] (0 for elastic users) */
+  double* zeta_sic;    /* [M][N][l(l-1)/2] C14 multiplier of decoding positions (a<b) */
+  double* user_rate;   /* [K] r_k (bits/s/Hz, summed over subcarriers) */
+  double ee;           /* R/P at the returned allocation (bits/s/Hz/W) */
+  double rate_sum, power_sum;
+  int32_t dinkelbach_iters, sweeps;
+  uint32_t status_flags;
+} alloc_result;
+
+/* Solve one drop on the context's stream; returns when the results are
+ * written (the call synchronises the stream). */
+ALLOC_API int alloc_solve(alloc_ctx* ctx, const alloc_problem* prob, const alloc_params* prm,
+                const alloc_warm* warm, alloc_result* res);
+
+ALLOC_API const char* alloc_strerror(int code);
+
+/* Kernel timing for measurement: when enabled, alloc_solve records HIP events
+ * on the context's stream around the persistent solve kernel, and
+ * alloc_ctx_last_kernel_ms returns that kernel's duration in milliseconds for
+ * the last call (-1 if timing is off or no solve ran). */
+ALLOC_API int alloc_ctx_set_timing(alloc_ctx* ctx, int enable);
+ALLOC_API double alloc_ctx_last_kernel_ms(alloc_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,234 @@
+"""MI355X energy-efficiency resource allocator for PD-NOMA H-CRANs.
+
+Thin ctypes binding over the C ABI in ``include/alloc.h`` (``_liballoc.so``,
+built from ``csrc/alloc.hip`` for gfx950).  Every step of the solve runs in
+the HIP kernels; this module only marshals arguments.  There is no CPU
+fallback: if the library is missing, importing the solver raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_liballoc.so")
+
+ALLOC_GAIN_ON_DEVICE = 1
+ALLOC_OUT_ON_DEVICE = 2
+NOT_CONVERGED = 1
+QOS_INFEASIBLE = 2
+NONFINITE = 8
+
+_lib = None
+
+
+class AllocError(RuntimeError):
+    pass
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [("M", ctypes.c_int32), ("N", ctypes.c_int32), ("K", ctypes.c_int32),
+                ("l", ctypes.c_int32), ("gain", ctypes.c_void_p), ("user_type", ctypes.c_void_p),
+                ("arrival_bps", ctypes.c_void_p), ("delay_s", ctypes.c_void_p),
+                ("pmax_w", ctypes.c_void_p), ("eta", ctypes.c_void_p),
+                ("pmask_w", ctypes.c_void_p), ("weight", ctypes.c_void_p),
+                ("noise_w", ctypes.c_double), ("bw_hz", ctypes.c_double),
+                ("packet_bits", ctypes.c_double), ("p_fiber_hpn", ctypes.c_double),
+                ("p_fiber_lpn", ctypes.c_double), ("p_circuit_hpn", ctypes.c_double),
+                ("p_circuit_lpn", ctypes.c_double)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("max_dinkelbach", ctypes.c_int32), ("sweeps_per_dinkelbach", ctypes.c_int32),
+                ("refit_period", ctypes.c_int32), ("fixed_count", ctypes.c_int32),
+                ("churn_limit", ctypes.c_int32), ("tol_dinkelbach", ctypes.c_double),
+                ("tol_dual", ctypes.c_double), ("step0", ctypes.c_double),
+                ("flags", ctypes.c_uint32), ("max_groups", ctypes.c_int32)]
+
+
+class _Warm(ctypes.Structure):
+    _fields_ = [("p0", ctypes.c_void_p), ("xi0", ctypes.c_void_p), ("zeta0", ctypes.c_void_p)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("sel", ctypes.c_void_p), ("slot_power", ctypes.c_void_p),
+                ("power", ctypes.c_void_p), ("rrh_of_user", ctypes.c_void_p),
+                ("xi", ctypes.c_void_p), ("zeta", ctypes.c_void_p),
+                ("zeta_sic", ctypes.c_void_p), ("user_rate", ctypes.c_void_p),
+                ("ee", ctypes.c_double), ("rate_sum", ctypes.c_double),
+                ("power_sum", ctypes.c_double), ("dinkelbach_iters", ctypes.c_int32),
+                ("sweeps", ctypes.c_int32), ("status_flags", ctypes.c_uint32)]
+
+
+EXPORTS = ("alloc_ctx_create", "alloc_ctx_destroy", "alloc_params_default", "alloc_solve",
+           "alloc_strerror", "alloc_ctx_set_timing", "alloc_ctx_last_kernel_ms")
+
+
+def load():
+    """Load _liballoc.so (raises if it is not built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise AllocError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        lib = ctypes.CDLL(LIB_PATH)
+        lib.alloc_ctx_create.argtypes = [ctypes.c_int, ctypes.c_void_p,
+                                         ctypes.POINTER(ctypes.c_void_p)]
+        lib.alloc_ctx_create.restype = ctypes.c_int
+        lib.alloc_ctx_destroy.argtypes = [ctypes.c_void_p]
+        lib.alloc_ctx_destroy.restype = None
+        lib.alloc_params_default.argtypes = [ctypes.POINTER(_Params)]
+        lib.alloc_params_default.restype = None
+        lib.alloc_solve.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Problem),
+                                    ctypes.POINTER(_Params), ctypes.POINTER(_Warm),
+                                    ctypes.POINTER(_Result)]
+        lib.alloc_solve.restype = ctypes.c_int
+        lib.alloc_strerror.argtypes = [ctypes.c_int]
+        lib.alloc_strerror.restype = ctypes.c_char_p
+        lib.alloc_ctx_set_timing.argtypes = [ctypes.c_void_p, ctypes.c_int]
+        lib.alloc_ctx_set_timing.restype = ctypes.c_int
+        lib.alloc_ctx_last_kernel_ms.argtypes = [ctypes.c_void_p]
+        lib.alloc_ctx_last_kernel_ms.restype = ctypes.c_double
+        _lib = lib
+    return _lib
+
+
+def _check(rc: int):
+    if rc != 0:
+        raise AllocError(f"alloc error {rc}: {load().alloc_strerror(rc).decode()}")
+
+
+@dataclasses.dataclass
+class Params:
+    max_dinkelbach: int = 20
+    sweeps_per_dinkelbach: int = 200
+    refit_period: int = 1
+    fixed_count: int = 1
+    churn_limit: int = 8
+    tol_dinkelbach: float = 1e-6
+    tol_dual: float = 1e-7
+    step0: float = 0.1
+    max_groups: int = 0
+
+    def _c(self, flags: int) -> _Params:
+        return _Params(self.max_dinkelbach, self.sweeps_per_dinkelbach, self.refit_period,
+                       self.fixed_count, self.churn_limit, self.tol_dinkelbach, self.tol_dual,
+                       self.step0, flags, self.max_groups)
+
+
+def default_params() -> Params:
+    p = _Params()
+    load().alloc_params_default(ctypes.byref(p))
+    return Params(p.max_dinkelbach, p.sweeps_per_dinkelbach, p.refit_period, p.fixed_count,
+                  p.churn_limit, p.tol_dinkelbach, p.tol_dual, p.step0, p.max_groups)
+
+
+@dataclasses.dataclass
+class Result:
+    sel: np.ndarray
+    slot_power: np.ndarray
+    rrh_of_user: np.ndarray
+    xi: np.ndarray
+    zeta: np.ndarray
+    zeta_sic: np.ndarray
+    user_rate: np.ndarray
+    ee: float
+    rate_sum: float
+    power_sum: float
+    dinkelbach_iters: int
+    sweeps: int
+    status_flags: int
+    power: np.ndarray | None = None
+
+
+def _hp(keep, a, dtype):
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=dtype)
+    keep.append(a)
+    return a.ctypes.data
+
+
+class Context:
+    """A device context bound to one HIP stream (default: torch's current stream)."""
+
+    def __init__(self, device: int = 0, stream: int | None = None):
+        lib = load()
+        if stream is None:
+            import torch
+            stream = torch.cuda.current_stream(device).cuda_stream
+        h = ctypes.c_void_p()
+        _check(lib.alloc_ctx_create(device, ctypes.c_void_p(stream), ctypes.byref(h)))
+        self._h = h
+        self.device = device
+
+    def set_timing(self, enable: bool = True):
+        """Record HIP events around the solve kernel of each call."""
+        _check(load().alloc_ctx_set_timing(self._h, int(enable)))
+
+    def last_kernel_ms(self) -> float:
+        return load().alloc_ctx_last_kernel_ms(self._h)
+
+    def close(self):
+        if self._h:
+            load().alloc_ctx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, drop, params: Params | None = None, gain=None, warm=None, pmask=None,
+              weight=None, dense_power: bool = False) -> Result:
+        """Solve one drop.
+
+        ``gain`` may be a torch tensor on the GPU ([M][N][K] float32, contiguous);
+        otherwise ``drop.gain`` (host) is copied by the library.
+        ``warm`` is a dict with optional host arrays p0 [M][N][K], xi0 [M], zeta0 [K].
+        """
+        params = params or Params()
+        keep = []
+        flags = 0
+        if gain is not None and hasattr(gain, "data_ptr"):
+            if not gain.is_cuda or not gain.is_contiguous() or gain.dtype.itemsize != 4:
+                raise ValueError("gain tensor must be contiguous float32 on the GPU")
+            if tuple(gain.shape) != (drop.M, drop.N, drop.K):
+                raise ValueError(f"gain shape {tuple(gain.shape)} != {(drop.M, drop.N, drop.K)}")
+            gptr = gain.data_ptr()
+            flags |= ALLOC_GAIN_ON_DEVICE
+        else:
+            g = drop.gain if gain is None else gain
+            if np.shape(g) != (drop.M, drop.N, drop.K):
+                raise ValueError("gain shape mismatch")
+            gptr = _hp(keep, g, np.float32)
+        pb = _Problem(drop.M, drop.N, drop.K, drop.l, gptr, _hp(keep, drop.user_type, np.uint8),
+                      _hp(keep, drop.arrival_bps, np.float64), _hp(keep, drop.delay_s, np.float64),
+                      _hp(keep, drop.pmax_w, np.float64), _hp(keep, drop.eta, np.float64),
+                      _hp(keep, pmask, np.float64), _hp(keep, weight, np.float64),
+                      drop.noise_w, drop.bw_hz, drop.packet_bits, drop.p_fiber_hpn,
+                      drop.p_fiber_lpn, drop.p_circuit_hpn, drop.p_circuit_lpn)
+        M, N, K, L = drop.M, drop.N, drop.K, drop.l
+        NP = L * (L - 1) // 2
+        out = dict(sel=np.empty((M, N, L), np.int32), slot_power=np.empty((M, N, L)),
+                   rrh_of_user=np.empty(K, np.int32), xi=np.empty(M), zeta=np.empty(K),
+                   zeta_sic=np.empty((M, N, NP)), user_rate=np.empty(K))
+        dense = np.empty((M, N, K), np.float32) if dense_power else None
+        res = _Result(out["sel"].ctypes.data, out["slot_power"].ctypes.data,
+                      dense.ctypes.data if dense is not None else None,
+                      out["rrh_of_user"].ctypes.data, out["xi"].ctypes.data,
+                      out["zeta"].ctypes.data, out["zeta_sic"].ctypes.data if NP else None,
+                      out["user_rate"].ctypes.data, 0.0, 0.0, 0.0, 0, 0, 0)
+        wm = None
+        if warm is not None:
+            wm = _Warm(_hp(keep, warm.get("p0"), np.float64), _hp(keep, warm.get("xi0"), np.float64),
+                       _hp(keep, warm.get("zeta0"), np.float64))
+        pc = params._c(flags)
+        _check(load().alloc_solve(self._h, ctypes.byref(pb), ctypes.byref(pc),
+                                  ctypes.byref(wm) if wm is not None else None, ctypes.byref(res)))
+        return Result(ee=res.ee, rate_sum=res.rate_sum, power_sum=res.power_sum,
+                      dinkelbach_iters=res.dinkelbach_iters, sweeps=res.sweeps,
+                      status_flags=res.status_flags, power=dense, **out)
