@@ -28,6 +28,7 @@
  *    sweep;
  *  - subgradient step step0/sqrt(1+v); xi' scaled by N*l/(ln2*pmax_m);
  *    the relative C13 violation clipped to [-1, 1];
+ *  - closed-form powers below 1e-20 of the mask are set to zero;
  *  - churn cap: within one Dinkelbach step the selected set of an (m,n) and
  *    the RRH of a user may change at most churn_limit times, after which
  *    they are frozen (simultaneous discrete updates can cycle); all
@@ -44,6 +45,10 @@
 #define ORC_API __attribute__((visibility("default")))
 #define LN2 0.69314718055994530942
 #define MAXL 8
+/* Powers below this fraction of the mask are set to exactly zero: decaying
+ * closed-form powers would otherwise reach the subnormal range, where the
+ * SINR underflows and the SCALE refit produces 0 * log2(0). */
+#define POWER_FLOOR_REL 1e-20
 
 /* ------------------------------------------------------------------ basics */
 
@@ -613,7 +618,10 @@ static void sweep_subcarrier(orc_state* st, int n, double delta_v, int refit) {
       const double cp = (st->elastic[k] ? st->E * st->eta[m] : 0.0) + st->xi[m] +
                         cand_pintra[k] + pinter[m] + pplus;
       const double num = wmu * alph / LN2 + p_old * pminus;
-      const double pn = (cp > 0.0) ? fmin(fmax(num / cp, 0.0), st->pmask[m]) : st->pmask[m];
+      double pn = (cp > 0.0) ? fmin(fmax(num / cp, 0.0), st->pmask[m]) : st->pmask[m];
+      const double floor_p = POWER_FLOOR_REL * st->pmask[m];
+      if (pn > 0.0) note_margin(fabs(pn - floor_p) / floor_p, tr, &ties, &minm);
+      if (pn < floor_p) pn = 0.0;
       new_user[s] = k;
       new_p[s] = pn;
       new_al[s] = alph;

@@ -37,6 +37,9 @@ constexpr int kMaxM = 32;
 constexpr int kMaxK = 1024;
 constexpr int kMaxMK = 4608;
 constexpr int kBlock = 512;
+// Closed-form powers below this fraction of the mask become exactly zero, so
+// decaying powers never reach the subnormal range.
+constexpr double kPowerFloorRel = 1e-20;
 
 enum Mode : int { kSweep = 0, kEval = 1, kDone = 2 };
 
@@ -49,6 +52,7 @@ struct Ctrl {
   int mode;
   int total;      // sweeps done in total
   int reset;      // next sweep starts a Dinkelbach step
+  int pass;       // passes (sweeps and evaluations) done
   uint32_t flags;
 };
 
@@ -86,7 +90,7 @@ struct Drop {
   double* pel_part;        // [G][M] power, elastic users
   double* R_part;          // [G] weighted elastic rate
   double* d_part;          // [G] max |dp|/pmask
-  int* chg_part;           // [G] association changes
+  int* chg_count;          // [2] association changes, indexed by pass parity
   double* red;             // [4] R, P, delta (written by workgroup 0)
   double* user_rate;       // [K]
   // decoding-order copies of the last evaluated state
@@ -109,6 +113,9 @@ struct Lds {
   int* Al;        // [K]
   int* grp;       // [K] users grouped by RRH
   int* grp_off;   // [M+1]
+  int* grpk;      // [K] rank of a user within its RRH group
+  int* wcnt;      // [kBlock/64][M] per-wave group counts
+  int* gcur;      // [M]
   // slots of the current subcarrier, storage order
   int* su;        // [M][L]
   double* sp;     // [M][L]
@@ -136,6 +143,7 @@ struct Lds {
   double* dmax;   // [M]
   int* churn;     // [M]
   double* red;    // [kBlock] scratch for reductions
+  double* tmp;    // [M+2] reduction results
 };
 
 __host__ __device__ inline size_t align8(size_t x) { return (x + 7) & ~size_t(7); }
@@ -153,6 +161,8 @@ __host__ __device__ inline size_t lds_bytes(int M, int K, int L) {
   b += 9 * sizeof(double) * M + sizeof(double) * M * M;
   b += align8(sizeof(int) * M);
   b += sizeof(double) * kBlock;
+  b += align8(sizeof(int) * K) + align8(sizeof(int) * (kBlock / 64) * M) + align8(sizeof(int) * M);
+  b += sizeof(double) * (M + 2);
   return b + 64;
 }
 
@@ -175,6 +185,9 @@ __device__ Lds carve(char* base, int M, int K, int L) {
   s.Al = (int*)take(sizeof(int) * K);
   s.grp = (int*)take(sizeof(int) * K);
   s.grp_off = (int*)take(sizeof(int) * (M + 1));
+  s.grpk = (int*)take(sizeof(int) * K);
+  s.wcnt = (int*)take(sizeof(int) * (kBlock / 64) * M);
+  s.gcur = (int*)take(sizeof(int) * M);
   s.su = (int*)take(sizeof(int) * M * L);
   s.sp = (double*)take(sizeof(double) * M * L);
   s.sal = (double*)take(sizeof(double) * M * L);
@@ -200,6 +213,7 @@ __device__ Lds carve(char* base, int M, int K, int L) {
   s.dmax = (double*)take(sizeof(double) * M);
   s.churn = (int*)take(sizeof(int) * M);
   s.red = (double*)take(sizeof(double) * kBlock);
+  s.tmp = (double*)take(sizeof(double) * (M + 2));
   return s;
 }
 
@@ -244,15 +258,44 @@ __device__ void begin_pass(const Drop& d, Lds& s) {
     s.dmax[m] = 0.0;
   }
   __syncthreads();
-  if (tid == 0) {  // counting sort of users by RRH, ascending user index
-    for (int m = 0; m <= M; ++m) s.grp_off[m] = 0;
-    for (int k = 0; k < K; ++k)
-      if (s.Al[k] >= 0) s.grp_off[s.Al[k] + 1]++;
-    for (int m = 0; m < M; ++m) s.grp_off[m + 1] += s.grp_off[m];
-    for (int m = 0; m < M; ++m) s.churn[m] = s.grp_off[m];  // fill cursor
-    for (int k = 0; k < K; ++k)
-      if (s.Al[k] >= 0) s.grp[s.churn[s.Al[k]]++] = k;
+  // Users grouped by RRH in ascending user order: each wave ranks its lanes
+  // with ballots, per-wave counts are scanned in wave order.
+  const int lane = tid & 63, wave = tid >> 6, nwaves = nth >> 6;
+  for (int base = 0; base < K; base += nth) {
+    const int k = base + tid;
+    const int a = (k < K) ? s.Al[k] : -1;
+    int rank = 0;
+    for (int m = 0; m < M; ++m) {
+      const unsigned long long bal = __ballot(a == m);
+      if (a == m) rank = __popcll(bal & ((1ull << lane) - 1ull));
+      if (lane == 0) s.wcnt[wave * M + m] = __popcll(bal);
+    }
+    __syncthreads();
+    if (tid < M) {  // running start of group m for each wave of this chunk
+      const int m = tid;
+      int run = (base == 0) ? 0 : s.gcur[m];
+      for (int w = 0; w < nwaves; ++w) {
+        const int c = s.wcnt[w * M + m];
+        s.wcnt[w * M + m] = run;  // exclusive prefix within group m
+        run += c;
+      }
+      s.gcur[m] = run;
+    }
+    __syncthreads();
+    if (a >= 0) s.grpk[k] = s.wcnt[wave * M + a] + rank;  // rank of k within its group
+    __syncthreads();
   }
+  if (tid == 0) {
+    int off = 0;
+    for (int m = 0; m < M; ++m) {
+      s.grp_off[m] = off;
+      off += s.gcur[m];
+    }
+    s.grp_off[M] = off;
+  }
+  __syncthreads();
+  for (int k = tid; k < K; k += nth)
+    if (s.Al[k] >= 0) s.grp[s.grp_off[s.Al[k]] + s.grpk[k]] = k;
   __syncthreads();
 }
 
@@ -525,7 +568,8 @@ __device__ void subcarrier(const Drop& d, const Sched& sc, const PassConst& pc, 
       const double wmu = (d.w ? d.w[(size_t)m * K + k] : 1.0) * s.mu[k];
       const double cp = (d.elastic[k] ? pc.E * d.eta[m] : 0.0) + s.xi[m] + s.pic[k] + s.pinter[m] + pplus;
       const double num = wmu * alph / kLn2 + p_old * pminus;
-      const double pn = (cp > 0.0) ? fmin(fmax(num / cp, 0.0), d.pmask[m]) : d.pmask[m];
+      double pn = (cp > 0.0) ? fmin(fmax(num / cp, 0.0), d.pmask[m]) : d.pmask[m];
+      if (pn < kPowerFloorRel * d.pmask[m]) pn = 0.0;
       nu_[a] = k;
       np_[a] = pn;
       na_[a] = alph;
@@ -580,109 +624,104 @@ __device__ void write_partials(const Drop& d, const Lds& s, int b) {
   }
 }
 
-// Block-wide sum of per-thread values in a fixed order.
-__device__ double block_sum(Lds& s, double v) {
-  const int tid = threadIdx.x;
-  s.red[tid] = v;
+// Sums (or maxima) over workgroups g of v(g, m) = base[g*gs + m*ms] for
+// m < M, in a fixed order: strided partial sums per (m, chunk), then a tree
+// over chunks.  Result in out[m] (LDS), visible to all threads on return.
+template <bool kMax>
+__device__ void reduce_groups(Lds& s, const double* base, int G, int M, size_t gs, size_t ms,
+                              double* out) {
+  const int tid = threadIdx.x, nth = blockDim.x;
+  const int chunks = nth / M;
+  if (tid < M * chunks) {
+    const int m = tid % M, c = tid / M;
+    double acc = 0.0;
+    for (int g = c; g < G; g += chunks) {
+      const double v = base[(size_t)g * gs + (size_t)m * ms];
+      acc = kMax ? fmax(acc, v) : acc + v;
+    }
+    s.red[tid] = acc;
+  }
   __syncthreads();
-  for (int w = blockDim.x / 2; w > 0; w >>= 1) {
-    if (tid < w) s.red[tid] += s.red[tid + w];
+  for (int st = 1; st < chunks; st <<= 1) {
+    if (tid < M * chunks) {
+      const int c = tid / M;
+      if ((c % (2 * st)) == 0 && c + st < chunks) {
+        const double o = s.red[tid + st * M];
+        s.red[tid] = kMax ? fmax(s.red[tid], o) : s.red[tid] + o;
+      }
+    }
     __syncthreads();
   }
-  const double r = s.red[0];
+  if (tid < M) out[tid] = s.red[tid];
   __syncthreads();
-  return r;
 }
 
 // Reductions across workgroups: users k = b, b+G, ... per workgroup;
 // workgroup 0 also does the per-RRH and scalar sums.
 __device__ void reduce_pass(const Drop& d, const Sched& sc, const Ctrl& c, Lds& s, int b, int G,
                             bool update, double delta_v) {
-  const int M = d.M, K = d.K, tid = threadIdx.x, nth = blockDim.x;
+  const int M = d.M, K = d.K, tid = threadIdx.x;
+  const int par = c.pass & 1;
   int changes = 0;
+  if (b == 0 && tid == 0) store_shared(&d.chg_count[par ^ 1], 0);  // next pass's counter
   for (int k = b; k < K; k += G) {
-    // true and surrogate rate of user k
-    double r = 0.0, rh = 0.0;
-    for (int t = tid; t < G; t += nth) {
-      r += d.r_part[(size_t)t * K + k];
-      rh += d.rh_part[(size_t)t * K + k];
-    }
-    r = block_sum(s, r);
-    rh = block_sum(s, rh);
-    if (!update) {
-      if (tid == 0) d.user_rate[k] = r;
-      continue;
-    }
-    // association metric: thread t sums workgroups t/M', t/M'+chunks ... for m = t % M
-    const int chunks = nth / M;
-    for (int t = tid; t < M * chunks; t += nth) {
-      const int m = t % M, ch = t / M;
-      double acc = 0.0;
-      for (int g = ch; g < G; g += chunks) acc += d.S_part[((size_t)g * M + m) * K + k];
-      s.red[t] = acc;
-    }
-    __syncthreads();
+    reduce_groups<false>(s, d.r_part + k, G, 1, K, 0, s.tmp);
+    reduce_groups<false>(s, d.rh_part + k, G, 1, K, 0, s.tmp + 1);
+    if (update) reduce_groups<false>(s, d.S_part + k, G, M, (size_t)M * K, K, s.tmp + 2);
     if (tid == 0) {
+      const double r = s.tmp[0], rh = s.tmp[1];
       d.user_rate[k] = r;
-      double best = -INFINITY;
-      int bm = 0;
-      for (int m = 0; m < M; ++m) {
-        double S = 0.0;
-        for (int ch = 0; ch < chunks; ++ch) S += s.red[ch * M + m];
-        if (S > best) {
-          best = S;
-          bm = m;
+      if (update) {
+        double best = -INFINITY;
+        int bm = 0;
+        for (int m = 0; m < M; ++m)
+          if (s.tmp[2 + m] > best) {
+            best = s.tmp[2 + m];
+            bm = m;
+          }
+        int ch_A = c.reset ? 0 : d.churn_A[k];
+        const int before = d.A[k];
+        if (!(sc.churn > 0 && ch_A >= sc.churn)) {
+          int after = before;
+          if (best > 0.0)
+            after = bm;
+          else if (d.elastic[k])
+            after = -1;
+          if (after != before) {
+            d.A[k] = after;
+            ++ch_A;
+            ++changes;
+          }
         }
-      }
-      int ch_A = c.reset ? 0 : d.churn_A[k];
-      const int before = d.A[k];
-      if (!(sc.churn > 0 && ch_A >= sc.churn)) {
-        int after = before;
-        if (best > 0.0)
-          after = bm;
-        else if (d.elastic[k])
-          after = -1;
-        if (after != before) {
-          d.A[k] = after;
-          ++ch_A;
-          ++changes;
+        d.churn_A[k] = ch_A;
+        if (!d.elastic[k]) {
+          const double viol = fmin(fmax((d.psi[k] - rh) / d.psi[k], -1.0), 1.0);
+          d.zeta[k] = fmax(d.zeta[k] + delta_v * viol, 0.0);
         }
-      }
-      d.churn_A[k] = ch_A;
-      if (!d.elastic[k]) {
-        const double viol = fmin(fmax((d.psi[k] - rh) / d.psi[k], -1.0), 1.0);
-        d.zeta[k] = fmax(d.zeta[k] + delta_v * viol, 0.0);
       }
     }
     __syncthreads();
   }
-  if (tid == 0) store_shared(&d.chg_part[b], changes);
+  if (tid == 0 && changes > 0)
+    __hip_atomic_fetch_add(&d.chg_count[par], changes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   if (b == 0) {
-    // per-RRH sums (workgroup order fixed), xi' step, R, P, max delta
-    for (int m = tid; m < M; m += nth) {
-      double ps = 0.0, pe = 0.0;
-      for (int g = 0; g < G; ++g) {
-        ps += d.psum_part[(size_t)g * M + m];
-        pe += d.pel_part[(size_t)g * M + m];
-      }
-      s.psacc[m] = ps;
-      s.peacc[m] = pe;
-      if (update) {
+    // per-RRH sums, xi' step, R, P, max delta (fixed-order trees)
+    reduce_groups<false>(s, d.psum_part, G, M, M, 1, s.psacc);
+    reduce_groups<false>(s, d.pel_part, G, M, M, 1, s.peacc);
+    reduce_groups<false>(s, d.R_part, G, 1, 1, 0, s.tmp);
+    reduce_groups<true>(s, d.d_part, G, 1, 1, 0, s.tmp + 1);
+    if (update)
+      for (int m = tid; m < M; m += blockDim.x) {
+        const double ps = s.psacc[m];
         const double scale = (double)d.N * d.L / (kLn2 * d.pmax[m]);
         d.xi[m] = fmax(d.xi[m] + delta_v * scale * (ps - d.pmax[m]) / d.pmax[m], 0.0);
       }
-    }
-    __syncthreads();
     if (tid == 0) {
-      double R = 0.0, dm = 0.0, P = d.pstatic;
-      for (int g = 0; g < G; ++g) {
-        R += d.R_part[g];
-        dm = fmax(dm, d.d_part[g]);
-      }
+      double P = d.pstatic;
       for (int m = 0; m < M; ++m) P += d.eta[m] * s.peacc[m];
-      store_shared(&d.red[0], R);
+      store_shared(&d.red[0], s.tmp[0]);
       store_shared(&d.red[1], P);
-      store_shared(&d.red[2], dm);
+      store_shared(&d.red[2], s.tmp[1]);
     }
   }
 }
@@ -692,8 +731,7 @@ __device__ void reduce_pass(const Drop& d, const Sched& sc, const Ctrl& c, Lds& 
 __device__ void control(const Drop& d, const Sched& sc, Ctrl& c, int G) {
   const double R = load_shared(&d.red[0]), P = load_shared(&d.red[1]), dm = load_shared(&d.red[2]);
   if (c.mode == kSweep) {
-    int changes = 0;
-    for (int g = 0; g < G; ++g) changes += load_shared(&d.chg_part[g]);
+    const int changes = load_shared(&d.chg_count[c.pass & 1]);
     c.v += 1;
     c.total += 1;
     c.reset = 0;
@@ -748,6 +786,7 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(Drop d, Sched sc) {
     reduce_pass(d, sc, c, s, b, G, update, pc.delta_v);
     grid.sync();
     control(d, sc, c, G);
+    c.pass += 1;
     if (b == 0 && threadIdx.x == 0) *d.ctrl = c;
   }
 }
@@ -1067,7 +1106,7 @@ int alloc_solve(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm
   const size_t oPep = lay.add(sizeof(double) * G * M);
   const size_t oRP = lay.add(sizeof(double) * G);
   const size_t oDp = lay.add(sizeof(double) * G);
-  const size_t oChg = lay.add(sizeof(int) * G);
+  const size_t oChg = lay.add(sizeof(int) * 2);
   const size_t oRed = lay.add(sizeof(double) * 4);
   const size_t oUr = lay.add(sizeof(double) * K);
   const size_t oOs = lay.add(sizeof(int) * ns);
@@ -1101,6 +1140,8 @@ int alloc_solve(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm
   c0.mode = kSweep;
   c0.reset = 1;
   ok = ok && h2d(oCtrl, &c0, sizeof c0);
+  static const int zeros2[2] = {0, 0};
+  ok = ok && h2d(oChg, zeros2, sizeof zeros2);
   if (!ok) return ALLOC_EDEVICE;
 
   Drop d;
@@ -1131,7 +1172,7 @@ int alloc_solve(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm
   d.pel_part = (double*)(ws + oPep);
   d.R_part = (double*)(ws + oRP);
   d.d_part = (double*)(ws + oDp);
-  d.chg_part = (int*)(ws + oChg);
+  d.chg_count = (int*)(ws + oChg);
   d.red = (double*)(ws + oRed);
   d.user_rate = (double*)(ws + oUr);
   d.out_sel = (int*)(ws + oOs);

@@ -4,6 +4,7 @@ Every case prints its name before the GPU call so that a failing run names
 it.  Inputs come from the seeded generator; expected values from the oracle
 (run here, or stored by tests/golden/make_goldens.py for the full-size case).
 """
+import dataclasses
 import hashlib
 import os
 import sys
@@ -42,13 +43,18 @@ def _gpu_params(op):
 
 def _run(ctx, d, op, label, device_gain=False, **kw):
     print(f"[gpu case] {label} M={d.M} N={d.N} K={d.K} l={d.l}", flush=True)
-    orc = oracle.solve(d, op, **{k: v for k, v in kw.items() if k in ("pmask", "weight", "warm")})
+    okw = {k: v for k, v in kw.items() if k in ("pmask", "weight", "warm")}
+    orc = oracle.solve(d, op, **okw)
     gain = None
     if device_gain:
         import torch
         gain = torch.from_numpy(d.gain).cuda()
     gpu = ctx.solve(d, _gpu_params(op), gain=gain, **kw)
-    info = parity.compare(d, gpu, orc, pmask=kw.get("pmask"), label=label)
+
+    def rerun(scale):
+        return oracle.solve(dataclasses.replace(d, noise_w=d.noise_w * scale), op, **okw)
+
+    info = parity.compare(d, gpu, orc, pmask=kw.get("pmask"), label=label, rerun=rerun)
     print(info, flush=True)
     return gpu, orc, info
 
@@ -60,11 +66,17 @@ def test_cfg1_converge(ctx):
     assert "skipped" not in info
 
 
-@pytest.mark.parametrize("seed", range(8))
-def test_cfg2_converge_with_caps(ctx, seed):
-    d = synth.make_drop(synth.CFG2, seed, 0)
-    op = oracle.Params(fixed_count=0)
-    _run(ctx, d, op, f"cfg2 seed{seed}", device_gain=True)
+def test_cfg2_converge_with_caps(ctx):
+    """Seeds 0-15 of the 5-RRH / 64-subcarrier / 32-user configuration; at most
+    a quarter may be rounding-chaotic (compared on EE and structure only)."""
+    chaotic = []
+    for seed in range(16):
+        d = synth.make_drop(synth.CFG2, seed, 0)
+        _, _, info = _run(ctx, d, oracle.Params(fixed_count=0), f"cfg2 seed{seed}", device_gain=True)
+        if info.get("skipped"):
+            chaotic.append(seed)
+    print("cfg2 drops compared on EE only:", chaotic, flush=True)
+    assert len(chaotic) <= 4
 
 
 @pytest.mark.parametrize("seed", range(3))

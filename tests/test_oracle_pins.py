@@ -485,6 +485,9 @@ def test_output_feasible_and_consistent(seed):
     assert ok["budget"] or r.xi.max() > 0
     ev = refeval.evaluate(d, P)
     assert r.ee == pytest.approx(ev["ee"], rel=1e-12)
+    # powers are zero or at least 1e-20 of the mask
+    pmask = (d.pmax_w / d.N)[:, None, None]
+    assert ((r.slot_power == 0) | (r.slot_power >= 1e-20 * pmask)).all()
     np.testing.assert_allclose(r.user_rate, ev["user_rate"], rtol=1e-12, atol=1e-13)
     # users are served only by their associated RRH
     for m in range(d.M):
