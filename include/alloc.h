@@ -55,6 +55,7 @@ extern "C" {
 /* alloc_params.flags */
 #define ALLOC_GAIN_ON_DEVICE 1u /* problem.gain is a device pointer */
 #define ALLOC_OUT_ON_DEVICE 2u  /* array outputs of alloc_result are device pointers */
+#define ALLOC_WARM_ON_DEVICE 4u /* alloc_warm arrays are device pointers */
 
 /* alloc_result.status_flags */
 #define ALLOC_NOT_CONVERGED 1u  /* Dinkelbach stopped at max_dinkelbach */
@@ -100,12 +101,23 @@ typedef struct {
   double step0;                  /* 0.1: subgradient step step0/sqrt(1+v) */
   uint32_t flags;                /* ALLOC_GAIN_ON_DEVICE | ALLOC_OUT_ON_DEVICE */
   int32_t max_groups;            /* 0: cap on the workgroups of the solve grid
-                                    (0 = as many as can be co-resident, <= N) */
+                                    (0 = one per compute unit, <= N) */
+  int32_t tile;                  /* 0: subcarriers a workgroup processes together
+                                    (0 = as many as its LDS holds) */
 } alloc_params;
 
 ALLOC_API void alloc_params_default(alloc_params* p);
 
-/* Optional warm start: any pointer may be NULL (host, double). */
+/* Optional warm start: any pointer may be NULL (double; host, or device with
+ * ALLOC_WARM_ON_DEVICE).  With p0 the initial allocation is built from it and
+ * is Dinkelbach's p^0 (Sec. III): the first step evaluates it without dual
+ * sweeps, E^1 = R(p^0)/P(p^0).  Users go to the RRH of largest total p0
+ * (a user with no positive p0 keeps the cold-start RRH, the one of largest
+ * sum over n of log2(1 + Gamma pmask/sigma)); each (m,n) takes the l users of
+ * largest positive p0 among its users, at power min(p0, pmask).  Without p0
+ * the cold start applies (those RRHs, the l strongest users of each (m,n),
+ * power pmax/(N l)).  xi' starts at max(xi0, 0) (else 0), zeta' at
+ * max(zeta0, 0) for streaming users (else 1). */
 typedef struct {
   const double* p0;    /* [M][N][K] initial powers */
   const double* xi0;   /* [M] */
@@ -134,6 +146,19 @@ typedef struct {
  * written (the call synchronises the stream). */
 ALLOC_API int alloc_solve(alloc_ctx* ctx, const alloc_problem* prob, const alloc_params* prm,
                 const alloc_warm* warm, alloc_result* res);
+
+/* Solve B independent drops of any sizes in one persistent launch: each
+ * workgroup takes the next drop from a work queue (largest M*N*K first) and
+ * solves it completely (same method and schedule as alloc_solve, reductions
+ * over the drop's subcarriers in the workgroup).  probs[b].gain are device
+ * pointers with ALLOC_GAIN_ON_DEVICE (each drop its own [M][N][K] array),
+ * host pointers otherwise.  results[b] arrays are host pointers (the
+ * ALLOC_OUT_ON_DEVICE flag is rejected).  warms is NULL or [B] warm starts
+ * (each with NULL members for a cold start).  Any error in any drop's
+ * arguments rejects the whole call before work starts. */
+ALLOC_API int alloc_solve_batch(alloc_ctx* ctx, int32_t B, const alloc_problem* probs,
+                                const alloc_params* prm, const alloc_warm* warms,
+                                alloc_result* results);
 
 ALLOC_API const char* alloc_strerror(int code);
 

@@ -881,11 +881,14 @@ ORC_API int orc_solve(const orc_problem* pb, const orc_params* prm, const orc_wa
   int i = 0, total = 0;
   double* rate = (double*)malloc(sizeof(double) * K);
   st->E = 0.0; /* E^0 = 0 */
+  /* A warm initial allocation is the Dinkelbach iteration's p^0 itself: its
+   * first step runs no dual sweeps, so E^1 = R(p^0)/P(p^0). */
+  int skip_sweeps = (warm && warm->p0) ? 1 : 0;
   for (;;) {
     orc_state_reset_scale(st);
     orc_state_reset_churn(st);
     int v = 0;
-    for (;;) {
+    for (; !skip_sweeps;) {
       const int refit = prm->refit_period > 0 && (v % prm->refit_period) == 0;
       const double d = orc_state_sweep(st, v, refit);
       ++v;
@@ -900,6 +903,7 @@ ORC_API int orc_solve(const orc_problem* pb, const orc_params* prm, const orc_wa
         if (d < prm->tol_dual) break;
       }
     }
+    skip_sweeps = 0;
     orc_state_eval(st, &R, &P, NULL, rate);
     const double F = R - st->E * P;
     if (res->trace_E) res->trace_E[i] = st->E;

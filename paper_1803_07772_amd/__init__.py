@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "_liballoc.so")
 
 ALLOC_GAIN_ON_DEVICE = 1
 ALLOC_OUT_ON_DEVICE = 2
+ALLOC_WARM_ON_DEVICE = 4
 NOT_CONVERGED = 1
 QOS_INFEASIBLE = 2
 NONFINITE = 8
@@ -46,7 +47,8 @@ class _Params(ctypes.Structure):
                 ("refit_period", ctypes.c_int32), ("fixed_count", ctypes.c_int32),
                 ("churn_limit", ctypes.c_int32), ("tol_dinkelbach", ctypes.c_double),
                 ("tol_dual", ctypes.c_double), ("step0", ctypes.c_double),
-                ("flags", ctypes.c_uint32), ("max_groups", ctypes.c_int32)]
+                ("flags", ctypes.c_uint32), ("max_groups", ctypes.c_int32),
+                ("tile", ctypes.c_int32)]
 
 
 class _Warm(ctypes.Structure):
@@ -64,7 +66,11 @@ class _Result(ctypes.Structure):
 
 
 EXPORTS = ("alloc_ctx_create", "alloc_ctx_destroy", "alloc_params_default", "alloc_solve",
-           "alloc_strerror", "alloc_ctx_set_timing", "alloc_ctx_last_kernel_ms")
+           "alloc_solve_batch", "alloc_strerror", "alloc_ctx_set_timing", "alloc_ctx_last_kernel_ms",
+           "alloc_mlp_create", "alloc_mlp_destroy", "alloc_mlp_set_params", "alloc_mlp_get_params",
+           "alloc_mlp_features", "alloc_mlp_forward", "alloc_mlp_grad", "alloc_mlp_train_step",
+           "alloc_mlp_adamw", "alloc_mlp_rows", "alloc_mlp_warm", "alloc_solve_mlp",
+           "alloc_solve_batch_mlp", "alloc_mlp_last_ms")
 
 
 def load():
@@ -85,6 +91,10 @@ def load():
                                     ctypes.POINTER(_Params), ctypes.POINTER(_Warm),
                                     ctypes.POINTER(_Result)]
         lib.alloc_solve.restype = ctypes.c_int
+        lib.alloc_solve_batch.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(_Problem),
+                                          ctypes.POINTER(_Params), ctypes.POINTER(_Warm),
+                                          ctypes.POINTER(_Result)]
+        lib.alloc_solve_batch.restype = ctypes.c_int
         lib.alloc_strerror.argtypes = [ctypes.c_int]
         lib.alloc_strerror.restype = ctypes.c_char_p
         lib.alloc_ctx_set_timing.argtypes = [ctypes.c_void_p, ctypes.c_int]
@@ -111,18 +121,19 @@ class Params:
     tol_dual: float = 1e-7
     step0: float = 0.1
     max_groups: int = 0
+    tile: int = 0
 
     def _c(self, flags: int) -> _Params:
         return _Params(self.max_dinkelbach, self.sweeps_per_dinkelbach, self.refit_period,
                        self.fixed_count, self.churn_limit, self.tol_dinkelbach, self.tol_dual,
-                       self.step0, flags, self.max_groups)
+                       self.step0, flags, self.max_groups, self.tile)
 
 
 def default_params() -> Params:
     p = _Params()
     load().alloc_params_default(ctypes.byref(p))
     return Params(p.max_dinkelbach, p.sweeps_per_dinkelbach, p.refit_period, p.fixed_count,
-                  p.churn_limit, p.tol_dinkelbach, p.tol_dual, p.step0, p.max_groups)
+                  p.churn_limit, p.tol_dinkelbach, p.tol_dual, p.step0, p.max_groups, p.tile)
 
 
 @dataclasses.dataclass
@@ -149,6 +160,53 @@ def _hp(keep, a, dtype):
     a = np.ascontiguousarray(a, dtype=dtype)
     keep.append(a)
     return a.ctypes.data
+
+
+def problem_struct(drop, keep, gain=None, pmask=None, weight=None):
+    """(alloc_problem, flags) of a drop; ``gain`` is None (host drop.gain), a
+    host array, or a contiguous float32 [M][N][K] GPU tensor."""
+    flags = 0
+    if gain is not None and hasattr(gain, "data_ptr"):
+        if not gain.is_cuda or not gain.is_contiguous() or gain.dtype.itemsize != 4:
+            raise ValueError("gain tensor must be contiguous float32 on the GPU")
+        if tuple(gain.shape) != (drop.M, drop.N, drop.K):
+            raise ValueError(f"gain shape {tuple(gain.shape)} != {(drop.M, drop.N, drop.K)}")
+        gptr = gain.data_ptr()
+        flags |= ALLOC_GAIN_ON_DEVICE
+    else:
+        g = drop.gain if gain is None else gain
+        if np.shape(g) != (drop.M, drop.N, drop.K):
+            raise ValueError("gain shape mismatch")
+        gptr = _hp(keep, g, np.float32)
+    pb = _Problem(drop.M, drop.N, drop.K, drop.l, gptr, _hp(keep, drop.user_type, np.uint8),
+                  _hp(keep, drop.arrival_bps, np.float64), _hp(keep, drop.delay_s, np.float64),
+                  _hp(keep, drop.pmax_w, np.float64), _hp(keep, drop.eta, np.float64),
+                  _hp(keep, pmask, np.float64), _hp(keep, weight, np.float64),
+                  drop.noise_w, drop.bw_hz, drop.packet_bits, drop.p_fiber_hpn,
+                  drop.p_fiber_lpn, drop.p_circuit_hpn, drop.p_circuit_lpn)
+    return pb, flags
+
+
+def result_struct(drop, dense_power=False):
+    """(alloc_result with host output arrays, the arrays, dense power or None)."""
+    M, N, K, L = drop.M, drop.N, drop.K, drop.l
+    NP = L * (L - 1) // 2
+    out = dict(sel=np.empty((M, N, L), np.int32), slot_power=np.empty((M, N, L)),
+               rrh_of_user=np.empty(K, np.int32), xi=np.empty(M), zeta=np.empty(K),
+               zeta_sic=np.empty((M, N, NP)), user_rate=np.empty(K))
+    dense = np.empty((M, N, K), np.float32) if dense_power else None
+    res = _Result(out["sel"].ctypes.data, out["slot_power"].ctypes.data,
+                  dense.ctypes.data if dense is not None else None,
+                  out["rrh_of_user"].ctypes.data, out["xi"].ctypes.data,
+                  out["zeta"].ctypes.data, out["zeta_sic"].ctypes.data if NP else None,
+                  out["user_rate"].ctypes.data, 0.0, 0.0, 0.0, 0, 0, 0)
+    return res, out, dense
+
+
+def to_result(res, out, dense) -> "Result":
+    return Result(ee=res.ee, rate_sum=res.rate_sum, power_sum=res.power_sum,
+                  dinkelbach_iters=res.dinkelbach_iters, sweeps=res.sweeps,
+                  status_flags=res.status_flags, power=dense, **out)
 
 
 class Context:
@@ -182,6 +240,49 @@ class Context:
         except Exception:
             pass
 
+    def solve_batch(self, drops, params: Params | None = None, gains=None,
+                    dense_power: bool = False, warms=None) -> list:
+        """Solve a list of drops in one persistent launch.
+
+        ``gains`` is None (host gains of each drop are copied) or a list of
+        contiguous float32 GPU tensors, one [M][N][K] per drop.  ``warms`` is
+        None or one dict per drop (keys p0, xi0, zeta0; None for a cold start)
+        of host float64 arrays."""
+        params = params or Params()
+        keep = []
+        flags = ALLOC_GAIN_ON_DEVICE if gains is not None else 0
+        B = len(drops)
+        cwarms = None
+        if warms is not None:
+            if len(warms) != B:
+                raise ValueError("one warm start (or None) per drop")
+            cwarms = (_Warm * B)()
+            for b, w in enumerate(warms):
+                w = w or {}
+                cwarms[b] = _Warm(*(_hp(keep, w[k], np.float64) if w.get(k) is not None else None
+                                    for k in ("p0", "xi0", "zeta0")))
+        probs, results, outs = self._batch_structs(drops, keep, gains, dense_power)
+        pc = params._c(flags)
+        _check(load().alloc_solve_batch(self._h, B, probs, ctypes.byref(pc), cwarms, results))
+        return [to_result(results[b], *outs[b]) for b in range(B)]
+
+    @staticmethod
+    def _batch_structs(drops, keep, gains, dense_power):
+        B = len(drops)
+        probs = (_Problem * B)()
+        results = (_Result * B)()
+        outs = []
+        if gains is not None and len(gains) != B:
+            raise ValueError("one gain tensor per drop")
+        for b, drop in enumerate(drops):
+            g = None if gains is None else gains[b]
+            if g is not None and not hasattr(g, "data_ptr"):
+                raise ValueError(f"gain {b} must be a GPU tensor")
+            probs[b], _ = problem_struct(drop, keep, g)
+            results[b], out, dense = result_struct(drop, dense_power)
+            outs.append((out, dense))
+        return probs, results, outs
+
     def solve(self, drop, params: Params | None = None, gain=None, warm=None, pmask=None,
               weight=None, dense_power: bool = False) -> Result:
         """Solve one drop.
@@ -192,36 +293,8 @@ class Context:
         """
         params = params or Params()
         keep = []
-        flags = 0
-        if gain is not None and hasattr(gain, "data_ptr"):
-            if not gain.is_cuda or not gain.is_contiguous() or gain.dtype.itemsize != 4:
-                raise ValueError("gain tensor must be contiguous float32 on the GPU")
-            if tuple(gain.shape) != (drop.M, drop.N, drop.K):
-                raise ValueError(f"gain shape {tuple(gain.shape)} != {(drop.M, drop.N, drop.K)}")
-            gptr = gain.data_ptr()
-            flags |= ALLOC_GAIN_ON_DEVICE
-        else:
-            g = drop.gain if gain is None else gain
-            if np.shape(g) != (drop.M, drop.N, drop.K):
-                raise ValueError("gain shape mismatch")
-            gptr = _hp(keep, g, np.float32)
-        pb = _Problem(drop.M, drop.N, drop.K, drop.l, gptr, _hp(keep, drop.user_type, np.uint8),
-                      _hp(keep, drop.arrival_bps, np.float64), _hp(keep, drop.delay_s, np.float64),
-                      _hp(keep, drop.pmax_w, np.float64), _hp(keep, drop.eta, np.float64),
-                      _hp(keep, pmask, np.float64), _hp(keep, weight, np.float64),
-                      drop.noise_w, drop.bw_hz, drop.packet_bits, drop.p_fiber_hpn,
-                      drop.p_fiber_lpn, drop.p_circuit_hpn, drop.p_circuit_lpn)
-        M, N, K, L = drop.M, drop.N, drop.K, drop.l
-        NP = L * (L - 1) // 2
-        out = dict(sel=np.empty((M, N, L), np.int32), slot_power=np.empty((M, N, L)),
-                   rrh_of_user=np.empty(K, np.int32), xi=np.empty(M), zeta=np.empty(K),
-                   zeta_sic=np.empty((M, N, NP)), user_rate=np.empty(K))
-        dense = np.empty((M, N, K), np.float32) if dense_power else None
-        res = _Result(out["sel"].ctypes.data, out["slot_power"].ctypes.data,
-                      dense.ctypes.data if dense is not None else None,
-                      out["rrh_of_user"].ctypes.data, out["xi"].ctypes.data,
-                      out["zeta"].ctypes.data, out["zeta_sic"].ctypes.data if NP else None,
-                      out["user_rate"].ctypes.data, 0.0, 0.0, 0.0, 0, 0, 0)
+        pb, flags = problem_struct(drop, keep, gain, pmask, weight)
+        res, out, dense = result_struct(drop, dense_power)
         wm = None
         if warm is not None:
             wm = _Warm(_hp(keep, warm.get("p0"), np.float64), _hp(keep, warm.get("xi0"), np.float64),
@@ -229,6 +302,4 @@ class Context:
         pc = params._c(flags)
         _check(load().alloc_solve(self._h, ctypes.byref(pb), ctypes.byref(pc),
                                   ctypes.byref(wm) if wm is not None else None, ctypes.byref(res)))
-        return Result(ee=res.ee, rate_sum=res.rate_sum, power_sum=res.power_sum,
-                      dinkelbach_iters=res.dinkelbach_iters, sweeps=res.sweeps,
-                      status_flags=res.status_flags, power=dense, **out)
+        return to_result(res, out, dense)

@@ -17,10 +17,10 @@ FLAGS = [
 
 
 def build(verbose: bool = False) -> str:
-    src = os.path.join(_HERE, "csrc", "alloc.hip")
+    srcs = [os.path.join(_HERE, "csrc", f) for f in ("alloc.hip", "mlp.hip")]
     out = os.path.join(_HERE, "_liballoc.so")
     tmp = out + ".tmp"
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-o", tmp, src]
+    cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-o", tmp, *srcs]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

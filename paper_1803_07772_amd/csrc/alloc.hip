@@ -26,6 +26,7 @@
 #include <vector>
 
 #include "alloc.h"
+#include "ctx.h"
 
 namespace cg = cooperative_groups;
 
@@ -57,7 +58,7 @@ struct Ctrl {
 };
 
 struct Sched {
-  int max_d, sweeps, refit_period, fixed, churn;
+  int max_d, sweeps, refit_period, fixed, churn, tile;
   double tol_d, tol_dual, step0;
 };
 
@@ -98,123 +99,141 @@ struct Drop {
   double* out_p;           // [M][N][L]
   double* out_zs;          // [M][N][NP]
   Ctrl* ctrl;              // final control state for the host
+  int tile;                // subcarriers per LDS tile (batched solver)
+  int preset;              // batched solver: the initial state is already written
+  int start_eval;          // the initial allocation is Dinkelbach's p^0 (warm start)
 };
 
-// LDS carve-up for one workgroup.
+// LDS carve-up for one workgroup.  Arrays marked [T] have one row per
+// subcarrier of the tile being processed.
 struct Lds {
-  float* g;       // [M][K] gains of the current subcarrier
-  double* u;      // [M][K] (sigma + ICI)/Gamma
+  float* g;       // [T][M][K] gains
+  double* u;      // [T][M][K] (sigma + ICI)/Gamma
   double* Sacc;   // [M][K] association metric summed over my subcarriers
   double* mu;     // [K] 1 (elastic) or zeta'
-  double* Hc;     // [K] H of user k on its own RRH
-  double* pic;    // [K] intra-cell price of user k on its own RRH
   double* racc;   // [K]
   double* rhacc;  // [K]
   int* Al;        // [K]
+  int* el;        // [K] 1 elastic
   int* grp;       // [K] users grouped by RRH
-  int* grp_off;   // [M+1]
   int* grpk;      // [K] rank of a user within its RRH group
+  int* grp_off;   // [M+1]
   int* wcnt;      // [kBlock/64][M] per-wave group counts
   int* gcur;      // [M]
-  // slots of the current subcarrier, storage order
-  int* su;        // [M][L]
-  double* sp;     // [M][L]
-  double* sal;    // [M][L]
-  double* sbe;    // [M][L]
-  double* szs;    // [M][L][L]
-  double* szn;    // [M][L][L] after this sweep's subgradient step
-  // per-RRH view in decoding order
-  int* vcnt;      // [M]
-  int* vslot;     // [M][L]
-  int* vuser;     // [M][L]
-  double* vu;     // [M][L]
-  double* vpre;   // [M][L+1]
-  double* vc;     // [M][L]
-  double* vcg;    // [M][L]
-  double* vT;     // [M][L+1] suffix sums of vcg
-  double* Ptot;   // [M]
-  double* pinter; // [M]
-  double* psic;   // [M]
-  double* contrib; // [M][M]
+  double* Hc;     // [T][K] H of user k on its own RRH
+  double* pic;    // [T][K] intra-cell price of user k on its own RRH
+  double* rk;     // [T][K] rate of user k on the subcarrier
+  double* rhk;    // [T][K] surrogate rate
+  int* su;        // [T][M][L] slots, storage order
+  double* sp;     // [T][M][L]
+  double* sal;    // [T][M][L]
+  double* sbe;    // [T][M][L]
+  double* szs;    // [T][M][L][L]
+  double* szn;    // [T][M][L][L] after this sweep's subgradient step
+  int* vcnt;      // [T][M] per-RRH view in decoding order
+  int* vslot;     // [T][M][L]
+  int* vuser;     // [T][M][L]
+  double* vu;     // [T][M][L]
+  double* vpre;   // [T][M][L+1]
+  double* vc;     // [T][M][L]
+  double* vcg;    // [T][M][L]
+  double* vr;     // [T][M][L]
+  double* vT;     // [T][M][L+1] suffix sums of vcg
+  double* Ptot;   // [T][M]
+  double* pinter; // [T][M]
+  double* psic;   // [T][M]
+  double* tps;    // [T][M]
+  double* tpe;    // [T][M]
+  double* tR;     // [T][M]
+  int* frozen;    // [T][M]
+  int* churn;     // [T][M]
+  int* np;        // [T][M]
+  double* pij;    // [T][M][M]
+  double* contrib; // [T][M][M]
+  int* chosen;    // [T][M][L]
+  int* nold;      // [T][M][L]
+  double* dmi;    // [T][M][L]
   double* xi;     // [M]
+  double* eta;    // [M]
+  double* pmask;  // [M]
   double* psacc;  // [M]
   double* peacc;  // [M]
   double* Racc;   // [M]
   double* dmax;   // [M]
-  int* churn;     // [M]
   double* red;    // [kBlock] scratch for reductions
   double* tmp;    // [M+2] reduction results
 };
 
 __host__ __device__ inline size_t align8(size_t x) { return (x + 7) & ~size_t(7); }
 
-__host__ __device__ inline size_t lds_bytes(int M, int K, int L) {
-  size_t b = 0;
-  b += align8(sizeof(float) * M * K);
-  b += 2 * sizeof(double) * M * K;
-  b += 5 * sizeof(double) * K;
-  b += 2 * sizeof(int) * K + align8(sizeof(int) * (M + 1));
-  b += align8(sizeof(int) * M * L) + 3 * sizeof(double) * M * L;
-  b += 2 * sizeof(double) * M * L * L;
-  b += align8(sizeof(int) * M) + 2 * align8(sizeof(int) * M * L);
-  b += 3 * sizeof(double) * M * L + 2 * sizeof(double) * M * (L + 1);
-  b += 9 * sizeof(double) * M + sizeof(double) * M * M;
-  b += align8(sizeof(int) * M);
-  b += sizeof(double) * kBlock;
-  b += align8(sizeof(int) * K) + align8(sizeof(int) * (kBlock / 64) * M) + align8(sizeof(int) * M);
-  b += sizeof(double) * (M + 2);
-  return b + 64;
-}
-
-__device__ Lds carve(char* base, int M, int K, int L) {
+// Lays the arrays out from `base`; returns the bytes used.  With base ==
+// nullptr it only measures (host side).
+__host__ __device__ inline size_t carve_lds(char* base, int M, int K, int L, int T, Lds* out) {
   Lds s;
   size_t o = 0;
   auto take = [&](size_t bytes) {
-    char* p = base + o;
+    char* p = base ? base + o : nullptr;
     o += align8(bytes);
     return p;
   };
-  s.g = (float*)take(sizeof(float) * M * K);
-  s.u = (double*)take(sizeof(double) * M * K);
+  const size_t TM = (size_t)T * M, TML = TM * L, TK = (size_t)T * K;
+  s.g = (float*)take(sizeof(float) * TM * K);
+  s.u = (double*)take(sizeof(double) * TM * K);
   s.Sacc = (double*)take(sizeof(double) * M * K);
   s.mu = (double*)take(sizeof(double) * K);
-  s.Hc = (double*)take(sizeof(double) * K);
-  s.pic = (double*)take(sizeof(double) * K);
   s.racc = (double*)take(sizeof(double) * K);
   s.rhacc = (double*)take(sizeof(double) * K);
   s.Al = (int*)take(sizeof(int) * K);
+  s.el = (int*)take(sizeof(int) * K);
   s.grp = (int*)take(sizeof(int) * K);
-  s.grp_off = (int*)take(sizeof(int) * (M + 1));
   s.grpk = (int*)take(sizeof(int) * K);
+  s.grp_off = (int*)take(sizeof(int) * (M + 1));
   s.wcnt = (int*)take(sizeof(int) * (kBlock / 64) * M);
   s.gcur = (int*)take(sizeof(int) * M);
-  s.su = (int*)take(sizeof(int) * M * L);
-  s.sp = (double*)take(sizeof(double) * M * L);
-  s.sal = (double*)take(sizeof(double) * M * L);
-  s.sbe = (double*)take(sizeof(double) * M * L);
-  s.szs = (double*)take(sizeof(double) * M * L * L);
-  s.szn = (double*)take(sizeof(double) * M * L * L);
-  s.vcnt = (int*)take(sizeof(int) * M);
-  s.vslot = (int*)take(sizeof(int) * M * L);
-  s.vuser = (int*)take(sizeof(int) * M * L);
-  s.vu = (double*)take(sizeof(double) * M * L);
-  s.vpre = (double*)take(sizeof(double) * M * (L + 1));
-  s.vc = (double*)take(sizeof(double) * M * L);
-  s.vcg = (double*)take(sizeof(double) * M * L);
-  s.vT = (double*)take(sizeof(double) * M * (L + 1));
-  s.Ptot = (double*)take(sizeof(double) * M);
-  s.pinter = (double*)take(sizeof(double) * M);
-  s.psic = (double*)take(sizeof(double) * M);
-  s.contrib = (double*)take(sizeof(double) * M * M);
+  s.Hc = (double*)take(sizeof(double) * TK);
+  s.pic = (double*)take(sizeof(double) * TK);
+  s.rk = (double*)take(sizeof(double) * TK);
+  s.rhk = (double*)take(sizeof(double) * TK);
+  s.su = (int*)take(sizeof(int) * TML);
+  s.sp = (double*)take(sizeof(double) * TML);
+  s.sal = (double*)take(sizeof(double) * TML);
+  s.sbe = (double*)take(sizeof(double) * TML);
+  s.szs = (double*)take(sizeof(double) * TML * L);
+  s.szn = (double*)take(sizeof(double) * TML * L);
+  s.vcnt = (int*)take(sizeof(int) * TM);
+  s.vslot = (int*)take(sizeof(int) * TML);
+  s.vuser = (int*)take(sizeof(int) * TML);
+  s.vu = (double*)take(sizeof(double) * TML);
+  s.vpre = (double*)take(sizeof(double) * TM * (L + 1));
+  s.vc = (double*)take(sizeof(double) * TML);
+  s.vcg = (double*)take(sizeof(double) * TML);
+  s.vr = (double*)take(sizeof(double) * TML);
+  s.vT = (double*)take(sizeof(double) * TM * (L + 1));
+  s.Ptot = (double*)take(sizeof(double) * TM);
+  s.pinter = (double*)take(sizeof(double) * TM);
+  s.psic = (double*)take(sizeof(double) * TM);
+  s.tps = (double*)take(sizeof(double) * TM);
+  s.tpe = (double*)take(sizeof(double) * TM);
+  s.tR = (double*)take(sizeof(double) * TM);
+  s.frozen = (int*)take(sizeof(int) * TM);
+  s.churn = (int*)take(sizeof(int) * TM);
+  s.np = (int*)take(sizeof(int) * TM);
+  s.pij = (double*)take(sizeof(double) * TM * M);
+  s.contrib = (double*)take(sizeof(double) * TM * M);
+  s.chosen = (int*)take(sizeof(int) * TML);
+  s.nold = (int*)take(sizeof(int) * TML);
+  s.dmi = (double*)take(sizeof(double) * TML);
   s.xi = (double*)take(sizeof(double) * M);
+  s.eta = (double*)take(sizeof(double) * M);
+  s.pmask = (double*)take(sizeof(double) * M);
   s.psacc = (double*)take(sizeof(double) * M);
   s.peacc = (double*)take(sizeof(double) * M);
   s.Racc = (double*)take(sizeof(double) * M);
   s.dmax = (double*)take(sizeof(double) * M);
-  s.churn = (int*)take(sizeof(int) * M);
   s.red = (double*)take(sizeof(double) * kBlock);
   s.tmp = (double*)take(sizeof(double) * (M + 2));
-  return s;
+  if (out) *out = s;
+  return o;
 }
 
 __device__ inline double log2_1p(double x) { return log1p(x) / kLn2; }
@@ -244,6 +263,7 @@ __device__ inline int load_shared(const int* p) {
 __device__ void begin_pass(const Drop& d, Lds& s) {
   const int M = d.M, K = d.K, tid = threadIdx.x, nth = blockDim.x;
   for (int k = tid; k < K; k += nth) {
+    s.el[k] = d.elastic[k];
     s.mu[k] = d.elastic[k] ? 1.0 : d.zeta[k];
     s.Al[k] = d.A[k];
     s.racc[k] = 0.0;
@@ -252,6 +272,8 @@ __device__ void begin_pass(const Drop& d, Lds& s) {
   for (int i = tid; i < M * K; i += nth) s.Sacc[i] = 0.0;
   for (int m = tid; m < M; m += nth) {
     s.xi[m] = d.xi[m];
+    s.eta[m] = d.eta[m];
+    s.pmask[m] = d.pmask[m];
     s.psacc[m] = 0.0;
     s.peacc[m] = 0.0;
     s.Racc[m] = 0.0;
@@ -305,300 +327,388 @@ struct PassConst {
 };
 
 // One subcarrier of a sweep (update) or of an evaluation pass (no update).
-__device__ void subcarrier(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s, int n) {
+// Indexing of the per-tile LDS arrays (s = subcarrier within the tile).
+#define IX_MK(s, m, k) ((((s) * M) + (m)) * K + (k))
+#define IX_ML(s, m, q) ((((s) * M) + (m)) * L + (q))
+#define IX_ML1(s, m, t) ((((s) * M) + (m)) * (L + 1) + (t))
+#define IX_MLL(s, m, a, b) (((((s) * M) + (m)) * L + (a)) * L + (b))
+#define IX_SM(s, m) ((s) * M + (m))
+#define IX_SMM(s, m, j) ((((s) * M) + (m)) * M + (j))
+#define IX_SK(s, k) ((s) * K + (k))
+
+// One tile of ns subcarriers n = n0, n0 + nstep, ... of a sweep (update) or
+// of an evaluation pass (no update).  Everything here is defined per
+// subcarrier; the tile only gives each barrier interval more independent work.
+__device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s, int n0, int nstep,
+                     int ns) {
   const int M = d.M, N = d.N, K = d.K, L = d.L, tid = threadIdx.x, nth = blockDim.x;
   const double sg = d.sigma;
+#define NOF(t) (n0 + (t) * nstep)
 
-  // 1. gains and slot state into LDS
-  for (int i = tid; i < M * K; i += nth) {
-    const int m = i / K, k = i - m * K;
-    s.g[i] = d.G[((size_t)m * N + n) * K + k];
+  // 1. gains, slot state and per-RRH totals into LDS
+  for (int i = tid; i < ns * M * K; i += nth) {
+    const int t = i / (M * K), r = i - t * M * K, m = r / K, k = r - m * K;
+    s.g[i] = d.G[((size_t)m * N + NOF(t)) * K + k];
   }
-  for (int i = tid; i < M * L; i += nth) {
-    const int m = i / L, q = i - m * L;
-    const size_t gi = ((size_t)m * N + n) * L + q;
+  for (int i = tid; i < ns * M * L; i += nth) {
+    const int t = i / (M * L), r = i - t * M * L, m = r / L, q = r - m * L;
+    const size_t gi = ((size_t)m * N + NOF(t)) * L + q;
     s.su[i] = d.sel[gi];
     s.sp[i] = d.p[gi];
     s.sal[i] = pc.reset ? 1.0 : d.al[gi];
     s.sbe[i] = pc.reset ? 0.0 : d.be[gi];
+    s.chosen[i] = -1;
   }
-  for (int i = tid; i < M * L * L; i += nth) {
-    s.szs[i] = d.zs[(size_t)n * L * L + (size_t)(i / (L * L)) * N * L * L + (i % (L * L))];
+  for (int i = tid; i < ns * M * L * L; i += nth) {
+    const int t = i / (M * L * L), r = i - t * M * L * L, m = r / (L * L), ab = r - m * L * L;
+    s.szs[i] = d.zs[((size_t)m * N + NOF(t)) * L * L + ab];
     s.szn[i] = 0.0;
   }
-  for (int m = tid; m < M; m += nth) s.churn[m] = pc.reset ? 0 : d.churn_sel[(size_t)m * N + n];
-  __syncthreads();
-
-  // 2. total power per RRH on n
-  for (int m = tid; m < M; m += nth) {
-    double acc = 0.0;
-    for (int q = 0; q < L; ++q)
-      if (s.su[m * L + q] >= 0) acc += s.sp[m * L + q];
-    s.Ptot[m] = acc;
+  for (int i = tid; i < ns * M; i += nth) {
+    const int t = i / M, m = i - t * M;
+    s.churn[i] = pc.reset ? 0 : d.churn_sel[(size_t)m * N + NOF(t)];
+    double acc = 0.0;  // total power of RRH m on the subcarrier
+    for (int q = 0; q < L; ++q) {
+      const size_t gi = ((size_t)m * N + NOF(t)) * L + q;
+      if (d.sel[gi] >= 0) acc += d.p[gi];
+    }
+    s.Ptot[i] = acc;
+  }
+  for (int i = tid; i < ns * K; i += nth) {
+    s.rk[i] = 0.0;
+    s.rhk[i] = 0.0;
   }
   __syncthreads();
 
-  // 3. inter-cell interference as exclusive prefix + suffix over RRHs (no
+  // 2. inter-cell interference as exclusive prefix + suffix over RRHs (no
   //    subtraction), stored as u = (sigma + ICI)/Gamma
-  for (int k = tid; k < K; k += nth) {
+  for (int i = tid; i < ns * K; i += nth) {
+    const int t = i / K, k = i - t * K;
     double suf = 0.0;
     for (int m = M - 1; m >= 0; --m) {
-      s.u[m * K + k] = suf;
-      suf += s.Ptot[m] * (double)s.g[m * K + k];
+      s.u[IX_MK(t, m, k)] = suf;
+      suf += s.Ptot[IX_SM(t, m)] * (double)s.g[IX_MK(t, m, k)];
     }
     double pre = 0.0;
     for (int m = 0; m < M; ++m) {
-      const double gm = (double)s.g[m * K + k];
-      const double ici = pre + s.u[m * K + k];
-      pre += s.Ptot[m] * gm;
-      s.u[m * K + k] = (sg + ici) / gm;
+      const double gm = (double)s.g[IX_MK(t, m, k)];
+      const double ici = pre + s.u[IX_MK(t, m, k)];
+      pre += s.Ptot[IX_SM(t, m)] * gm;
+      s.u[IX_MK(t, m, k)] = (sg + ici) / gm;
     }
   }
   __syncthreads();
 
-  // 4. per RRH: decoding order, SINR, rates, SCALE refit, prices
-  for (int m = tid; m < M; m += nth) {
-    int cnt = 0, slot[kMaxL], usr[kMaxL];
-    double uu[kMaxL];
-    for (int q = 0; q < L; ++q) {
-      const int k = s.su[m * L + q];
-      if (k < 0) continue;
-      slot[cnt] = q;
-      usr[cnt] = k;
-      uu[cnt] = s.u[m * K + k];
-      ++cnt;
+  // 3. SIC decoding order of each RRH's users: normalised gain descending
+  //    (u ascending), ties to the lower user; position by rank
+  for (int i = tid; i < ns * M * L; i += nth) {
+    const int t = i / (M * L), r = i - t * M * L, m = r / L, q = r - m * L;
+    const int k = s.su[i];
+    if (k < 0) continue;
+    const double uq = s.u[IX_MK(t, m, k)];
+    int pos = 0;
+    for (int q2 = 0; q2 < L; ++q2) {
+      const int k2 = s.su[IX_ML(t, m, q2)];
+      if (q2 == q || k2 < 0) continue;
+      const double u2 = s.u[IX_MK(t, m, k2)];
+      if (u2 < uq || (u2 == uq && k2 < k)) ++pos;
     }
-    for (int i = 1; i < cnt; ++i)  // normalised gain descending = u ascending
-      for (int j = i; j > 0 && (uu[j - 1] > uu[j] || (uu[j - 1] == uu[j] && usr[j - 1] > usr[j])); --j) {
-        double tu = uu[j]; uu[j] = uu[j - 1]; uu[j - 1] = tu;
-        int ti = usr[j]; usr[j] = usr[j - 1]; usr[j - 1] = ti;
-        ti = slot[j]; slot[j] = slot[j - 1]; slot[j - 1] = ti;
-      }
-    double pre = 0.0, ps = 0.0, pe = 0.0, Rm = 0.0;
-    for (int t = 0; t < cnt; ++t) {
-      const int k = usr[t], q = slot[t];
-      const double pq = s.sp[m * L + q];
-      const double wmk = d.w ? d.w[(size_t)m * K + k] : 1.0;
-      const double gam = pq / (uu[t] + pre);
-      const double r = log2_1p(gam);
-      double a = s.sal[m * L + q], b = s.sbe[m * L + q];
-      if (pc.refit && pq > 0.0) {
-        a = gam / (1.0 + gam);
-        b = r - a * log2(gam);
-        s.sal[m * L + q] = a;
-        s.sbe[m * L + q] = b;
-      }
-      const double rh = (pq > 0.0) ? b + a * log2(gam) : 0.0;
-      const double cg = wmk * s.mu[k] * a / (kLn2 * (uu[t] + pre));
-      s.vslot[m * L + t] = q;
-      s.vuser[m * L + t] = k;
-      s.vu[m * L + t] = uu[t];
-      s.vpre[m * (L + 1) + t] = pre;
-      s.vcg[m * L + t] = cg;
-      s.vc[m * L + t] = cg / (double)s.g[m * K + k];
-      s.racc[k] += wmk * r;  // a user holds at most one slot per subcarrier
-      s.rhacc[k] += wmk * rh;
-      ps += pq;
-      if (d.elastic[k]) {
-        pe += pq;
-        Rm += wmk * r;
-      }
-      pre += pq;
+    s.vslot[IX_ML(t, m, pos)] = q;
+    s.vuser[IX_ML(t, m, pos)] = k;
+    s.vu[IX_ML(t, m, pos)] = uq;
+  }
+  for (int i = tid; i < ns * M; i += nth) {
+    int cnt = 0;
+    for (int q = 0; q < L; ++q) cnt += s.su[i * L + q] >= 0;
+    s.vcnt[i] = cnt;
+  }
+  __syncthreads();
+
+  // 4. per selected user: SINR, rate, SCALE refit and surrogate, price c
+  for (int i = tid; i < ns * M * L; i += nth) {
+    const int t = i / (M * L), r = i - t * M * L, m = r / L, a = r - m * L;
+    if (a >= s.vcnt[IX_SM(t, m)]) continue;
+    double pre = 0.0;
+    for (int a2 = 0; a2 < a; ++a2) pre += s.sp[IX_ML(t, m, s.vslot[IX_ML(t, m, a2)])];
+    const int k = s.vuser[i], q = s.vslot[i];
+    const double pq = s.sp[IX_ML(t, m, q)];
+    const double wmk = d.w ? d.w[(size_t)m * K + k] : 1.0;
+    const double uu = s.vu[i];
+    const double gam = pq / (uu + pre);
+    const double rr = log2_1p(gam);
+    double al = s.sal[IX_ML(t, m, q)], be = s.sbe[IX_ML(t, m, q)];
+    if (pc.refit && pq > 0.0) {
+      al = gam / (1.0 + gam);
+      be = rr - al * log2(gam);
+      s.sal[IX_ML(t, m, q)] = al;
+      s.sbe[IX_ML(t, m, q)] = be;
     }
-    s.vpre[m * (L + 1) + cnt] = pre;
-    s.vcnt[m] = cnt;
-    s.psacc[m] += ps;
-    s.peacc[m] += pe;
-    s.Racc[m] += Rm;
+    const double rh = (pq > 0.0) ? be + al * log2(gam) : 0.0;
+    const double cg = wmk * s.mu[k] * al / (kLn2 * (uu + pre));
+    s.vpre[IX_ML1(t, m, a)] = pre;
+    s.vcg[i] = cg;
+    s.vc[i] = cg / (double)s.g[IX_MK(t, m, k)];
+    s.vr[i] = wmk * rr;
+    s.rk[IX_SK(t, k)] = wmk * rr;  // a user holds at most one slot per subcarrier
+    s.rhk[IX_SK(t, k)] = wmk * rh;
     if (pc.write_out) {
-      for (int t = 0; t < L; ++t) {
-        const size_t o = ((size_t)m * N + n) * L + t;
-        d.out_sel[o] = t < cnt ? usr[t] : -1;
-        d.out_p[o] = t < cnt ? s.sp[m * L + slot[t]] : 0.0;
+      const size_t o = ((size_t)m * N + NOF(t)) * L + a;
+      d.out_sel[o] = k;
+      d.out_p[o] = pq;
+    }
+  }
+  __syncthreads();
+  for (int i = tid; i < ns * M; i += nth) {
+    const int t = i / M, m = i - t * M;
+    const int cnt = s.vcnt[i];
+    double ps = 0.0, pe = 0.0, Rm = 0.0;
+    for (int a = 0; a < cnt; ++a) {
+      const double pq = s.sp[IX_ML(t, m, s.vslot[IX_ML(t, m, a)])];
+      ps += pq;
+      if (s.el[s.vuser[IX_ML(t, m, a)]]) {
+        pe += pq;
+        Rm += s.vr[IX_ML(t, m, a)];
+      }
+    }
+    s.vpre[IX_ML1(t, m, cnt)] = ps;
+    s.tps[i] = ps;
+    s.tpe[i] = pe;
+    s.tR[i] = Rm;
+    if (pc.write_out) {
+      for (int a = cnt; a < L; ++a) {
+        const size_t o = ((size_t)m * N + NOF(t)) * L + a;
+        d.out_sel[o] = -1;
+        d.out_p[o] = 0.0;
       }
       int pi = 0;
       for (int a = 0; a < L; ++a)
         for (int b = a + 1; b < L; ++b, ++pi)
-          d.out_zs[((size_t)m * N + n) * d.NP + pi] =
-              (b < cnt) ? s.szs[m * L * L + slot[a] * L + slot[b]] : 0.0;
+          d.out_zs[((size_t)m * N + NOF(t)) * d.NP + pi] =
+              (b < cnt) ? s.szs[IX_MLL(t, m, s.vslot[IX_ML(t, m, a)], s.vslot[IX_ML(t, m, b)])] : 0.0;
     }
   }
   __syncthreads();
-  if (!pc.update) return;
-
-  // 5. inter-cell price and the C14 terms of this subcarrier's pairs
+  // tile sums into the pass accumulators, in subcarrier order
+  for (int k = tid; k < K; k += nth) {
+    double r = 0.0, rh = 0.0;
+    for (int t = 0; t < ns; ++t) {
+      r += s.rk[IX_SK(t, k)];
+      rh += s.rhk[IX_SK(t, k)];
+    }
+    s.racc[k] += r;
+    s.rhacc[k] += rh;
+  }
   for (int m = tid; m < M; m += nth) {
-    double acc = 0.0;
-    for (int j = 0; j < M; ++j) {
-      if (j == m) continue;
-      for (int t = 0; t < s.vcnt[j]; ++t) acc += s.vc[j * L + t] * (double)s.g[m * K + s.vuser[j * L + t]];
+    for (int t = 0; t < ns; ++t) {
+      s.psacc[m] += s.tps[IX_SM(t, m)];
+      s.peacc[m] += s.tpe[IX_SM(t, m)];
+      s.Racc[m] += s.tR[IX_SM(t, m)];
     }
-    s.pinter[m] = acc;
-    for (int j = 0; j < M; ++j) s.contrib[m * M + j] = 0.0;
-    const int cnt = s.vcnt[m];
-    for (int a = 0; a < cnt; ++a)
-      for (int b = a + 1; b < cnt; ++b) {
-        const int ka = s.vuser[m * L + a], kb = s.vuser[m * L + b];
-        const double ga = s.g[m * K + ka], gb = s.g[m * K + kb];
-        const bool swap = gb > ga || (gb == ga && kb < ka);  // strong = larger raw gain
-        const int ps_ = swap ? b : a, pw_ = swap ? a : b;
-        const int ks = s.vuser[m * L + ps_], kw = s.vuser[m * L + pw_];
-        const double us = s.vu[m * L + ps_], uw = s.vu[m * L + pw_];
-        const double om = (us - uw) / (us + uw);  // Omega / nu
-        const int sa = s.vslot[m * L + a], sb = s.vslot[m * L + b];
-        const double z = s.szs[m * L * L + sa * L + sb];
-        const double gs = s.g[m * K + ks], gw = s.g[m * K + kw];
-        for (int j = 0; j < M; ++j) {
-          if (j == m) continue;
-          const double dj = ((double)s.g[j * K + ks] / gs - (double)s.g[j * K + kw] / gw) / (us + uw);
-          s.contrib[m * M + j] += z * dj;
+  }
+  if (!pc.update) {
+    __syncthreads();
+    return;
+  }
+
+  // 5. inter-cell price and C14 terms per (RRH m, other RRH j)
+  for (int i = tid; i < ns * M * M; i += nth) {
+    const int t = i / (M * M), r = i - t * M * M, m = r / M, j = r - m * M;
+    double inter = 0.0, sic = 0.0;
+    if (j != m) {
+      const int cj = s.vcnt[IX_SM(t, j)];
+      for (int a = 0; a < cj; ++a)
+        inter += s.vc[IX_ML(t, j, a)] * (double)s.g[IX_MK(t, m, s.vuser[IX_ML(t, j, a)])];
+      // pairs of RRH m: their margins move with the power of RRH j
+      const int cnt = s.vcnt[IX_SM(t, m)];
+      for (int a = 0; a < cnt; ++a)
+        for (int b = a + 1; b < cnt; ++b) {
+          const int ka = s.vuser[IX_ML(t, m, a)], kb = s.vuser[IX_ML(t, m, b)];
+          const double ga = s.g[IX_MK(t, m, ka)], gb = s.g[IX_MK(t, m, kb)];
+          const bool swap = gb > ga || (gb == ga && kb < ka);  // strong = larger raw gain
+          const int ks = swap ? kb : ka, kw = swap ? ka : kb;
+          const double us = swap ? s.vu[IX_ML(t, m, b)] : s.vu[IX_ML(t, m, a)];
+          const double uw = swap ? s.vu[IX_ML(t, m, a)] : s.vu[IX_ML(t, m, b)];
+          const double z = s.szs[IX_MLL(t, m, s.vslot[IX_ML(t, m, a)], s.vslot[IX_ML(t, m, b)])];
+          const double gs = swap ? gb : ga, gw = swap ? ga : gb;
+          const double dj = ((double)s.g[IX_MK(t, j, ks)] / gs - (double)s.g[IX_MK(t, j, kw)] / gw) / (us + uw);
+          sic += z * dj;
         }
-        const double zn = fmax(z + pc.delta_v * om, 0.0);
-        s.szn[m * L * L + sa * L + sb] = zn;
-        s.szn[m * L * L + sb * L + sa] = zn;
-      }
+    }
+    s.pij[i] = inter;
+    s.contrib[i] = sic;
+  }
+  // subgradient step of each pair's C14 multiplier on the margin Omega/nu
+  for (int i = tid; i < ns * M * L * L; i += nth) {
+    const int t = i / (M * L * L), r = i - t * M * L * L, m = r / (L * L), a = (r / L) % L, b = r % L;
+    if (!(a < b && b < s.vcnt[IX_SM(t, m)])) continue;
+    const int ka = s.vuser[IX_ML(t, m, a)], kb = s.vuser[IX_ML(t, m, b)];
+    const double ga = s.g[IX_MK(t, m, ka)], gb = s.g[IX_MK(t, m, kb)];
+    const bool swap = gb > ga || (gb == ga && kb < ka);
+    const double us = swap ? s.vu[IX_ML(t, m, b)] : s.vu[IX_ML(t, m, a)];
+    const double uw = swap ? s.vu[IX_ML(t, m, a)] : s.vu[IX_ML(t, m, b)];
+    const double om = (us - uw) / (us + uw);
+    const int sa = s.vslot[IX_ML(t, m, a)], sb = s.vslot[IX_ML(t, m, b)];
+    const double zn = fmax(s.szs[IX_MLL(t, m, sa, sb)] + pc.delta_v * om, 0.0);
+    s.szn[IX_MLL(t, m, sa, sb)] = zn;
+    s.szn[IX_MLL(t, m, sb, sa)] = zn;
   }
   __syncthreads();
-  for (int j = tid; j < M; j += nth) {
-    double acc = 0.0;
-    for (int m = 0; m < M; ++m)
-      if (m != j) acc += s.contrib[m * M + j];
-    s.psic[j] = acc;
-    const int cnt = s.vcnt[j];
-    s.vT[j * (L + 1) + cnt] = 0.0;
-    for (int t = cnt - 1; t >= 0; --t) s.vT[j * (L + 1) + t] = s.vT[j * (L + 1) + t + 1] + s.vcg[j * L + t];
+  for (int i = tid; i < ns * M; i += nth) {
+    const int t = i / M, m = i - t * M;
+    double inter = 0.0, sic = 0.0;
+    for (int j = 0; j < M; ++j) {
+      inter += s.pij[IX_SMM(t, m, j)];
+      if (j != m) sic += s.contrib[IX_SMM(t, j, m)];
+    }
+    s.pinter[i] = inter;
+    s.psic[i] = sic;
+    const int cnt = s.vcnt[i];
+    s.vT[IX_ML1(t, m, cnt)] = 0.0;
+    for (int a = cnt - 1; a >= 0; --a) s.vT[IX_ML1(t, m, a)] = s.vT[IX_ML1(t, m, a + 1)] + s.vcg[IX_ML(t, m, a)];
+    s.frozen[i] = sc.churn > 0 && s.churn[i] >= sc.churn;
   }
   __syncthreads();
 
-  // 6. per-triple Lagrangian maximum H for every (m,k)
+  // 6. per-triple Lagrangian maximum H for every (m,k), summed over the
+  //    tile's subcarriers in order
   for (int i = tid; i < M * K; i += nth) {
     const int m = i / K, k = i - m * K;
-    const double u = s.u[i];
-    const int cnt = s.vcnt[m];
-    int q = -1;
-    for (int t = 0; t < cnt; ++t)
-      if (s.vuser[m * L + t] == k) q = t;
-    double Sb, pin;
-    if (q >= 0) {
-      Sb = s.vpre[m * (L + 1) + q];
-      pin = s.vT[m * (L + 1) + q + 1];
-    } else {
-      int pos = 0;
-      for (int t = 0; t < cnt; ++t) {
-        const double ut = s.vu[m * L + t];
-        if (ut < u || (ut == u && s.vuser[m * L + t] < k)) ++pos;
-      }
-      Sb = s.vpre[m * (L + 1) + pos];
-      pin = s.vT[m * (L + 1) + pos];
-    }
     const double wmu = (d.w ? d.w[(size_t)m * K + k] : 1.0) * s.mu[k];
-    const double c = (d.elastic[k] ? pc.E * d.eta[m] : 0.0) + s.xi[m] + pin + s.pinter[m] + s.psic[m];
-    double H = 0.0;
-    if (wmu > 0.0) {
-      const double ainv = u + Sb;
-      double pt;
-      if (c <= 0.0) {
-        pt = d.pmask[m];
-      } else {
-        const double Wl = wmu / (c * kLn2);
-        pt = fmin(fmax(Wl - ainv, 0.0), d.pmask[m]);
+    const bool el = s.el[k];
+    const bool own = s.Al[k] == m;
+    double Hsum = 0.0;
+    for (int t = 0; t < ns; ++t) {
+      const double u = s.u[IX_MK(t, m, k)];
+      const int cnt = s.vcnt[IX_SM(t, m)];
+      int q = -1, pos = 0;
+      for (int a = 0; a < cnt; ++a) {
+        const int ka = s.vuser[IX_ML(t, m, a)];
+        const double ua = s.vu[IX_ML(t, m, a)];
+        if (ka == k) q = a;
+        if (ua < u || (ua == u && ka < k)) ++pos;
       }
-      if (pt > 0.0) H = wmu * log2_1p(pt / ainv) - c * pt;
+      const double Sb = s.vpre[IX_ML1(t, m, q >= 0 ? q : pos)];
+      const double pin = s.vT[IX_ML1(t, m, q >= 0 ? q + 1 : pos)];
+      const double c = (el ? pc.E * s.eta[m] : 0.0) + s.xi[m] + pin + s.pinter[IX_SM(t, m)] + s.psic[IX_SM(t, m)];
+      double H = 0.0;
+      if (wmu > 0.0) {
+        const double ainv = u + Sb;
+        double pt;
+        if (c <= 0.0) {
+          pt = s.pmask[m];
+        } else {
+          const double Wl = wmu / (c * kLn2);
+          pt = fmin(fmax(Wl - ainv, 0.0), s.pmask[m]);
+        }
+        if (pt > 0.0) H = wmu * log2_1p(pt / ainv) - c * pt;
+      }
+      Hsum += H;
+      if (own) {
+        s.Hc[IX_SK(t, k)] = H;
+        s.pic[IX_SK(t, k)] = pin;
+      }
     }
-    s.Sacc[i] += H;
-    if (s.Al[k] == m) {
-      s.Hc[k] = H;
-      s.pic[k] = pin;
-    }
+    s.Sacc[i] += Hsum;
   }
   __syncthreads();
 
-  // 7. selection, closed-form powers, C14 multipliers follow their pairs
-  for (int m = tid; m < M; m += nth) {
-    const int cnt = s.vcnt[m];
-    const bool frozen = sc.churn > 0 && s.churn[m] >= sc.churn;
-    int chosen[kMaxL], np = 0;
-    if (frozen) {
-      for (int t = 0; t < cnt; ++t)
-        if (s.Al[s.vuser[m * L + t]] == m) chosen[np++] = s.vuser[m * L + t];
+  // 7. selection: the l best of RRH m's users with H > 0 (H desc, user asc),
+  //    by each candidate's rank within its group
+  for (int i = tid; i < ns * K; i += nth) {
+    const int t = i / K, k = i - t * K;
+    const int m = s.Al[k];
+    if (m < 0 || s.frozen[IX_SM(t, m)]) continue;
+    const double h = s.Hc[i];
+    if (!(h > 0.0)) continue;
+    int rank = 0;
+    for (int e = s.grp_off[m]; e < s.grp_off[m + 1]; ++e) {
+      const int j = s.grp[e];
+      const double hj = s.Hc[IX_SK(t, j)];
+      rank += (hj > h) || (hj == h && j < k);
+    }
+    if (rank < L) s.chosen[IX_ML(t, m, rank)] = k;
+  }
+  __syncthreads();
+  for (int i = tid; i < ns * M; i += nth) {
+    const int t = i / M, m = i - t * M;
+    const int cnt = s.vcnt[i];
+    int np = 0;
+    if (s.frozen[i]) {  // churn cap reached: keep the incumbents still associated with m
+      for (int a = 0; a < cnt; ++a)
+        if (s.Al[s.vuser[IX_ML(t, m, a)]] == m) s.chosen[IX_ML(t, m, np++)] = s.vuser[IX_ML(t, m, a)];
     } else {
-      double bh[kMaxL];
-      for (int e = s.grp_off[m]; e < s.grp_off[m + 1]; ++e) {
-        const int k = s.grp[e];
-        const double h = s.Hc[k];
-        if (!(h > 0.0)) continue;
-        int t = np < L ? np : L;
-        while (t > 0 && (bh[t - 1] < h || (bh[t - 1] == h && chosen[t - 1] > k))) {
-          if (t < L) {
-            bh[t] = bh[t - 1];
-            chosen[t] = chosen[t - 1];
-          }
-          --t;
-        }
-        if (t < L) {
-          bh[t] = h;
-          chosen[t] = k;
-          if (np < L) ++np;
-        }
-      }
+      while (np < L && s.chosen[IX_ML(t, m, np)] >= 0) ++np;
       bool same = (np == cnt);
       for (int a = 0; a < np && same; ++a) {
         bool f = false;
-        for (int t = 0; t < cnt; ++t) f = f || (s.vuser[m * L + t] == chosen[a]);
+        for (int b = 0; b < cnt; ++b) f = f || (s.vuser[IX_ML(t, m, b)] == s.chosen[IX_ML(t, m, a)]);
         same = f;
       }
-      if (!same) s.churn[m]++;
+      if (!same) s.churn[i]++;
     }
-    const double pplus = fmax(s.psic[m], 0.0), pminus = fmax(-s.psic[m], 0.0);
-    double dm = s.dmax[m];
-    int nu_[kMaxL];
-    double np_[kMaxL], na_[kMaxL], nb_[kMaxL];
-    int oldslot[kMaxL];
-    for (int a = 0; a < np; ++a) {
-      const int k = chosen[a];
-      int old = -1;
-      for (int t = 0; t < cnt; ++t)
-        if (s.vuser[m * L + t] == k) old = s.vslot[m * L + t];
-      double p_old = 0.0, alph = 1.0, bet = 0.0;
-      if (old >= 0) {
-        p_old = s.sp[m * L + old];
-        alph = s.sal[m * L + old];
-        bet = s.sbe[m * L + old];
-      }
-      const double wmu = (d.w ? d.w[(size_t)m * K + k] : 1.0) * s.mu[k];
-      const double cp = (d.elastic[k] ? pc.E * d.eta[m] : 0.0) + s.xi[m] + s.pic[k] + s.pinter[m] + pplus;
-      const double num = wmu * alph / kLn2 + p_old * pminus;
-      double pn = (cp > 0.0) ? fmin(fmax(num / cp, 0.0), d.pmask[m]) : d.pmask[m];
-      if (pn < kPowerFloorRel * d.pmask[m]) pn = 0.0;
-      nu_[a] = k;
-      np_[a] = pn;
-      na_[a] = alph;
-      nb_[a] = bet;
-      oldslot[a] = old;
-      dm = fmax(dm, fabs(pn - p_old) / d.pmask[m]);
-    }
-    for (int t = 0; t < cnt; ++t) {
-      bool kept = false;
-      for (int a = 0; a < np; ++a) kept = kept || (nu_[a] == s.vuser[m * L + t]);
-      if (!kept) dm = fmax(dm, s.sp[m * L + s.vslot[m * L + t]] / d.pmask[m]);
-    }
-    s.dmax[m] = dm;
-    const size_t base = ((size_t)m * N + n) * L;
-    for (int a = 0; a < L; ++a) {
-      d.sel[base + a] = a < np ? nu_[a] : -1;
-      d.p[base + a] = a < np ? np_[a] : 0.0;
-      d.al[base + a] = a < np ? na_[a] : 1.0;
-      d.be[base + a] = a < np ? nb_[a] : 0.0;
-      for (int b = 0; b < L; ++b) {
-        double z = 0.0;
-        if (a < np && b < np && a != b && oldslot[a] >= 0 && oldslot[b] >= 0)
-          z = s.szn[m * L * L + oldslot[a] * L + oldslot[b]];
-        d.zs[(base + a) * L + b] = z;
-      }
-    }
-    d.churn_sel[(size_t)m * N + n] = s.churn[m];
+    s.np[i] = np;
+    d.churn_sel[(size_t)m * N + NOF(t)] = s.churn[i];
   }
   __syncthreads();
+  // closed-form powers of the new selection
+  for (int i = tid; i < ns * M * L; i += nth) {
+    const int t = i / (M * L), r = i - t * M * L, m = r / L, a = r - m * L;
+    const int cnt = s.vcnt[IX_SM(t, m)], np = s.np[IX_SM(t, m)];
+    double dm = 0.0;
+    int k = -1, old = -1;
+    double pn = 0.0, alph = 1.0, bet = 0.0;
+    if (a < np) {
+      k = s.chosen[i];
+      double p_old = 0.0;
+      for (int b = 0; b < cnt; ++b)
+        if (s.vuser[IX_ML(t, m, b)] == k) old = s.vslot[IX_ML(t, m, b)];
+      if (old >= 0) {
+        p_old = s.sp[IX_ML(t, m, old)];
+        alph = s.sal[IX_ML(t, m, old)];
+        bet = s.sbe[IX_ML(t, m, old)];
+      }
+      const double wmu = (d.w ? d.w[(size_t)m * K + k] : 1.0) * s.mu[k];
+      const double ps = s.psic[IX_SM(t, m)];
+      const double pplus = fmax(ps, 0.0), pminus = fmax(-ps, 0.0);
+      const double cp = (s.el[k] ? pc.E * s.eta[m] : 0.0) + s.xi[m] + s.pic[IX_SK(t, k)] +
+                        s.pinter[IX_SM(t, m)] + pplus;
+      const double num = wmu * alph / kLn2 + p_old * pminus;
+      pn = (cp > 0.0) ? fmin(fmax(num / cp, 0.0), s.pmask[m]) : s.pmask[m];
+      if (pn < kPowerFloorRel * s.pmask[m]) pn = 0.0;
+      dm = fabs(pn - p_old) / s.pmask[m];
+    }
+    if (a < cnt) {  // an incumbent that leaves the selection
+      const int kt = s.vuser[IX_ML(t, m, a)];
+      bool kept = false;
+      for (int b = 0; b < np; ++b) kept = kept || (s.chosen[IX_ML(t, m, b)] == kt);
+      if (!kept) dm = fmax(dm, s.sp[IX_ML(t, m, s.vslot[IX_ML(t, m, a)])] / s.pmask[m]);
+    }
+    s.nold[i] = old;
+    s.dmi[i] = dm;
+    const size_t gi = ((size_t)m * N + NOF(t)) * L + a;
+    d.sel[gi] = k;
+    d.p[gi] = pn;
+    d.al[gi] = alph;
+    d.be[gi] = bet;
+  }
+  __syncthreads();
+  // C14 multipliers follow their user pair into the new slots
+  for (int i = tid; i < ns * M * L * L; i += nth) {
+    const int t = i / (M * L * L), r = i - t * M * L * L, m = r / (L * L), a = (r / L) % L, b = r % L;
+    const int np = s.np[IX_SM(t, m)];
+    double z = 0.0;
+    if (a < np && b < np && a != b && s.nold[IX_ML(t, m, a)] >= 0 && s.nold[IX_ML(t, m, b)] >= 0)
+      z = s.szn[IX_MLL(t, m, s.nold[IX_ML(t, m, a)], s.nold[IX_ML(t, m, b)])];
+    d.zs[(((size_t)m * N + NOF(t)) * L + a) * L + b] = z;
+  }
+  for (int m = tid; m < M; m += nth) {
+    double dm = s.dmax[m];
+    for (int t = 0; t < ns; ++t)
+      for (int a = 0; a < L; ++a) dm = fmax(dm, s.dmi[IX_ML(t, m, a)]);
+    s.dmax[m] = dm;
+  }
+  __syncthreads();
+#undef NOF
 }
 
 // Per-workgroup partials after its subcarriers.
@@ -728,10 +838,9 @@ __device__ void reduce_pass(const Drop& d, const Sched& sc, const Ctrl& c, Lds& 
 
 // Loop control, identical in every workgroup (mirrors the Dinkelbach and
 // dual-loop stopping rules).
-__device__ void control(const Drop& d, const Sched& sc, Ctrl& c, int G) {
-  const double R = load_shared(&d.red[0]), P = load_shared(&d.red[1]), dm = load_shared(&d.red[2]);
+// One step of the loop control from the reduced values of the pass just done.
+__device__ void advance(const Sched& sc, Ctrl& c, double R, double P, double dm, int changes) {
   if (c.mode == kSweep) {
-    const int changes = load_shared(&d.chg_count[c.pass & 1]);
     c.v += 1;
     c.total += 1;
     c.reset = 0;
@@ -762,11 +871,21 @@ __device__ void control(const Drop& d, const Sched& sc, Ctrl& c, int G) {
       c.mode = kSweep;
     }
   }
+  c.pass += 1;
+}
+
+// Loop control of the grid solver, identical in every workgroup: the reduced
+// values are read with device-scope atomics after the grid barrier.
+__device__ void control(const Drop& d, const Sched& sc, Ctrl& c) {
+  const double R = load_shared(&d.red[0]), P = load_shared(&d.red[1]), dm = load_shared(&d.red[2]);
+  const int changes = c.mode == kSweep ? load_shared(&d.chg_count[c.pass & 1]) : 0;
+  advance(sc, c, R, P, dm, changes);
 }
 
 __global__ void __launch_bounds__(kBlock) solve_kernel(Drop d, Sched sc) {
   extern __shared__ __align__(16) char smem[];
-  Lds s = carve(smem, d.M, d.K, d.L);
+  Lds s;
+  carve_lds(smem, d.M, d.K, d.L, sc.tile, &s);
   cg::grid_group grid = cg::this_grid();
   const int b = blockIdx.x, G = gridDim.x;
   Ctrl c = *d.ctrl;
@@ -780,14 +899,189 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(Drop d, Sched sc) {
     pc.update = update;
     pc.write_out = !update;
     begin_pass(d, s);
-    for (int n = b; n < d.N; n += G) subcarrier(d, sc, pc, s, n);
+    const int nb = (d.N - b + G - 1) / G;  // my subcarriers: b, b+G, ...
+    for (int j = 0; j < nb; j += sc.tile) tile(d, sc, pc, s, b + j * G, G, min(sc.tile, nb - j));
     write_partials(d, s, b);
     grid.sync();
     reduce_pass(d, sc, c, s, b, G, update, pc.delta_v);
     grid.sync();
-    control(d, sc, c, G);
-    c.pass += 1;
+    control(d, sc, c);
     if (b == 0 && threadIdx.x == 0) *d.ctrl = c;
+  }
+}
+
+// ---------------------------------------------------------- batched solver
+
+// Cold start of one drop inside a workgroup (same rules as the grid solver's
+// initial-point kernels): association by the summed log2(1 + Gamma pmask /
+// sigma) over n in increasing n, the l strongest users of each (m,n),
+// p = pmax/(N l).
+__device__ void block_cold_start(const Drop& d, Lds& s) {
+  const int M = d.M, N = d.N, K = d.K, L = d.L, tid = threadIdx.x, nth = blockDim.x;
+  for (int i = tid; i < M * K; i += nth) {
+    const int m = i / K, k = i - m * K;
+    double acc = 0.0;
+    for (int n = 0; n < N; ++n)
+      acc += log2_1p((double)d.G[((size_t)m * N + n) * K + k] * d.pmask[m] / d.sigma);
+    s.Sacc[i] = acc;
+  }
+  __syncthreads();
+  for (int k = tid; k < K; k += nth) {
+    int best = 0;
+    double bv = -1.0;
+    for (int m = 0; m < M; ++m)
+      if (s.Sacc[m * K + k] > bv) {
+        bv = s.Sacc[m * K + k];
+        best = m;
+      }
+    d.A[k] = best;
+    d.churn_A[k] = 0;
+    d.zeta[k] = d.elastic[k] ? 0.0 : 1.0;
+  }
+  for (int m = tid; m < M; m += nth) d.xi[m] = 0.0;
+  __syncthreads();
+  for (int i = tid; i < M * N; i += nth) {
+    const int m = i / N, n = i - m * N;
+    int bk[kMaxL];
+    double bv[kMaxL];
+    int cnt = 0;
+    for (int k = 0; k < K; ++k) {
+      if (d.A[k] != m) continue;
+      const double v = d.G[((size_t)m * N + n) * K + k];
+      int t = cnt < L ? cnt : L;
+      while (t > 0 && (bv[t - 1] < v || (bv[t - 1] == v && bk[t - 1] > k))) {
+        if (t < L) {
+          bv[t] = bv[t - 1];
+          bk[t] = bk[t - 1];
+        }
+        --t;
+      }
+      if (t < L) {
+        bv[t] = v;
+        bk[t] = k;
+        if (cnt < L) ++cnt;
+      }
+    }
+    const size_t base = ((size_t)m * N + n) * L;
+    for (int a = 0; a < L; ++a) {
+      d.sel[base + a] = a < cnt ? bk[a] : -1;
+      d.p[base + a] = a < cnt ? d.pmax[m] / ((double)N * L) : 0.0;
+      d.al[base + a] = 1.0;
+      d.be[base + a] = 0.0;
+      for (int b = 0; b < L; ++b) d.zs[(base + a) * L + b] = 0.0;
+    }
+    d.churn_sel[i] = 0;
+  }
+  __syncthreads();
+}
+
+// Reductions and multiplier steps of one pass from the workgroup's own
+// accumulators (it holds every subcarrier of the drop).
+__device__ void block_reduce(const Drop& d, const Sched& sc, const Ctrl& c, Lds& s, bool update,
+                             double delta_v, int* changes) {
+  const int M = d.M, K = d.K, tid = threadIdx.x, nth = blockDim.x;
+  for (int k = tid; k < K; k += nth) {
+    d.user_rate[k] = s.racc[k];
+    if (!update) continue;
+    double best = -INFINITY;
+    int bm = 0;
+    for (int m = 0; m < M; ++m)
+      if (s.Sacc[m * K + k] > best) {
+        best = s.Sacc[m * K + k];
+        bm = m;
+      }
+    int ch_A = c.reset ? 0 : d.churn_A[k];
+    const int before = d.A[k];
+    if (!(sc.churn > 0 && ch_A >= sc.churn)) {
+      int after = before;
+      if (best > 0.0)
+        after = bm;
+      else if (d.elastic[k])
+        after = -1;
+      if (after != before) {
+        d.A[k] = after;
+        ++ch_A;
+        atomicAdd(changes, 1);
+      }
+    }
+    d.churn_A[k] = ch_A;
+    if (!d.elastic[k]) {
+      const double viol = fmin(fmax((d.psi[k] - s.rhacc[k]) / d.psi[k], -1.0), 1.0);
+      d.zeta[k] = fmax(d.zeta[k] + delta_v * viol, 0.0);
+    }
+  }
+  if (update)
+    for (int m = tid; m < M; m += nth) {
+      const double ps = s.psacc[m];
+      const double scale = (double)d.N * d.L / (kLn2 * d.pmax[m]);
+      d.xi[m] = fmax(d.xi[m] + delta_v * scale * (ps - d.pmax[m]) / d.pmax[m], 0.0);
+    }
+  __syncthreads();
+}
+
+// Persistent batched solver: workgroups take drops from an atomic queue (in
+// the host's order: largest estimated work first) and solve each completely.
+__global__ void __launch_bounds__(kBlock) batch_kernel(const Drop* drops, const int* order, int B,
+                                                      Sched sc, int* queue, Ctrl* ctrls) {
+  extern __shared__ __align__(16) char smem[];
+  __shared__ int s_idx, s_changes;
+  __shared__ Ctrl s_c;
+  for (;;) {
+    if (threadIdx.x == 0) s_idx = atomicAdd(queue, 1);
+    __syncthreads();
+    const int idx = s_idx;
+    __syncthreads();
+    if (idx >= B) break;
+    const Drop& d = drops[order[idx]];
+    Sched sd = sc;
+    sd.tile = d.tile;
+    Lds s;
+    carve_lds(smem, d.M, d.K, d.L, sd.tile, &s);
+    if (!d.preset) block_cold_start(d, s);
+    if (threadIdx.x == 0) {
+      Ctrl c0;
+      c0.E = 0.0;
+      c0.R = 0.0;
+      c0.P = d.pstatic;
+      c0.i = 0;
+      c0.v = 0;
+      c0.mode = d.start_eval ? kEval : kSweep;
+      c0.total = 0;
+      c0.reset = 1;
+      c0.pass = 0;
+      c0.flags = 0;
+      s_c = c0;
+    }
+    __syncthreads();
+    while (s_c.mode != kDone) {
+      const Ctrl c = s_c;
+      const bool update = c.mode == kSweep;
+      PassConst pc;
+      pc.E = c.E;
+      pc.delta_v = sd.step0 / sqrt(1.0 + (double)c.v);
+      pc.refit = update && sd.refit_period > 0 && (c.v % sd.refit_period) == 0;
+      pc.reset = update && c.reset;
+      pc.update = update;
+      pc.write_out = !update;
+      if (threadIdx.x == 0) s_changes = 0;
+      begin_pass(d, s);
+      for (int n0 = 0; n0 < d.N; n0 += sd.tile) tile(d, sd, pc, s, n0, 1, min(sd.tile, d.N - n0));
+      block_reduce(d, sd, c, s, update, pc.delta_v, &s_changes);
+      if (threadIdx.x == 0) {
+        double R = 0.0, P = d.pstatic, dm = 0.0;
+        for (int m = 0; m < d.M; ++m) {
+          R += s.Racc[m];
+          P += d.eta[m] * s.peacc[m];
+          dm = fmax(dm, s.dmax[m]);
+        }
+        Ctrl cn = c;
+        advance(sd, cn, R, P, dm, s_changes);
+        s_c = cn;
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) ctrls[order[idx]] = s_c;
+    __syncthreads();
   }
 }
 
@@ -887,6 +1181,14 @@ __global__ void p0_sum_kernel(Drop d, const double* p0, double* out) {
   out[i] = acc;
 }
 
+// Initial multipliers: xi' = max(xi0, 0) (0 without xi0); zeta' = max(zeta0, 0)
+// for streaming users (1 without zeta0), 0 for elastic users.
+__global__ void init_mult_kernel(Drop d, const double* xi0, const double* zeta0) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < d.M) d.xi[i] = xi0 ? fmax(xi0[i], 0.0) : 0.0;
+  if (i < d.K) d.zeta[i] = d.elastic[i] ? 0.0 : (zeta0 ? fmax(zeta0[i], 0.0) : 1.0);
+}
+
 // Dense [M][N][K] powers from the decoding-order slots.
 __global__ void dense_kernel(Drop d, float* out) {
   const size_t total = (size_t)d.M * d.N * d.K;
@@ -909,18 +1211,6 @@ __global__ void scatter_kernel(Drop d, float* out) {
 
 // ==================================================================== host
 
-struct alloc_ctx {
-  int device;
-  hipStream_t stream;
-  char* ws;         // device workspace
-  size_t ws_bytes;
-  int cus;
-  size_t lds_max;
-  int timing;
-  hipEvent_t ev0, ev1;
-  double last_ms;
-};
-
 namespace {
 
 // Minimum rate (Sec. II-B, C9): Psi = lambda zbar / (B_n (1 - 1/(x + sqrt(1+x^2)))),
@@ -938,7 +1228,8 @@ int validate(const alloc_problem* pb, const alloc_params* prm) {
   if (!(pb->noise_w > 0) || !(pb->bw_hz > 0) || !(pb->packet_bits > 0)) return ALLOC_EINVAL;
   if (!std::isfinite(pb->noise_w)) return ALLOC_EINVAL;
   if (pb->M > kMaxM || pb->l > kMaxL || pb->K > kMaxK || pb->M * pb->K > kMaxMK) return ALLOC_ETOOBIG;
-  if (prm->sweeps_per_dinkelbach < 1 || prm->max_dinkelbach < 1 || prm->max_groups < 0) return ALLOC_EINVAL;
+  if (prm->sweeps_per_dinkelbach < 1 || prm->max_dinkelbach < 1 || prm->max_groups < 0 || prm->tile < 0)
+    return ALLOC_EINVAL;
   for (int m = 0; m < pb->M; ++m) {
     if (!(pb->pmax_w[m] > 0) || !std::isfinite(pb->pmax_w[m])) return ALLOC_EINVAL;
     if (!(pb->eta[m] > 0) || !std::isfinite(pb->eta[m])) return ALLOC_EINVAL;
@@ -985,6 +1276,7 @@ void alloc_params_default(alloc_params* p) {
   p->step0 = 0.1;
   p->flags = 0;
   p->max_groups = 0;
+  p->tile = 0;
 }
 
 int alloc_ctx_set_timing(alloc_ctx* ctx, int enable) {
@@ -1042,14 +1334,18 @@ void alloc_ctx_destroy(alloc_ctx* c) {
   delete c;
 }
 
-int alloc_solve(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm,
-                const alloc_warm* warm, alloc_result* res) {
+}  // extern "C"
+
+namespace alloc_internal {
+
+int solve_one(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, const alloc_warm* warm,
+              const DevWarm* dev, alloc_result* res) {
   if (!ctx || !res) return ALLOC_EINVAL;
+  if (warm && dev) return ALLOC_EINVAL;
   int rc = validate(pb, prm);
   if (rc != ALLOC_OK) return rc;
   const int M = pb->M, N = pb->N, K = pb->K, L = pb->l, NP = L * (L - 1) / 2;
-  const size_t lds = lds_bytes(M, K, L);
-  if (lds > ctx->lds_max) return ALLOC_ETOOBIG;
+  if (carve_lds(nullptr, M, K, L, 1, nullptr) > ctx->lds_max) return ALLOC_ETOOBIG;
   if (hipSetDevice(ctx->device) != hipSuccess) return ALLOC_EDEVICE;
   const bool gain_dev = prm->flags & ALLOC_GAIN_ON_DEVICE;
   const bool out_dev = prm->flags & ALLOC_OUT_ON_DEVICE;
@@ -1059,14 +1355,20 @@ int alloc_solve(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm
       if (!(pb->gain[i] > 0.0f) || !std::isfinite(pb->gain[i])) return ALLOC_EINVAL;
   }
 
-  // grid: one workgroup per subcarrier up to what can be co-resident
+  // grid: up to one workgroup per CU (the LDS tile fills a CU), at most one
+  // per subcarrier; the tile is as many of a workgroup's subcarriers as fit
+  int G = std::min(N, ctx->cus);
+  if (prm->max_groups > 0) G = std::min(G, prm->max_groups);
+  const int nb = (N + G - 1) / G;
+  int T = prm->tile > 0 ? std::min(prm->tile, nb) : nb;
+  while (T > 1 && carve_lds(nullptr, M, K, L, T, nullptr) > ctx->lds_max) --T;
+  const size_t lds = carve_lds(nullptr, M, K, L, T, nullptr);
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)solve_kernel, kBlock, lds) !=
       hipSuccess)
     return ALLOC_EDEVICE;
   if (per_cu < 1) return ALLOC_ETOOBIG;
-  int G = std::min(N, per_cu * ctx->cus);
-  if (prm->max_groups > 0) G = std::min(G, prm->max_groups);
+  G = std::min(G, per_cu * ctx->cus);
 
   // host-side constants (FP64)
   std::vector<double> psi(K, 0.0), pmask(M), w;
@@ -1114,8 +1416,12 @@ int alloc_solve(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm
   const size_t oOz = lay.add(sizeof(double) * (size_t)M * N * (NP > 0 ? NP : 1));
   const size_t oCtrl = lay.add(sizeof(Ctrl));
   const size_t oSnr = lay.add(sizeof(double) * M * K);
-  const size_t oP0 = lay.add(warm && warm->p0 ? sizeof(double) * n3 : 0);
-  const size_t oP0s = lay.add(warm && warm->p0 ? sizeof(double) * M * K : 0);
+  const bool h_p0 = warm && warm->p0, h_xi = warm && warm->xi0, h_z = warm && warm->zeta0;
+  const bool has_p0 = h_p0 || (dev && dev->p0);
+  const size_t oP0 = lay.add(h_p0 ? sizeof(double) * n3 : 0);
+  const size_t oP0s = lay.add(has_p0 ? sizeof(double) * M * K : 0);
+  const size_t oXi0 = lay.add(h_xi ? sizeof(double) * M : 0);
+  const size_t oZ0 = lay.add(h_z ? sizeof(double) * K : 0);
   if (lay.total > ctx->ws_bytes) {
     if (ctx->ws) (void)hipFree(ctx->ws);
     ctx->ws = nullptr;
@@ -1134,10 +1440,13 @@ int alloc_solve(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm
        h2d(oPmax, pb->pmax_w, sizeof(double) * M) && h2d(oEta, pb->eta, sizeof(double) * M) &&
        h2d(oPmask, pmask.data(), sizeof(double) * M);
   if (pb->weight) ok = ok && h2d(oW, pb->weight, sizeof(double) * M * K);
-  if (warm && warm->p0) ok = ok && h2d(oP0, warm->p0, sizeof(double) * n3);
+  if (h_p0) ok = ok && h2d(oP0, warm->p0, sizeof(double) * n3);
+  if (h_xi) ok = ok && h2d(oXi0, warm->xi0, sizeof(double) * M);
+  if (h_z) ok = ok && h2d(oZ0, warm->zeta0, sizeof(double) * K);
   Ctrl c0;
   memset(&c0, 0, sizeof c0);
-  c0.mode = kSweep;
+  // a warm initial allocation is Dinkelbach's p^0: evaluate it first
+  c0.mode = has_p0 ? kEval : kSweep;
   c0.reset = 1;
   ok = ok && h2d(oCtrl, &c0, sizeof c0);
   static const int zeros2[2] = {0, 0};
@@ -1145,6 +1454,7 @@ int alloc_solve(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm
   if (!ok) return ALLOC_EDEVICE;
 
   Drop d;
+  memset(&d, 0, sizeof d);
   d.M = M; d.N = N; d.K = K; d.L = L; d.NP = NP;
   d.G = gain_dev ? pb->gain : (const float*)(ws + oG);
   d.psi = (const double*)(ws + oPsi);
@@ -1181,8 +1491,9 @@ int alloc_solve(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm
   d.ctrl = (Ctrl*)(ws + oCtrl);
 
   // initial point
-  if (hipMemsetAsync(d.xi, 0, sizeof(double) * M, st) != hipSuccess) return ALLOC_EDEVICE;
-  const double* p0 = (warm && warm->p0) ? (const double*)(ws + oP0) : nullptr;
+  const double* p0 = h_p0 ? (const double*)(ws + oP0) : (dev ? dev->p0 : nullptr);
+  const double* xi0 = h_xi ? (const double*)(ws + oXi0) : (dev ? dev->xi0 : nullptr);
+  const double* zeta0 = h_z ? (const double*)(ws + oZ0) : (dev ? dev->zeta0 : nullptr);
   double* p0s = p0 ? (double*)(ws + oP0s) : nullptr;
   const int tb = 256;
   hipLaunchKernelGGL(cold_assoc_kernel, dim3((M * K + tb - 1) / tb), dim3(tb), 0, st, d,
@@ -1191,16 +1502,8 @@ int alloc_solve(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm
   hipLaunchKernelGGL(cold_pick_kernel, dim3((K + tb - 1) / tb), dim3(tb), 0, st, d,
                      (const double*)(ws + oSnr), (const double*)p0s);
   hipLaunchKernelGGL(cold_select_kernel, dim3((M * N + tb - 1) / tb), dim3(tb), 0, st, d, p0);
-  if (warm && (warm->xi0 || warm->zeta0)) {
-    std::vector<double> xi0(M, 0.0), z0(K, 0.0);
-    if (warm->xi0)
-      for (int m = 0; m < M; ++m) xi0[m] = std::max(warm->xi0[m], 0.0);
-    if (warm->xi0 && !h2d(oXi, xi0.data(), sizeof(double) * M)) return ALLOC_EDEVICE;
-    if (warm->zeta0) {
-      for (int k = 0; k < K; ++k) z0[k] = el[k] ? 0.0 : std::max(warm->zeta0[k], 0.0);
-      if (!h2d(oZeta, z0.data(), sizeof(double) * K)) return ALLOC_EDEVICE;
-    }
-  }
+  hipLaunchKernelGGL(init_mult_kernel, dim3((std::max(M, K) + tb - 1) / tb), dim3(tb), 0, st, d, xi0,
+                     zeta0);
   if (hipGetLastError() != hipSuccess) return ALLOC_EDEVICE;
 
   Sched sc;
@@ -1212,6 +1515,7 @@ int alloc_solve(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm
   sc.tol_d = prm->tol_dinkelbach;
   sc.tol_dual = prm->tol_dual;
   sc.step0 = prm->step0;
+  sc.tile = T;
   void* args[] = {(void*)&d, (void*)&sc};
   if (ctx->timing && hipEventRecord(ctx->ev0, st) != hipSuccess) return ALLOC_EDEVICE;
   if (hipLaunchCooperativeKernel((const void*)solve_kernel, dim3(G), dim3(kBlock), args, lds, st) !=
@@ -1269,6 +1573,323 @@ int alloc_solve(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm
   res->sweeps = cf.total;
   res->status_flags = flags;
   return ALLOC_OK;
+}
+
+int solve_batch(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc_params* prm,
+                const alloc_warm* warms, const WarmFn* fn, alloc_result* results) {
+  if (!ctx || !probs || !results || B < 1 || !prm) return ALLOC_EINVAL;
+  if (warms && fn) return ALLOC_EINVAL;
+  if (prm->flags & ALLOC_OUT_ON_DEVICE) return ALLOC_EINVAL;
+  const bool gain_dev = prm->flags & ALLOC_GAIN_ON_DEVICE;
+  for (int b = 0; b < B; ++b) {
+    const int rc = validate(&probs[b], prm);
+    if (rc != ALLOC_OK) return rc;
+    if (!gain_dev) {
+      const alloc_problem& pb = probs[b];
+      const size_t n3 = (size_t)pb.M * pb.N * pb.K;
+      for (size_t i = 0; i < n3; ++i)
+        if (!(pb.gain[i] > 0.0f) || !std::isfinite(pb.gain[i])) return ALLOC_EINVAL;
+    }
+  }
+  if (hipSetDevice(ctx->device) != hipSuccess) return ALLOC_EDEVICE;
+  const size_t budget = ctx->lds_max - 1024;  // the kernel's static LDS stays below 1 KB
+  for (int b = 0; b < B; ++b)
+    if (carve_lds(nullptr, probs[b].M, probs[b].K, probs[b].l, 1, nullptr) > budget) return ALLOC_ETOOBIG;
+
+  // workspace: per drop inputs, state and outputs, packed
+  struct Off {
+    size_t G, psi, el, pmax, eta, pmask, w, A, sel, p, al, be, zs, xi, zeta, chs, cha, ur, os, op, oz;
+  };
+  std::vector<Off> off(B);
+  size_t tot = 0;
+  auto add = [&](size_t bytes) {
+    const size_t o = tot;
+    tot += (bytes + 255) & ~size_t(255);
+    return o;
+  };
+  const size_t oDrops = add(sizeof(Drop) * B);
+  const size_t oOrder = add(sizeof(int) * B);
+  const size_t oQueue = add(sizeof(int));
+  const size_t oCtrls = add(sizeof(Ctrl) * B);
+  const size_t small_begin = tot;
+  for (int b = 0; b < B; ++b) {
+    const alloc_problem& pb = probs[b];
+    const size_t M = pb.M, K = pb.K;
+    off[b].psi = add(sizeof(double) * K);
+    off[b].el = add(K);
+    off[b].pmax = add(sizeof(double) * M);
+    off[b].eta = add(sizeof(double) * M);
+    off[b].pmask = add(sizeof(double) * M);
+    off[b].w = add(pb.weight ? sizeof(double) * M * K : 0);
+  }
+  const size_t small_end = tot;
+  const size_t out_begin = tot;
+  for (int b = 0; b < B; ++b) {
+    const alloc_problem& pb = probs[b];
+    const size_t M = pb.M, N = pb.N, K = pb.K, L = pb.l, NP = L * (L - 1) / 2;
+    off[b].os = add(sizeof(int) * M * N * L);
+    off[b].op = add(sizeof(double) * M * N * L);
+    off[b].oz = add(sizeof(double) * M * N * (NP > 0 ? NP : 1));
+    off[b].A = add(sizeof(int) * K);
+    off[b].xi = add(sizeof(double) * M);
+    off[b].zeta = add(sizeof(double) * K);
+    off[b].ur = add(sizeof(double) * K);
+  }
+  const size_t out_end = tot;
+  // scratch of the warm-start initialisation, reused drop after drop
+  size_t max_mk = 1, max_m = 1, max_k = 1, max_n3 = 0;
+  for (int b = 0; b < B; ++b) {
+    max_mk = std::max(max_mk, (size_t)probs[b].M * probs[b].K);
+    max_m = std::max(max_m, (size_t)probs[b].M);
+    max_k = std::max(max_k, (size_t)probs[b].K);
+    if (warms && warms[b].p0) max_n3 = std::max(max_n3, (size_t)probs[b].M * probs[b].N * probs[b].K);
+  }
+  const bool any_warm = warms || fn;
+  const size_t oISnr = add(any_warm ? sizeof(double) * max_mk : 0);
+  const size_t oIP0s = add(any_warm ? sizeof(double) * max_mk : 0);
+  const size_t oIP0 = add(sizeof(double) * max_n3);
+  const size_t oIXi = add(warms ? sizeof(double) * max_m : 0);
+  const size_t oIZ = add(warms ? sizeof(double) * max_k : 0);
+  for (int b = 0; b < B; ++b) {
+    const alloc_problem& pb = probs[b];
+    const size_t M = pb.M, N = pb.N, K = pb.K, L = pb.l;
+    off[b].sel = add(sizeof(int) * M * N * L);
+    off[b].p = add(sizeof(double) * M * N * L);
+    off[b].al = add(sizeof(double) * M * N * L);
+    off[b].be = add(sizeof(double) * M * N * L);
+    off[b].zs = add(sizeof(double) * M * N * L * L);
+    off[b].chs = add(sizeof(int) * M * N);
+    off[b].cha = add(sizeof(int) * K);
+    off[b].G = add(gain_dev ? 0 : sizeof(float) * M * N * K);
+  }
+  if (tot > ctx->ws_bytes) {
+    if (ctx->ws) (void)hipFree(ctx->ws);
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+    if (hipMalloc((void**)&ctx->ws, tot) != hipSuccess) return ALLOC_ENOMEM;
+    ctx->ws_bytes = tot;
+  }
+  char* ws = ctx->ws;
+  hipStream_t st = ctx->stream;
+
+  // host image of the small inputs and the drop descriptors
+  std::vector<char> img(small_end - small_begin, 0);
+  std::vector<Drop> drops(B);
+  std::vector<double> psi_all;
+  std::vector<std::vector<double>> psis(B);
+  std::vector<std::vector<uint8_t>> els(B);
+  for (int b = 0; b < B; ++b) {
+    const alloc_problem& pb = probs[b];
+    const int M = pb.M, N = pb.N, K = pb.K, L = pb.l;
+    double* psi = (double*)(img.data() + off[b].psi - small_begin);
+    uint8_t* el = (uint8_t*)(img.data() + off[b].el - small_begin);
+    psis[b].assign(K, 0.0);
+    els[b].assign(K, 0);
+    for (int k = 0; k < K; ++k) {
+      el[k] = pb.user_type[k] == 0;
+      psi[k] = el[k] ? 0.0 : min_rate(pb.arrival_bps[k], pb.delay_s[k], pb.packet_bits, pb.bw_hz);
+      psis[b][k] = psi[k];
+      els[b][k] = el[k];
+    }
+    memcpy(img.data() + off[b].pmax - small_begin, pb.pmax_w, sizeof(double) * M);
+    memcpy(img.data() + off[b].eta - small_begin, pb.eta, sizeof(double) * M);
+    double* pm = (double*)(img.data() + off[b].pmask - small_begin);
+    for (int m = 0; m < M; ++m) pm[m] = pb.pmask_w ? pb.pmask_w[m] : pb.pmax_w[m] / N;
+    if (pb.weight) memcpy(img.data() + off[b].w - small_begin, pb.weight, sizeof(double) * M * K);
+    Drop& d = drops[b];
+    memset(&d, 0, sizeof d);
+    d.M = M; d.N = N; d.K = K; d.L = L; d.NP = L * (L - 1) / 2;
+    d.G = gain_dev ? pb.gain : (const float*)(ws + off[b].G);
+    d.psi = (const double*)(ws + off[b].psi);
+    d.elastic = (const uint8_t*)(ws + off[b].el);
+    d.pmax = (const double*)(ws + off[b].pmax);
+    d.eta = (const double*)(ws + off[b].eta);
+    d.pmask = (const double*)(ws + off[b].pmask);
+    d.w = pb.weight ? (const double*)(ws + off[b].w) : nullptr;
+    d.sigma = pb.noise_w;
+    d.pstatic = pb.p_fiber_hpn + (M - 1) * pb.p_fiber_lpn + (M - 1) * pb.p_circuit_lpn + pb.p_circuit_hpn;
+    d.A = (int*)(ws + off[b].A);
+    d.sel = (int*)(ws + off[b].sel);
+    d.p = (double*)(ws + off[b].p);
+    d.al = (double*)(ws + off[b].al);
+    d.be = (double*)(ws + off[b].be);
+    d.zs = (double*)(ws + off[b].zs);
+    d.xi = (double*)(ws + off[b].xi);
+    d.zeta = (double*)(ws + off[b].zeta);
+    d.churn_sel = (int*)(ws + off[b].chs);
+    d.churn_A = (int*)(ws + off[b].cha);
+    d.user_rate = (double*)(ws + off[b].ur);
+    d.out_sel = (int*)(ws + off[b].os);
+    d.out_p = (double*)(ws + off[b].op);
+    d.out_zs = (double*)(ws + off[b].oz);
+    int T = prm->tile > 0 ? std::min(prm->tile, N) : N;
+    while (T > 1 && carve_lds(nullptr, M, K, L, T, nullptr) > budget) --T;
+    d.tile = T;
+  }
+  // largest estimated work first
+  std::vector<int> order(B);
+  for (int b = 0; b < B; ++b) order[b] = b;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+    return (double)probs[x].M * probs[x].N * probs[x].K > (double)probs[y].M * probs[y].N * probs[y].K;
+  });
+  bool ok = hipMemcpyAsync(ws + small_begin, img.data(), img.size(), hipMemcpyHostToDevice, st) == hipSuccess;
+  if (!gain_dev)
+    for (int b = 0; b < B && ok; ++b)
+      ok = hipMemcpyAsync(ws + off[b].G, probs[b].gain,
+                          sizeof(float) * probs[b].M * probs[b].N * probs[b].K, hipMemcpyHostToDevice,
+                          st) == hipSuccess;
+  if (!ok) return ALLOC_EDEVICE;
+
+  // warm starts: the initial state of such drops is written here, in order,
+  // with the single-drop initialisation kernels
+  for (int b = 0; b < B && any_warm; ++b) {
+    DevWarm w{nullptr, nullptr, nullptr};
+    if (fn) {
+      const int rc = (*fn)(b, &w);
+      if (rc != ALLOC_OK) return rc;
+    } else {
+      const alloc_problem& pb = probs[b];
+      const size_t n3 = (size_t)pb.M * pb.N * pb.K;
+      auto up = [&](size_t o, const double* src, size_t n) {
+        return hipMemcpyAsync(ws + o, src, sizeof(double) * n, hipMemcpyHostToDevice, st) == hipSuccess;
+      };
+      if (warms[b].p0) {
+        if (!up(oIP0, warms[b].p0, n3)) return ALLOC_EDEVICE;
+        w.p0 = (const double*)(ws + oIP0);
+      }
+      if (warms[b].xi0) {
+        if (!up(oIXi, warms[b].xi0, pb.M)) return ALLOC_EDEVICE;
+        w.xi0 = (const double*)(ws + oIXi);
+      }
+      if (warms[b].zeta0) {
+        if (!up(oIZ, warms[b].zeta0, pb.K)) return ALLOC_EDEVICE;
+        w.zeta0 = (const double*)(ws + oIZ);
+      }
+    }
+    if (!w.p0 && !w.xi0 && !w.zeta0) continue;
+    Drop& d = drops[b];
+    const int tb = 256, M = d.M, N = d.N, K = d.K;
+    double* snr = (double*)(ws + oISnr);
+    double* p0s = w.p0 ? (double*)(ws + oIP0s) : nullptr;
+    hipLaunchKernelGGL(cold_assoc_kernel, dim3((M * K + tb - 1) / tb), dim3(tb), 0, st, d, snr);
+    if (w.p0) hipLaunchKernelGGL(p0_sum_kernel, dim3((M * K + tb - 1) / tb), dim3(tb), 0, st, d, w.p0, p0s);
+    hipLaunchKernelGGL(cold_pick_kernel, dim3((K + tb - 1) / tb), dim3(tb), 0, st, d, (const double*)snr,
+                       (const double*)p0s);
+    hipLaunchKernelGGL(cold_select_kernel, dim3((M * N + tb - 1) / tb), dim3(tb), 0, st, d, w.p0);
+    hipLaunchKernelGGL(init_mult_kernel, dim3((std::max(M, K) + tb - 1) / tb), dim3(tb), 0, st, d, w.xi0,
+                       w.zeta0);
+    if (hipGetLastError() != hipSuccess) return ALLOC_EDEVICE;
+    d.preset = 1;
+    d.start_eval = w.p0 != nullptr;
+  }
+  static const int zero = 0;
+  ok = hipMemcpyAsync(ws + oDrops, drops.data(), sizeof(Drop) * B, hipMemcpyHostToDevice, st) == hipSuccess &&
+       hipMemcpyAsync(ws + oOrder, order.data(), sizeof(int) * B, hipMemcpyHostToDevice, st) == hipSuccess &&
+       hipMemcpyAsync(ws + oQueue, &zero, sizeof(int), hipMemcpyHostToDevice, st) == hipSuccess;
+  if (!ok) return ALLOC_EDEVICE;
+
+  Sched sc;
+  sc.max_d = prm->max_dinkelbach;
+  sc.sweeps = prm->sweeps_per_dinkelbach;
+  sc.refit_period = prm->refit_period;
+  sc.fixed = prm->fixed_count;
+  sc.churn = prm->churn_limit;
+  sc.tol_d = prm->tol_dinkelbach;
+  sc.tol_dual = prm->tol_dual;
+  sc.step0 = prm->step0;
+  sc.tile = 1;
+  int per_cu = 0;
+  if (hipFuncSetAttribute((const void*)batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)budget) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)batch_kernel, kBlock, budget) !=
+          hipSuccess)
+    return ALLOC_EDEVICE;
+  if (per_cu < 1) return ALLOC_ETOOBIG;
+  int grid = std::min(B, per_cu * ctx->cus);
+  if (prm->max_groups > 0) grid = std::min(grid, prm->max_groups);
+  if (ctx->timing && hipEventRecord(ctx->ev0, st) != hipSuccess) return ALLOC_EDEVICE;
+  hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(kBlock), budget, st, (const Drop*)(ws + oDrops),
+                     (const int*)(ws + oOrder), B, sc, (int*)(ws + oQueue), (Ctrl*)(ws + oCtrls));
+  if (hipGetLastError() != hipSuccess) return ALLOC_EDEVICE;
+  if (ctx->timing && hipEventRecord(ctx->ev1, st) != hipSuccess) return ALLOC_EDEVICE;
+
+  // outputs: one copy of the packed region, scattered on the host
+  std::vector<char> out(out_end - out_begin);
+  std::vector<Ctrl> ctrls(B);
+  if (hipMemcpyAsync(out.data(), ws + out_begin, out.size(), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(ctrls.data(), ws + oCtrls, sizeof(Ctrl) * B, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return ALLOC_EDEVICE;
+  ctx->last_ms = -1.0;
+  if (ctx->timing) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1) != hipSuccess) return ALLOC_EDEVICE;
+    ctx->last_ms = ms;
+  }
+  for (int b = 0; b < B; ++b) {
+    const alloc_problem& pb = probs[b];
+    alloc_result& r = results[b];
+    const size_t M = pb.M, N = pb.N, K = pb.K, L = pb.l, NP = L * (L - 1) / 2;
+    auto src = [&](size_t o) { return out.data() + (o - out_begin); };
+    if (r.sel) memcpy(r.sel, src(off[b].os), sizeof(int) * M * N * L);
+    if (r.slot_power) memcpy(r.slot_power, src(off[b].op), sizeof(double) * M * N * L);
+    if (r.zeta_sic && NP > 0) memcpy(r.zeta_sic, src(off[b].oz), sizeof(double) * M * N * NP);
+    if (r.rrh_of_user) memcpy(r.rrh_of_user, src(off[b].A), sizeof(int) * K);
+    if (r.xi) memcpy(r.xi, src(off[b].xi), sizeof(double) * M);
+    if (r.zeta) memcpy(r.zeta, src(off[b].zeta), sizeof(double) * K);
+    const double* ur = (const double*)src(off[b].ur);
+    if (r.user_rate) memcpy(r.user_rate, ur, sizeof(double) * K);
+    if (r.power) {
+      memset(r.power, 0, sizeof(float) * M * N * K);
+      const int* os = (const int*)src(off[b].os);
+      const double* op = (const double*)src(off[b].op);
+      for (size_t i = 0; i < M * N; ++i)
+        for (size_t a = 0; a < L; ++a)
+          if (os[i * L + a] >= 0) r.power[i * K + os[i * L + a]] = (float)op[i * L + a];
+    }
+    const Ctrl& cf = ctrls[b];
+    uint32_t flags = cf.flags;
+    for (size_t k = 0; k < K; ++k) {
+      if (!els[b][k] && ur[k] < psis[b][k] * (1.0 - 1e-6)) flags |= ALLOC_QOS_INFEASIBLE;
+      if (!std::isfinite(ur[k])) flags |= ALLOC_NONFINITE;
+    }
+    r.ee = cf.P > 0.0 ? cf.R / cf.P : 0.0;
+    r.rate_sum = cf.R;
+    r.power_sum = cf.P;
+    r.dinkelbach_iters = cf.i;
+    r.sweeps = cf.total;
+    r.status_flags = flags;
+  }
+  return ALLOC_OK;
+}
+
+}  // namespace alloc_internal
+
+extern "C" {
+
+int alloc_solve(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, const alloc_warm* warm,
+                alloc_result* res) {
+  if (!prm) return ALLOC_EINVAL;
+  if (warm && (prm->flags & ALLOC_WARM_ON_DEVICE)) {
+    const alloc_internal::DevWarm dw{warm->p0, warm->xi0, warm->zeta0};
+    return alloc_internal::solve_one(ctx, pb, prm, nullptr, &dw, res);
+  }
+  return alloc_internal::solve_one(ctx, pb, prm, warm, nullptr, res);
+}
+
+int alloc_solve_batch(alloc_ctx* ctx, int32_t B, const alloc_problem* probs, const alloc_params* prm,
+                      const alloc_warm* warms, alloc_result* results) {
+  if (!prm) return ALLOC_EINVAL;
+  if (warms && (prm->flags & ALLOC_WARM_ON_DEVICE)) {
+    const alloc_internal::WarmFn fn = [warms](int b, alloc_internal::DevWarm* w) {
+      w->p0 = warms[b].p0;
+      w->xi0 = warms[b].xi0;
+      w->zeta0 = warms[b].zeta0;
+      return ALLOC_OK;
+    };
+    return alloc_internal::solve_batch(ctx, B, probs, prm, nullptr, &fn, results);
+  }
+  return alloc_internal::solve_batch(ctx, B, probs, prm, warms, nullptr, results);
 }
 
 }  // extern "C"

@@ -1,0 +1,156 @@
+"""GPU parity of the batched persistent solver (through alloc_solve_batch)."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    import paper_1803_07772_amd as pa
+    assert torch.cuda.is_available()
+    c = pa.Context(0)
+    yield c
+    c.close()
+
+
+def _mixed_batch():
+    """Ragged sizes: small, medium, one subcarrier, one user, l = 1..4."""
+    shapes = [(3, 8, 6, 2, 2), (5, 64, 32, 8, 2), (2, 1, 7, 2, 2), (4, 12, 1, 0, 1),
+              (3, 37, 37, 9, 3), (2, 9, 11, 2, 4), (1, 16, 8, 2, 2), (6, 128, 48, 12, 3),
+              (5, 64, 32, 8, 2), (4, 24, 12, 3, 1), (8, 33, 70, 17, 3), (3, 5, 9, 9, 2)]
+    drops = []
+    for i, (M, N, K, Ks, l) in enumerate(shapes):
+        rc = synth.CFG2.with_sizes(M, N, K, Ks)
+        rc.l = l
+        drops.append(synth.make_drop(rc, 40 + i, i))
+    return drops
+
+
+def test_batch_matches_oracle_per_drop(ctx):
+    import torch
+
+    import paper_1803_07772_amd as pa
+    drops = _mixed_batch()
+    op = oracle.Params(fixed_count=0, sweeps_per_dinkelbach=120)
+    p = pa.Params(fixed_count=0, sweeps_per_dinkelbach=120)
+    print(f"[gpu case] batch of {len(drops)} mixed drops", flush=True)
+    gains = [torch.from_numpy(d.gain).cuda() for d in drops]
+    res = ctx.solve_batch(drops, p, gains=gains)
+    chaotic = 0
+    for d, r in zip(drops, res):
+        o = oracle.solve(d, op)
+
+        def rerun(scale, d=d):
+            return oracle.solve(dataclasses.replace(d, noise_w=d.noise_w * scale), op)
+
+        info = parity.compare(d, r, o, label=f"batch drop {d.index} {d.M}x{d.N}x{d.K} l={d.l}",
+                              rerun=rerun)
+        print(info, flush=True)
+        chaotic += bool(info.get("skipped"))
+    assert chaotic <= 3
+
+
+def test_batch_host_gains_and_dense(ctx):
+    import paper_1803_07772_amd as pa
+    drops = _mixed_batch()[:4]
+    print("[gpu case] batch host gains", flush=True)
+    res = ctx.solve_batch(drops, pa.Params(sweeps_per_dinkelbach=30), dense_power=True)
+    for d, r in zip(drops, res):
+        dense = np.zeros((d.M, d.N, d.K), np.float32)
+        for m in range(d.M):
+            for n in range(d.N):
+                for a in range(d.l):
+                    if r.sel[m, n, a] >= 0:
+                        dense[m, n, r.sel[m, n, a]] = r.slot_power[m, n, a]
+        assert np.array_equal(dense, r.power)
+
+
+def test_batch_agrees_with_plain_solver(ctx):
+    """Same method, same schedule: the batched and the grid solver agree."""
+    import paper_1803_07772_amd as pa
+    drops = [synth.make_drop(synth.CFG2, s, 0) for s in (0, 1, 2, 4)]
+    p = pa.Params(sweeps_per_dinkelbach=100)
+    print("[gpu case] batch vs plain", flush=True)
+    res = ctx.solve_batch(drops, p)
+    for d, rb in zip(drops, res):
+        rp = ctx.solve(d, p)
+        assert rb.ee == pytest.approx(rp.ee, rel=1e-9)
+        assert np.array_equal(rb.sel, rp.sel)
+        assert np.array_equal(rb.rrh_of_user, rp.rrh_of_user)
+        np.testing.assert_allclose(rb.slot_power, rp.slot_power, rtol=1e-7, atol=1e-15)
+
+
+def test_batch_cfg4_generator_subset(ctx):
+    """Drops of the ragged 4096-drop configuration (a seeded subset of sizes
+    the oracle finishes quickly), solved in one batch with larger ones."""
+    import torch
+
+    import paper_1803_07772_amd as pa
+    M, N, K = synth.batch_sizes(64, seed=0)
+    idx = [b for b in range(64) if M[b] * N[b] * K[b] <= 60000][:6] + [int(np.argmax(M * N * K))]
+    drops = synth.make_batch(64, seed=0, indices=idx)
+    print(f"[gpu case] cfg4 subset sizes {[(d.M, d.N, d.K) for d in drops]}", flush=True)
+    gains = [torch.from_numpy(d.gain).cuda() for d in drops]
+    res = ctx.solve_batch(drops, pa.Params(fixed_count=0, sweeps_per_dinkelbach=60), gains=gains)
+    op = oracle.Params(fixed_count=0, sweeps_per_dinkelbach=60)
+    for d, r in list(zip(drops, res))[:-1]:
+        o = oracle.solve(d, op)
+
+        def rerun(scale, d=d):
+            return oracle.solve(dataclasses.replace(d, noise_w=d.noise_w * scale), op)
+
+        print(parity.compare(d, r, o, label=f"cfg4 drop {d.index}", rerun=rerun), flush=True)
+    assert np.isfinite(res[-1].ee) and res[-1].sweeps > 0
+
+
+def test_batch_rejects_bad_drop(ctx):
+    import paper_1803_07772_amd as pa
+    drops = _mixed_batch()[:3]
+    bad = dataclasses.replace(drops[1], l=0)
+    print("[gpu case] batch invalid", flush=True)
+    with pytest.raises(pa.AllocError, match="-22"):
+        ctx.solve_batch([drops[0], bad, drops[2]])
+
+
+def test_batch_warm_starts_match_oracle(ctx):
+    """Warm starts (initial powers and multipliers, or multipliers only) in a
+    batch, against the oracle from the same warm start; cold drops in between."""
+    import paper_1803_07772_amd as pa
+    drops = _mixed_batch()[:8]
+    rng = np.random.default_rng(5)
+    warms = []
+    for i, d in enumerate(drops):
+        if i % 3 == 2:
+            warms.append(None)
+            continue
+        w = dict(xi0=rng.uniform(0, 3, d.M), zeta0=rng.uniform(0, 2, d.K))
+        if i % 3 == 0:
+            pm = d.pmax_w / d.N
+            w["p0"] = np.where(rng.uniform(size=(d.M, d.N, d.K)) < 0.2,
+                               rng.uniform(0, 1.2, (d.M, d.N, d.K)) * pm[:, None, None], 0.0)
+        warms.append(w)
+    op = oracle.Params(fixed_count=0, sweeps_per_dinkelbach=80)
+    p = pa.Params(fixed_count=0, sweeps_per_dinkelbach=80)
+    print(f"[gpu case] batch of {len(drops)} drops with warm starts", flush=True)
+    res = ctx.solve_batch(drops, p, warms=warms)
+    chaotic = 0
+    for d, w, r in zip(drops, warms, res):
+        o = oracle.solve(d, op, warm=w)
+
+        def rerun(scale, d=d, w=w):
+            return oracle.solve(dataclasses.replace(d, noise_w=d.noise_w * scale), op, warm=w)
+
+        info = parity.compare(d, r, o, label=f"warm batch drop {d.index} warm={sorted(w or {})}",
+                              rerun=rerun)
+        print(info, flush=True)
+        chaotic += bool(info.get("skipped"))
+    assert chaotic <= 2
