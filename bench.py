@@ -1,14 +1,22 @@
 """Benchmark: allocations solved per second on one MI355X.
 
-Default workload: the single-drop plain solver on the 5-RRH, 64-subcarrier,
-32-user configuration (l=2), one step = a batch of drops (seeds) solved one
-after another through alloc_solve with the gains resident in HBM.  The large
-single drop (M=17, N=1024, K=256, l=3, 200 sweeps per Dinkelbach step) is
-timed beside it.  The dominant kernel's roofline uses its algorithmic bytes
-(one float32 gain read per (RRH, subcarrier, user) triple per sweep) over its
-HIP-event duration; the FP64 oracle is timed on a bounded sample on the host.
+Workload (value): batches of drops of the 5-RRH, 64-subcarrier, 32-user
+configuration (24 elastic, 8 streaming users, l=2), converge mode with caps,
+solved by the batched persistent solver (one alloc_solve_batch per step) with
+the gains resident in HBM.  Beside it, on the same GPU:
+* plain: the same drops through alloc_solve, one after another;
+* large_drop: the 17-RRH, 1024-subcarrier, 256-user drop (l=3, exactly 200
+  sweeps per Dinkelbach step) through alloc_solve;
+* nn_warm: a warm-start network trained on the GPU (solved drops of the same
+  generator, other seeds), then network inference + warm-started batched
+  solves of the benchmark's drops.
+The roofline object is the dominant kernel's (the batched solver):
+algorithmic bytes = 4 per (RRH, subcarrier, user) triple per sweep, over its
+HIP-event duration.  The FP64 oracle is timed on a bounded sample of the same
+drops on the host.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -18,24 +26,56 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
+MLP_FLOP_PER_ROW = 2 * (4 * 256 + 256 * 256 + 256 * 256 + 256 * 3)
+METRIC = "allocations solved/s at ≤1e-5 rel EE error; plain vs batched vs NN warm start"
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
-    ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--batch", type=int, default=16, help="drops per step")
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--batch", type=int, default=1024, help="drops per step")
+    ap.add_argument("--plain-drops", type=int, default=16)
+    ap.add_argument("--train-drops", type=int, default=512)
+    ap.add_argument("--train-steps", type=int, default=300)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-large", action="store_true")
+    ap.add_argument("--no-nn", action="store_true")
     return ap.parse_args()
+
+
+def traffic_for(kernel: str, launches_bytes=None):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken on the current kernel source (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        t = json.load(open(path))
+        src = open(os.path.join(ROOT, "paper_1803_07772_amd", "csrc", "alloc.hip"), "rb").read()
+        e = t[kernel]
+        if e["src_sha256"] != hashlib.sha256(src).hexdigest():
+            return None
+        return e["hbm_bytes_per_launch"]
+    except (KeyError, ValueError, OSError):
+        return None
+
+
+def roofline(kernel, bytes_per_launch, ms_per_launch):
+    ach = bytes_per_launch / (ms_per_launch * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(ach, 4), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS, "traffic": traffic_for(kernel), "kernel": kernel,
+            "algorithmic_bytes_per_launch": bytes_per_launch, "ms_per_launch": ms_per_launch}
 
 
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {a.gpus} is not supported "
-              "(drops shard across GPUs with no exchange, but this build runs on one).")
+        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported: drops shard across "
+              "GPUs with no exchange, and this build runs and reports one GPU only.", flush=True)
         sys.exit(2)
     import numpy as np
     import torch
@@ -46,49 +86,59 @@ def main():
     dev = torch.device("cuda:0")
     ctx = pa.Context(0)
     ctx.set_timing(True)
-    params = pa.Params(fixed_count=0)  # converge with caps (200 sweeps / step, 20 steps)
+    params = pa.Params(fixed_count=0)  # converge with caps: 200 sweeps per step, 20 steps
     drops = [synth.make_drop(synth.CFG2, s, 0) for s in range(a.batch)]
     gains = [torch.from_numpy(d.gain).to(dev) for d in drops]
     torch.cuda.synchronize()
+    print(f"[bench] {a.batch} drops of M=5 N=64 K=32 resident; warmup {a.warmup}, steps {a.steps}",
+          flush=True)
 
-    def step():
-        out = []
-        for d, g in zip(drops, gains):
-            r = ctx.solve(d, params, gain=g)
-            out.append((r, ctx.last_kernel_ms(), d))
-        return out
+    def batched_step():
+        res = ctx.solve_batch(drops, params, gains=gains)
+        return res, ctx.last_kernel_ms()
 
     for _ in range(a.warmup):
-        step()
+        batched_step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     runs = []
     for _ in range(a.steps):
-        runs += step()
+        runs.append(batched_step())
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    ms_per_step = 1000.0 * dt / a.steps
+    print(f"[bench] batched: {dt / a.steps * 1e3:.1f} ms per step", flush=True)
     value = a.batch * a.steps / dt
-
-    def roof(rs):
-        bytes_ = sum(4.0 * d.M * d.N * d.K * r.sweeps for r, _, d in rs)
-        kms = sum(k for _, k, _ in rs)
-        ach = bytes_ / (kms * 1e-3) / 1e9
-        return dict(bound="hbm", achieved=round(ach, 3), peak=HBM_PEAK_GBS, unit="GB/s",
-                    frac=ach / HBM_PEAK_GBS, traffic=None,
-                    kernel="solve_kernel", kernel_ms_avg=kms / len(rs),
-                    sweeps_avg=sum(r.sweeps for r, _, _ in rs) / len(rs))
-
+    kms = float(np.mean([k for _, k in runs]))
+    res0 = runs[-1][0]
+    bytes_launch = float(sum(4.0 * d.M * d.N * d.K * r.sweeps for d, r in zip(drops, res0)))
     line = {
-        "metric": "allocations solved/s at <=1e-5 rel EE error; plain vs batched vs NN warm start",
-        "value": value, "unit": "allocations/s", "n_gpus": 1, "steps": a.steps,
-        "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "plain single-drop solver, M=5 N=64 K=32 (24 elastic, 8 streaming) "
-                               "l=2, converge + caps", "drops_per_step": a.batch,
-                   "mode": "plain"},
-        "roofline": roof(runs),
+        "metric": METRIC, "value": value, "unit": "allocations/s", "n_gpus": 1,
+        "steps": a.steps, "warmup": a.warmup, "ms_per_step": 1e3 * dt / a.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded generator: 3GPP-style path loss, shadowing, Rayleigh)",
+        "config": {"workload": "batched solver, drops of M=5 N=64 K=32 (24 elastic, 8 streaming) l=2, "
+                               "converge with caps", "drops_per_step": a.batch, "mode": "batched"},
+        "roofline": roofline("batch_kernel", bytes_launch, kms),
+        "sweeps_mean": float(np.mean([r.sweeps for r in res0])),
+        "ee_mean": float(np.mean([r.ee for r in res0])),
     }
+    modes = {"batched": {"allocations_per_s": value, "kernel_ms": kms}}
+
+    if not a.no_plain:
+        sub = list(zip(drops, gains))[:a.plain_drops]
+        for d, g in sub[:2]:
+            ctx.solve(d, params, gain=g)
+        rs = []
+        t0 = time.perf_counter()
+        for d, g in sub:
+            r = ctx.solve(d, params, gain=g)
+            rs.append((d, r, ctx.last_kernel_ms()))
+        dtp = time.perf_counter() - t0
+        b = float(np.mean([4.0 * d.M * d.N * d.K * r.sweeps for d, r, _ in rs]))
+        modes["plain"] = {"allocations_per_s": len(sub) / dtp, "drops": len(sub),
+                          "roofline": roofline("solve_kernel", b, float(np.mean([k for _, _, k in rs])))}
+        print(f"[bench] plain: {len(sub) / dtp:.1f} allocations/s", flush=True)
+
     if not a.no_large:
         d3 = synth.make_drop(synth.CFG3, 0, 0)
         g3 = torch.from_numpy(d3.gain).to(dev)
@@ -98,27 +148,60 @@ def main():
         t0 = time.perf_counter()
         for _ in range(3):
             r = ctx.solve(d3, p3, gain=g3)
-            rs.append((r, ctx.last_kernel_ms(), d3))
+            rs.append((r, ctx.last_kernel_ms()))
         dt3 = (time.perf_counter() - t0) / 3
-        line["large_drop"] = {"workload": "M=17 N=1024 K=256 l=3, 200 sweeps per step",
-                              "allocations_per_s": 1.0 / dt3, "ms_per_solve": dt3 * 1e3,
-                              "ee": rs[-1][0].ee, "roofline": roof(rs)}
+        b = 4.0 * d3.M * d3.N * d3.K * rs[-1][0].sweeps
+        modes["large_drop"] = {"workload": "M=17 N=1024 K=256 l=3, 200 sweeps per Dinkelbach step",
+                               "allocations_per_s": 1.0 / dt3, "ms_per_solve": dt3 * 1e3,
+                               "sweeps": rs[-1][0].sweeps, "ee": rs[-1][0].ee,
+                               "roofline": roofline("solve_kernel", b, float(np.mean([k for _, k in rs])))}
+        print(f"[bench] large drop: {dt3 * 1e3:.1f} ms per solve", flush=True)
+
+    if not a.no_nn:
+        from paper_1803_07772_amd import warm
+        tdrops = [synth.make_drop(synth.CFG2, 1_000_000 + s, 0) for s in range(a.train_drops)]
+        tg = [torch.from_numpy(d.gain).to(dev) for d in tdrops]
+        cfg = warm.TrainConfig(steps=a.train_steps)
+        net, info = warm.fit(ctx, tdrops, params, cfg, gains=tg)
+        print(f"[bench] trained: {info}", flush=True)
+        net.solve_batch(drops[:64], params, gains=gains[:64])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        wr = net.solve_batch(drops, params, gains=gains)
+        dtw = time.perf_counter() - t0
+        mlp_ms = net.last_ms()
+        rows = sum(d.M * d.N * d.K for d in drops)
+        tfl = MLP_FLOP_PER_ROW * rows / (mlp_ms * 1e-3) / 1e12
+        ee_ratio = np.array([w.ee / c.ee for w, c in zip(wr, res0)])
+        modes["nn_warm"] = {
+            "allocations_per_s": a.batch / dtw, "includes": "network inference + warm-started batched solve",
+            "train": {k: v for k, v in info.items()}, "train_drops": a.train_drops,
+            "sweeps_mean_warm": float(np.mean([r.sweeps for r in wr])),
+            "sweeps_mean_cold": line["sweeps_mean"],
+            "ee_ratio_warm_over_cold_mean": float(ee_ratio.mean()),
+            "ee_ratio_min": float(ee_ratio.min()),
+            "fallbacks": int(sum(bool(r.status_flags & 16) for r in wr)),
+            "mlp_ms": mlp_ms,
+            "mlp_roofline": {"bound": "mfma", "achieved": tfl, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                             "frac": tfl / BF16_PEAK_TFLOPS, "flop_per_row": MLP_FLOP_PER_ROW, "rows": rows},
+        }
+        print(f"[bench] nn warm: {a.batch / dtw:.1f} allocations/s", flush=True)
+    line["modes"] = modes
+
     if not a.no_cpu_baseline:
         import oracle
         op = oracle.Params(fixed_count=0)
         t0 = time.perf_counter()
         n = 0
-        while True:
+        while time.perf_counter() - t0 < 10.0:
             oracle.solve(drops[n % len(drops)], op)
             n += 1
-            if time.perf_counter() - t0 > 10.0:
-                break
         dtc = time.perf_counter() - t0
         cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         line["cpu_baseline"] = {"value": n / dtc, "unit": "allocations/s", "cores": cores,
                                 "kind": "oracle",
-                                "sample": f"{n} solves of the same M=5 N=64 K=32 drops, "
-                                          f"{dtc:.1f} s, FP64 C oracle with OpenMP over subcarriers"}
+                                "sample": f"{n} solves of the first drops of the benchmark batch in "
+                                          f"{dtc:.1f} s (FP64 C oracle, OpenMP over subcarriers)"}
     ctx.close()
     print(json.dumps(line), flush=True)
 

@@ -14,13 +14,15 @@
  *                  Psi_k (0 for elastic users),  (10 log10(1000 pmax_m) - 40)/10];
  *  - 4 -> 256 -> 256 -> 256 -> 3, GELU (tanh form) after each hidden layer;
  *  - outputs y = [power logit, xi contribution, zeta contribution].
- * Warm start of a drop: q = sigmoid(y0), p0 = q pmask_m where q >= 0.1 else 0;
+ * Powers are coded over six decades below the mask: code(p) = 1 + log10(p/pmask)/6.
+ * Warm start of a drop: q = sigmoid(y0), p0 = pmask_m 10^(6(q-1)) where q >= 0.1
+ * else 0;
  * xi0_m = expm1(clip(mean_{n,k} y1, 0, 30)); zeta0_k = expm1(clip(mean_{m,n}
  * y2, 0, 30)) for streaming users, 0 for elastic users.
  * Training loss per row: w0 BCE-with-logits(y0, t0) + w1 (y1-t1)^2 +
  * w2 (y2-t2)^2, averaged over rows; targets from a solved drop are
- * t0 = p/pmask, t1 = log1p(xi_m), t2 = log1p(zeta_k), weights 1, 1, and the
- * streaming flag.
+ * t0 = code(p) clipped to [0,1] (0 where p = 0), t1 = log1p(xi_m),
+ * t2 = log1p(zeta_k), weights 1, 1, and the streaming flag.
  *
  * Rounding: inputs, weight matrices, hidden activations and the upstream
  * gradients that enter products are bfloat16 (round to nearest even);
@@ -52,8 +54,8 @@ extern "C" {
 #define ALLOC_MLP_NOUT 3
 #define ALLOC_MLP_NPARAMS 133635
 
-/* alloc_result.status_flags: the warm-started solve ended non-finite or
- * QoS-infeasible, and the returned result is the cold-started solve's */
+/* alloc_result.status_flags: the warm-started solve ended non-finite or with
+ * no allocation (EE <= 0), and the returned result is the cold-started solve's */
 #define ALLOC_WARM_FALLBACK 16u
 
 typedef struct alloc_mlp alloc_mlp;
@@ -101,7 +103,8 @@ ALLOC_API int alloc_mlp_adamw(alloc_mlp* net, const float* grad, const alloc_mlp
  * [M][N][K] indices, device) writes features feat [R][4], targets
  * target [R][3] and loss weights weight [R][3] (float32, device), from the
  * dense solved powers power [M][N][K] (float32, device) and the final
- * multipliers xi [M], zeta [K] (float64, device). */
+ * multipliers xi [M], zeta [K] (float64, device).  An index outside
+ * [0, M*N*K) gives an all-zero row (zero loss weights). */
 ALLOC_API int alloc_mlp_rows(alloc_mlp* net, const alloc_problem* prob, uint32_t flags,
                              const float* power, const double* xi, const double* zeta,
                              int64_t R, const int64_t* idx, float* feat, float* target,
@@ -114,13 +117,16 @@ ALLOC_API int alloc_mlp_warm(alloc_mlp* net, const alloc_problem* prob, uint32_t
 
 /* Network inference, then alloc_solve from that warm start.  Falls back to
  * the cold start (and sets ALLOC_WARM_FALLBACK) when the warm-started solve
- * ends with ALLOC_NONFINITE or ALLOC_QOS_INFEASIBLE. */
+ * ends with ALLOC_NONFINITE or with EE <= 0 (nothing allocated).  QoS
+ * infeasibility is reported, not a fallback: the cold start ends
+ * QoS-infeasible on most drops of the streaming-heavy configurations too. */
 ALLOC_API int alloc_solve_mlp(alloc_mlp* net, const alloc_problem* prob, const alloc_params* prm,
                               alloc_result* res);
 
 /* Network inference for B drops, then alloc_solve_batch from those warm
- * starts; drops whose warm-started solve ends non-finite or QoS-infeasible
- * are solved again from the cold start in a second batch (ALLOC_WARM_FALLBACK). */
+ * starts; drops whose warm-started solve needs the fallback (as for
+ * alloc_solve_mlp) are solved again from the cold start in a second batch
+ * (ALLOC_WARM_FALLBACK). */
 ALLOC_API int alloc_solve_batch_mlp(alloc_mlp* net, int32_t B, const alloc_problem* probs,
                                     const alloc_params* prm, alloc_result* results);
 

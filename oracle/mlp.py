@@ -33,15 +33,18 @@ Rounding model of the GPU kernels, emulated here when ``emulate`` is true:
 Loss per row r: BCE-with-logits(y0, t0) + (y1 - t1)^2 + (y2 - t2)^2, each term
 times its weight w_rj, averaged over the R rows.
 
+Powers are encoded over P_DECADES decades below the mask: a power p in
+[pmask 10^-P_DECADES, pmask] has the code 1 + log10(p/pmask)/P_DECADES in [0, 1].
+
 Warm start from the outputs of every triple of a drop:
 
-* q = sigmoid(y0); p0 = q pmask_m where q >= Q_MIN, else 0;
+* q = sigmoid(y0); p0 = pmask_m 10^(P_DECADES (q - 1)) where q >= Q_MIN, else 0;
 * xi0_m = expm1(clip(mean over (n, k) of y1, 0, 30));
 * zeta0_k = expm1(clip(mean over (m, n) of y2, 0, 30)) for streaming users,
   0 for elastic ones.
 
-Training targets from a solved drop: t0 = p*/pmask clipped to [0, 1],
-t1 = log1p(xi*_m), t2 = log1p(zeta*_k); weights 1, 1 and f1.
+Training targets from a solved drop: t0 = the code of p* clipped to [0, 1]
+(0 where p* = 0), t1 = log1p(xi*_m), t2 = log1p(zeta*_k); weights 1, 1 and f1.
 """
 from __future__ import annotations
 
@@ -51,6 +54,7 @@ import numpy as np
 
 NIN, HID, NOUT = 4, 256, 3
 Q_MIN = 0.1
+P_DECADES = 6.0
 LOG_CLIP = 30.0
 SHAPES = (("W1", (HID, NIN)), ("b1", (HID,)), ("W2", (HID, HID)), ("b2", (HID,)),
           ("W3", (HID, HID)), ("b3", (HID,)), ("W4", (NOUT, HID)), ("b4", (NOUT,)))
@@ -185,7 +189,7 @@ def warm_start(drop, y, pmask=None):
     M, N, K = drop.M, drop.N, drop.K
     pm = drop.pmax_w / N if pmask is None else np.asarray(pmask, dtype=np.float64)
     q = 0.5 * (1.0 + np.tanh(0.5 * y[..., 0]))
-    p0 = np.where(q >= Q_MIN, q * pm[:, None, None], 0.0)
+    p0 = np.where(q >= Q_MIN, pm[:, None, None] * 10.0 ** (P_DECADES * (q - 1.0)), 0.0)
     xi0 = np.expm1(np.clip(y[..., 1].mean(axis=(1, 2)), 0.0, LOG_CLIP))
     z = np.expm1(np.clip(y[..., 2].mean(axis=(0, 1)), 0.0, LOG_CLIP))
     zeta0 = np.where(drop.user_type.astype(bool), z, 0.0)
@@ -197,7 +201,10 @@ def targets(drop, power, xi, zeta, pmask=None):
     M, N, K = drop.M, drop.N, drop.K
     pm = drop.pmax_w / N if pmask is None else np.asarray(pmask, dtype=np.float64)
     T = np.empty((M, N, K, NOUT))
-    T[..., 0] = np.clip(np.asarray(power, dtype=np.float64) / pm[:, None, None], 0.0, 1.0)
+    pw = np.asarray(power, dtype=np.float64)
+    with np.errstate(divide="ignore"):
+        code = 1.0 + np.log10(pw / pm[:, None, None]) / P_DECADES
+    T[..., 0] = np.where(pw > 0, np.clip(code, 0.0, 1.0), 0.0)
     T[..., 1] = np.log1p(np.asarray(xi, dtype=np.float64))[:, None, None]
     T[..., 2] = np.log1p(np.asarray(zeta, dtype=np.float64))[None, None, :]
     Wt = np.ones((M, N, K, NOUT))

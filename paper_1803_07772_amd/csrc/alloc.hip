@@ -339,6 +339,10 @@ struct PassConst {
 // One tile of ns subcarriers n = n0, n0 + nstep, ... of a sweep (update) or
 // of an evaluation pass (no update).  Everything here is defined per
 // subcarrier; the tile only gives each barrier interval more independent work.
+// kItemH: step 6 runs one item per (t, m, k) and sums over t afterwards (the
+// batched solver's tiles span many subcarriers); otherwise one item per
+// (m, k) loops over t.  Both add the tile's H values in subcarrier order.
+template <bool kItemH>
 __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s, int n0, int nstep,
                      int ns) {
   const int M = d.M, N = d.N, K = d.K, L = d.L, tid = threadIdx.x, nth = blockDim.x;
@@ -569,46 +573,58 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
   }
   __syncthreads();
 
-  // 6. per-triple Lagrangian maximum H for every (m,k), summed over the
-  //    tile's subcarriers in order
-  for (int i = tid; i < M * K; i += nth) {
-    const int m = i / K, k = i - m * K;
+  // 6. per-triple Lagrangian maximum H
+  auto h_item = [&](int t, int m, int k, double u) -> double {
     const double wmu = (d.w ? d.w[(size_t)m * K + k] : 1.0) * s.mu[k];
-    const bool el = s.el[k];
-    const bool own = s.Al[k] == m;
-    double Hsum = 0.0;
-    for (int t = 0; t < ns; ++t) {
-      const double u = s.u[IX_MK(t, m, k)];
-      const int cnt = s.vcnt[IX_SM(t, m)];
-      int q = -1, pos = 0;
-      for (int a = 0; a < cnt; ++a) {
-        const int ka = s.vuser[IX_ML(t, m, a)];
-        const double ua = s.vu[IX_ML(t, m, a)];
-        if (ka == k) q = a;
-        if (ua < u || (ua == u && ka < k)) ++pos;
-      }
-      const double Sb = s.vpre[IX_ML1(t, m, q >= 0 ? q : pos)];
-      const double pin = s.vT[IX_ML1(t, m, q >= 0 ? q + 1 : pos)];
-      const double c = (el ? pc.E * s.eta[m] : 0.0) + s.xi[m] + pin + s.pinter[IX_SM(t, m)] + s.psic[IX_SM(t, m)];
-      double H = 0.0;
-      if (wmu > 0.0) {
-        const double ainv = u + Sb;
-        double pt;
-        if (c <= 0.0) {
-          pt = s.pmask[m];
-        } else {
-          const double Wl = wmu / (c * kLn2);
-          pt = fmin(fmax(Wl - ainv, 0.0), s.pmask[m]);
-        }
-        if (pt > 0.0) H = wmu * log2_1p(pt / ainv) - c * pt;
-      }
-      Hsum += H;
-      if (own) {
-        s.Hc[IX_SK(t, k)] = H;
-        s.pic[IX_SK(t, k)] = pin;
-      }
+    const int cnt = s.vcnt[IX_SM(t, m)];
+    int q = -1, pos = 0;
+    for (int a = 0; a < cnt; ++a) {
+      const int ka = s.vuser[IX_ML(t, m, a)];
+      const double ua = s.vu[IX_ML(t, m, a)];
+      if (ka == k) q = a;
+      if (ua < u || (ua == u && ka < k)) ++pos;
     }
-    s.Sacc[i] += Hsum;
+    const double Sb = s.vpre[IX_ML1(t, m, q >= 0 ? q : pos)];
+    const double pin = s.vT[IX_ML1(t, m, q >= 0 ? q + 1 : pos)];
+    const double c =
+        (s.el[k] ? pc.E * s.eta[m] : 0.0) + s.xi[m] + pin + s.pinter[IX_SM(t, m)] + s.psic[IX_SM(t, m)];
+    double H = 0.0;
+    if (wmu > 0.0) {
+      const double ainv = u + Sb;
+      double pt;
+      if (c <= 0.0) {
+        pt = s.pmask[m];
+      } else {
+        const double Wl = wmu / (c * kLn2);
+        pt = fmin(fmax(Wl - ainv, 0.0), s.pmask[m]);
+      }
+      if (pt > 0.0) H = wmu * log2_1p(pt / ainv) - c * pt;
+    }
+    if (s.Al[k] == m) {
+      s.Hc[IX_SK(t, k)] = H;
+      s.pic[IX_SK(t, k)] = pin;
+    }
+    return H;
+  };
+  if (kItemH) {
+    // H replaces the triple's own u (nothing later in the pass reads u)
+    for (int i = tid; i < ns * M * K; i += nth) {
+      const int t = i / (M * K), r = i - t * M * K, m = r / K, k = r - m * K;
+      s.u[i] = h_item(t, m, k, s.u[i]);
+    }
+    __syncthreads();
+    for (int i = tid; i < M * K; i += nth) {
+      double Hsum = 0.0;
+      for (int t = 0; t < ns; ++t) Hsum += s.u[t * M * K + i];
+      s.Sacc[i] += Hsum;
+    }
+  } else {
+    for (int i = tid; i < M * K; i += nth) {
+      const int m = i / K, k = i - m * K;
+      double Hsum = 0.0;
+      for (int t = 0; t < ns; ++t) Hsum += h_item(t, m, k, s.u[IX_MK(t, m, k)]);
+      s.Sacc[i] += Hsum;
+    }
   }
   __syncthreads();
 
@@ -900,7 +916,7 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(Drop d, Sched sc) {
     pc.write_out = !update;
     begin_pass(d, s);
     const int nb = (d.N - b + G - 1) / G;  // my subcarriers: b, b+G, ...
-    for (int j = 0; j < nb; j += sc.tile) tile(d, sc, pc, s, b + j * G, G, min(sc.tile, nb - j));
+    for (int j = 0; j < nb; j += sc.tile) tile<false>(d, sc, pc, s, b + j * G, G, min(sc.tile, nb - j));
     write_partials(d, s, b);
     grid.sync();
     reduce_pass(d, sc, c, s, b, G, update, pc.delta_v);
@@ -1065,7 +1081,7 @@ __global__ void __launch_bounds__(kBlock) batch_kernel(const Drop* drops, const 
       pc.write_out = !update;
       if (threadIdx.x == 0) s_changes = 0;
       begin_pass(d, s);
-      for (int n0 = 0; n0 < d.N; n0 += sd.tile) tile(d, sd, pc, s, n0, 1, min(sd.tile, d.N - n0));
+      for (int n0 = 0; n0 < d.N; n0 += sd.tile) tile<true>(d, sd, pc, s, n0, 1, min(sd.tile, d.N - n0));
       block_reduce(d, sd, c, s, update, pc.delta_v, &s_changes);
       if (threadIdx.x == 0) {
         double R = 0.0, P = d.pstatic, dm = 0.0;

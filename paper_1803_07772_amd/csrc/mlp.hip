@@ -42,6 +42,7 @@ constexpr int kLayerIn[5] = {0, kIn, kHid, kHid, kHid};
 constexpr int kLayerOut[5] = {0, kHid, kHid, kHid, kOut};
 constexpr float kGc = 0.7978845608028654f;  // sqrt(2/pi)
 constexpr double kQMin = 0.1, kLogClip = 30.0;
+constexpr double kDecades = 6.0;  // power code: 1 + log10(p/pmask)/kDecades
 constexpr int64_t kChunk = 1 << 20;  // rows per inference chunk
 
 // ----------------------------------------------------------------- helpers
@@ -313,11 +314,17 @@ __global__ void rows_kernel(FeatDrop d, const float* power, const double* xi, co
   if (r >= R) return;
   const int64_t i = idx[r];
   const int64_t NK = (int64_t)d.N * d.K;
+  if (i < 0 || i >= (int64_t)d.M * NK) {  // out-of-range index: an all-zero row
+    for (int c = 0; c < 4; ++c) feat[r * 4 + c] = 0.0f;
+    for (int c = 0; c < 3; ++c) target[r * 3 + c] = weight[r * 3 + c] = 0.0f;
+    return;
+  }
   const int m = (int)(i / NK), k = (int)(i % d.K);
   float f[4];
   triple_features(d, i, f);
   for (int c = 0; c < 4; ++c) feat[r * 4 + c] = f[c];
-  target[r * 3] = (float)fmin(fmax((double)power[i] / d.pmask[m], 0.0), 1.0);
+  const double pw = power[i];
+  target[r * 3] = pw > 0.0 ? (float)fmin(fmax(1.0 + log10(pw / d.pmask[m]) / kDecades, 0.0), 1.0) : 0.0f;
   target[r * 3 + 1] = (float)log1p(xi[m]);
   target[r * 3 + 2] = (float)log1p(zeta[k]);
   weight[r * 3] = 1.0f;
@@ -325,14 +332,14 @@ __global__ void rows_kernel(FeatDrop d, const float* power, const double* xi, co
   weight[r * 3 + 2] = f[1];
 }
 
-// Initial powers: q = sigmoid(y0); p0 = q pmask where q >= 0.1, else 0.
+// Initial powers: q = sigmoid(y0); p0 = pmask 10^(6 (q - 1)) where q >= 0.1, else 0.
 __global__ void p0_kernel(FeatDrop d, const float* y, double* p0) {
   const int64_t n = (int64_t)d.M * d.N * d.K;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n) return;
   const int m = (int)(t / ((int64_t)d.N * d.K));
   const double q = 1.0 / (1.0 + exp(-(double)y[t * 3]));
-  p0[t] = q >= kQMin ? q * d.pmask[m] : 0.0;
+  p0[t] = q >= kQMin ? d.pmask[m] * exp10(kDecades * (q - 1.0)) : 0.0;
 }
 
 // xi0_m = expm1(clip(mean_{n,k} y1, 0, 30)): one workgroup per RRH, fixed order.
@@ -708,7 +715,9 @@ WarmArrays warm_arrays(int64_t n3, int M, int K) {
   return w;
 }
 
-bool needs_fallback(uint32_t f) { return f & (ALLOC_NONFINITE | ALLOC_QOS_INFEASIBLE); }
+// The warm-started solve is replaced by the cold one when it ended
+// non-finite or with no allocation at all (EE not positive).
+bool needs_fallback(const alloc_result& r) { return (r.status_flags & ALLOC_NONFINITE) || !(r.ee > 0.0); }
 
 }  // namespace
 
@@ -911,7 +920,7 @@ int alloc_solve_mlp(alloc_mlp* net, const alloc_problem* pb, const alloc_params*
                                    (const double*)(net->ws + wa.zeta0)};
   rc = alloc_internal::solve_one(c, pb, prm, nullptr, &dw, res);
   if (rc) return rc;
-  if (needs_fallback(res->status_flags)) {
+  if (needs_fallback(*res)) {
     rc = alloc_internal::solve_one(c, pb, prm, nullptr, nullptr, res);
     if (rc) return rc;
     res->status_flags |= ALLOC_WARM_FALLBACK;
@@ -962,7 +971,7 @@ int alloc_solve_batch_mlp(alloc_mlp* net, int32_t B, const alloc_problem* probs,
   net->last_ms = c->timing ? mlp_ms : -1.0;
   std::vector<int> redo;
   for (int b = 0; b < B; ++b)
-    if (needs_fallback(results[b].status_flags)) redo.push_back(b);
+    if (needs_fallback(results[b])) redo.push_back(b);
   if (redo.empty()) return ALLOC_OK;
   std::vector<alloc_problem> rp;
   std::vector<alloc_result> rr;

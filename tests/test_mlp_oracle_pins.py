@@ -183,13 +183,13 @@ def test_warm_start_pooling():
     M, N, K = d.M, d.N, d.K
     y = np.zeros((M, N, K, 3))
     y[..., 0] = -10.0  # q ~ 4.5e-5 < Q_MIN: no power
-    y[1, 2, 4, 0] = 0.0  # q = 1/2
+    y[1, 2, 4, 0] = 0.0  # q = 1/2: code 1/2, three decades below the mask
     y[..., 1] = np.log1p(2.0)
     y[0, :, :, 1] = -5.0  # negative mean is clipped to 0
     y[..., 2] = np.log1p(3.0)
     p0, xi0, zeta0 = mlp.warm_start(d, y)
     pm = d.pmax_w / N
-    assert p0[1, 2, 4] == pytest.approx(0.5 * pm[1], rel=1e-14)
+    assert p0[1, 2, 4] == pytest.approx(1e-3 * pm[1], rel=1e-13)
     assert np.count_nonzero(p0) == 1
     assert xi0[0] == 0.0 and np.allclose(xi0[1:], 2.0, rtol=1e-13)
     assert np.allclose(zeta0[d.user_type == 1], 3.0, rtol=1e-13)
@@ -202,9 +202,14 @@ def test_targets_from_solution():
     power = np.zeros((d.M, d.N, d.K))
     power[2, 1, 3] = 0.25 * pm[2]
     power[0, 0, 0] = 2.0 * pm[0]  # above the mask: clipped to 1
+    power[1, 3, 5] = 1e-9 * pm[1]  # more than six decades below: clipped to 0
+    power[1, 4, 5] = 1e-3 * pm[1]  # three decades below: code 1/2
     xi = np.arange(d.M, dtype=np.float64)
     zeta = np.where(d.user_type == 1, 1.5, 0.0)
     T, W = mlp.targets(d, power, xi, zeta)
-    assert T[2, 1, 3, 0] == pytest.approx(0.25) and T[0, 0, 0, 0] == 1.0
+    assert T[2, 1, 3, 0] == pytest.approx(1.0 + math.log10(0.25) / 6.0, rel=1e-14)
+    assert T[0, 0, 0, 0] == 1.0 and T[1, 3, 5, 0] == 0.0
+    assert T[1, 4, 5, 0] == pytest.approx(0.5, rel=1e-14)
+    assert T[0, 1, 1, 0] == 0.0  # unselected
     assert np.allclose(T[:, 0, 0, 1], np.log1p(xi))
     assert np.all(W[..., 2] == d.user_type[None, None, :])
