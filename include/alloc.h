@@ -104,6 +104,9 @@ typedef struct {
                                     (0 = one per compute unit, <= N) */
   int32_t tile;                  /* 0: subcarriers a workgroup processes together
                                     (0 = as many as its LDS holds) */
+  int32_t lds_kb;                /* 0: batched solver only: LDS per workgroup in KiB
+                                    (0 = a whole compute unit's; smaller values let
+                                    several workgroups share a compute unit) */
 } alloc_params;
 
 ALLOC_API void alloc_params_default(alloc_params* p);
@@ -159,6 +162,23 @@ ALLOC_API int alloc_solve(alloc_ctx* ctx, const alloc_problem* prob, const alloc
 ALLOC_API int alloc_solve_batch(alloc_ctx* ctx, int32_t B, const alloc_problem* probs,
                                 const alloc_params* prm, const alloc_warm* warms,
                                 alloc_result* results);
+
+/* A resident batch: the drops' inputs, state and outputs stay on the device
+ * and the batched solve (work-queue reset and the persistent kernel, no host
+ * copies) is captured once into a HIP graph that every run replays.  Cold
+ * starts only (warms are not taken); results as for alloc_solve_batch.
+ * Device gain pointers (ALLOC_GAIN_ON_DEVICE) must stay valid for the life of
+ * the batch; host gains are copied in at creation. */
+typedef struct alloc_batch alloc_batch;
+ALLOC_API int alloc_batch_create(alloc_ctx* ctx, int32_t B, const alloc_problem* probs,
+                                 const alloc_params* prm, alloc_batch** out);
+/* Replays the captured solve on the context's stream and waits for it. */
+ALLOC_API int alloc_batch_run(alloc_batch* batch);
+/* Results of the last run (host arrays as in alloc_solve_batch). */
+ALLOC_API int alloc_batch_results(alloc_batch* batch, alloc_result* results);
+/* Duration of the last run's graph in ms (HIP events on the context's stream). */
+ALLOC_API double alloc_batch_last_ms(alloc_batch* batch);
+ALLOC_API void alloc_batch_destroy(alloc_batch* batch);
 
 ALLOC_API const char* alloc_strerror(int code);
 

@@ -48,7 +48,7 @@ class _Params(ctypes.Structure):
                 ("churn_limit", ctypes.c_int32), ("tol_dinkelbach", ctypes.c_double),
                 ("tol_dual", ctypes.c_double), ("step0", ctypes.c_double),
                 ("flags", ctypes.c_uint32), ("max_groups", ctypes.c_int32),
-                ("tile", ctypes.c_int32)]
+                ("tile", ctypes.c_int32), ("lds_kb", ctypes.c_int32)]
 
 
 class _Warm(ctypes.Structure):
@@ -70,7 +70,8 @@ EXPORTS = ("alloc_ctx_create", "alloc_ctx_destroy", "alloc_params_default", "all
            "alloc_mlp_create", "alloc_mlp_destroy", "alloc_mlp_set_params", "alloc_mlp_get_params",
            "alloc_mlp_features", "alloc_mlp_forward", "alloc_mlp_grad", "alloc_mlp_train_step",
            "alloc_mlp_adamw", "alloc_mlp_rows", "alloc_mlp_warm", "alloc_solve_mlp",
-           "alloc_solve_batch_mlp", "alloc_mlp_last_ms")
+           "alloc_solve_batch_mlp", "alloc_mlp_last_ms", "alloc_batch_create", "alloc_batch_run",
+           "alloc_batch_results", "alloc_batch_last_ms", "alloc_batch_destroy")
 
 
 def load():
@@ -101,6 +102,17 @@ def load():
         lib.alloc_ctx_set_timing.restype = ctypes.c_int
         lib.alloc_ctx_last_kernel_ms.argtypes = [ctypes.c_void_p]
         lib.alloc_ctx_last_kernel_ms.restype = ctypes.c_double
+        lib.alloc_batch_create.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(_Problem),
+                                           ctypes.POINTER(_Params), ctypes.POINTER(ctypes.c_void_p)]
+        lib.alloc_batch_create.restype = ctypes.c_int
+        lib.alloc_batch_run.argtypes = [ctypes.c_void_p]
+        lib.alloc_batch_run.restype = ctypes.c_int
+        lib.alloc_batch_results.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Result)]
+        lib.alloc_batch_results.restype = ctypes.c_int
+        lib.alloc_batch_last_ms.argtypes = [ctypes.c_void_p]
+        lib.alloc_batch_last_ms.restype = ctypes.c_double
+        lib.alloc_batch_destroy.argtypes = [ctypes.c_void_p]
+        lib.alloc_batch_destroy.restype = None
         _lib = lib
     return _lib
 
@@ -122,18 +134,19 @@ class Params:
     step0: float = 0.1
     max_groups: int = 0
     tile: int = 0
+    lds_kb: int = 0
 
     def _c(self, flags: int) -> _Params:
         return _Params(self.max_dinkelbach, self.sweeps_per_dinkelbach, self.refit_period,
                        self.fixed_count, self.churn_limit, self.tol_dinkelbach, self.tol_dual,
-                       self.step0, flags, self.max_groups, self.tile)
+                       self.step0, flags, self.max_groups, self.tile, self.lds_kb)
 
 
 def default_params() -> Params:
     p = _Params()
     load().alloc_params_default(ctypes.byref(p))
     return Params(p.max_dinkelbach, p.sweeps_per_dinkelbach, p.refit_period, p.fixed_count,
-                  p.churn_limit, p.tol_dinkelbach, p.tol_dual, p.step0, p.max_groups, p.tile)
+                  p.churn_limit, p.tol_dinkelbach, p.tol_dual, p.step0, p.max_groups, p.tile, p.lds_kb)
 
 
 @dataclasses.dataclass
@@ -303,3 +316,49 @@ class Context:
         _check(load().alloc_solve(self._h, ctypes.byref(pb), ctypes.byref(pc),
                                   ctypes.byref(wm) if wm is not None else None, ctypes.byref(res)))
         return to_result(res, out, dense)
+
+
+class Batch:
+    """A resident batch (alloc_batch_*): inputs stay on the device and every
+    run replays the captured batched solve."""
+
+    def __init__(self, ctx: Context, drops, params: Params | None = None, gains=None,
+                 dense_power: bool = False):
+        self.ctx = ctx
+        self._keep = []
+        self.drops = list(drops)
+        self._gains = gains  # device gains must outlive the batch
+        flags = ALLOC_GAIN_ON_DEVICE if gains is not None else 0
+        probs, results, outs = Context._batch_structs(self.drops, self._keep, gains, dense_power)
+        self._results, self._outs = results, outs
+        pc = (params or Params())._c(flags)
+        h = ctypes.c_void_p()
+        _check(load().alloc_batch_create(ctx._h, len(self.drops), probs, ctypes.byref(pc), ctypes.byref(h)))
+        self._h = h
+
+    def run(self):
+        _check(load().alloc_batch_run(self._h))
+
+    def last_ms(self) -> float:
+        return load().alloc_batch_last_ms(self._h)
+
+    def results(self) -> list:
+        _check(load().alloc_batch_results(self._h, self._results))
+        out = []
+        for b in range(len(self.drops)):
+            o, dense = self._outs[b]
+            r = to_result(self._results[b], {k: v.copy() for k, v in o.items()},
+                          None if dense is None else dense.copy())
+            out.append(r)
+        return out
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().alloc_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

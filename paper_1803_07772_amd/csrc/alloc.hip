@@ -104,134 +104,139 @@ struct Drop {
   int start_eval;          // the initial allocation is Dinkelbach's p^0 (warm start)
 };
 
-// LDS carve-up for one workgroup.  Arrays marked [T] have one row per
+// Pointers into the workgroup's LDS: 32-bit addresses, direct LDS access.
+#define LDS __attribute__((address_space(3)))
+
+// LDS carve-up for one workgroup.  The table of array pointers itself sits in
+// LDS (written once per drop by thread 0): the pointers are reloaded from
+// there as needed instead of occupying registers or spilling.  Arrays marked [T] have one row per
 // subcarrier of the tile being processed.
 struct Lds {
-  float* g;       // [T][M][K] gains
-  double* u;      // [T][M][K] (sigma + ICI)/Gamma
-  double* Sacc;   // [M][K] association metric summed over my subcarriers
-  double* mu;     // [K] 1 (elastic) or zeta'
-  double* racc;   // [K]
-  double* rhacc;  // [K]
-  int* Al;        // [K]
-  int* el;        // [K] 1 elastic
-  int* grp;       // [K] users grouped by RRH
-  int* grpk;      // [K] rank of a user within its RRH group
-  int* grp_off;   // [M+1]
-  int* wcnt;      // [kBlock/64][M] per-wave group counts
-  int* gcur;      // [M]
-  double* Hc;     // [T][K] H of user k on its own RRH
-  double* pic;    // [T][K] intra-cell price of user k on its own RRH
-  double* rk;     // [T][K] rate of user k on the subcarrier
-  double* rhk;    // [T][K] surrogate rate
-  int* su;        // [T][M][L] slots, storage order
-  double* sp;     // [T][M][L]
-  double* sal;    // [T][M][L]
-  double* sbe;    // [T][M][L]
-  double* szs;    // [T][M][L][L]
-  double* szn;    // [T][M][L][L] after this sweep's subgradient step
-  int* vcnt;      // [T][M] per-RRH view in decoding order
-  int* vslot;     // [T][M][L]
-  int* vuser;     // [T][M][L]
-  double* vu;     // [T][M][L]
-  double* vpre;   // [T][M][L+1]
-  double* vc;     // [T][M][L]
-  double* vcg;    // [T][M][L]
-  double* vr;     // [T][M][L]
-  double* vT;     // [T][M][L+1] suffix sums of vcg
-  double* Ptot;   // [T][M]
-  double* pinter; // [T][M]
-  double* psic;   // [T][M]
-  double* tps;    // [T][M]
-  double* tpe;    // [T][M]
-  double* tR;     // [T][M]
-  int* frozen;    // [T][M]
-  int* churn;     // [T][M]
-  int* np;        // [T][M]
-  double* pij;    // [T][M][M]
-  double* contrib; // [T][M][M]
-  int* chosen;    // [T][M][L]
-  int* nold;      // [T][M][L]
-  double* dmi;    // [T][M][L]
-  double* xi;     // [M]
-  double* eta;    // [M]
-  double* pmask;  // [M]
-  double* psacc;  // [M]
-  double* peacc;  // [M]
-  double* Racc;   // [M]
-  double* dmax;   // [M]
-  double* red;    // [kBlock] scratch for reductions
-  double* tmp;    // [M+2] reduction results
+  LDS float* g;       // [T][M][K] gains
+  LDS double* u;      // [T][M][K] (sigma + ICI)/Gamma
+  LDS double* Sacc;   // [M][K] association metric summed over my subcarriers
+  LDS double* mu;     // [K] 1 (elastic) or zeta'
+  LDS double* racc;   // [K]
+  LDS double* rhacc;  // [K]
+  LDS int* Al;        // [K]
+  LDS int* el;        // [K] 1 elastic
+  LDS int* grp;       // [K] users grouped by RRH
+  LDS int* grpk;      // [K] rank of a user within its RRH group
+  LDS int* grp_off;   // [M+1]
+  LDS int* wcnt;      // [kBlock/64][M] per-wave group counts
+  LDS int* gcur;      // [M]
+  LDS double* Hc;     // [T][K] H of user k on its own RRH
+  LDS double* pic;    // [T][K] intra-cell price of user k on its own RRH
+  LDS double* rk;     // [T][K] rate of user k on the subcarrier
+  LDS double* rhk;    // [T][K] surrogate rate
+  LDS int* su;        // [T][M][L] slots, storage order
+  LDS double* sp;     // [T][M][L]
+  LDS double* sal;    // [T][M][L]
+  LDS double* sbe;    // [T][M][L]
+  LDS double* szs;    // [T][M][L][L]
+  LDS double* szn;    // [T][M][L][L] after this sweep's subgradient step
+  LDS int* vcnt;      // [T][M] per-RRH view in decoding order
+  LDS int* vslot;     // [T][M][L]
+  LDS int* vuser;     // [T][M][L]
+  LDS double* vu;     // [T][M][L]
+  LDS double* vpre;   // [T][M][L+1]
+  LDS double* vc;     // [T][M][L]
+  LDS double* vcg;    // [T][M][L]
+  LDS double* vr;     // [T][M][L]
+  LDS double* vT;     // [T][M][L+1] suffix sums of vcg
+  LDS double* Ptot;   // [T][M]
+  LDS double* pinter; // [T][M]
+  LDS double* psic;   // [T][M]
+  LDS double* tps;    // [T][M]
+  LDS double* tpe;    // [T][M]
+  LDS double* tR;     // [T][M]
+  LDS int* frozen;    // [T][M]
+  LDS int* churn;     // [T][M]
+  LDS int* np;        // [T][M]
+  LDS double* pij;    // [T][M][M]
+  LDS double* contrib; // [T][M][M]
+  LDS int* chosen;    // [T][M][L]
+  LDS int* nold;      // [T][M][L]
+  LDS double* dmi;    // [T][M][L]
+  LDS double* xi;     // [M]
+  LDS double* eta;    // [M]
+  LDS double* pmask;  // [M]
+  LDS double* psacc;  // [M]
+  LDS double* peacc;  // [M]
+  LDS double* Racc;   // [M]
+  LDS double* dmax;   // [M]
+  LDS double* red;    // [kBlock] scratch for reductions
+  LDS double* tmp;    // [M+2] reduction results
 };
 
 __host__ __device__ inline size_t align8(size_t x) { return (x + 7) & ~size_t(7); }
 
 // Lays the arrays out from `base`; returns the bytes used.  With base ==
 // nullptr it only measures (host side).
-__host__ __device__ inline size_t carve_lds(char* base, int M, int K, int L, int T, Lds* out) {
+__host__ __device__ inline size_t carve_lds(LDS char* base, int M, int K, int L, int T, Lds* out) {
   Lds s;
   size_t o = 0;
   auto take = [&](size_t bytes) {
-    char* p = base ? base + o : nullptr;
+    LDS char* p = base ? base + o : nullptr;
     o += align8(bytes);
     return p;
   };
   const size_t TM = (size_t)T * M, TML = TM * L, TK = (size_t)T * K;
-  s.g = (float*)take(sizeof(float) * TM * K);
-  s.u = (double*)take(sizeof(double) * TM * K);
-  s.Sacc = (double*)take(sizeof(double) * M * K);
-  s.mu = (double*)take(sizeof(double) * K);
-  s.racc = (double*)take(sizeof(double) * K);
-  s.rhacc = (double*)take(sizeof(double) * K);
-  s.Al = (int*)take(sizeof(int) * K);
-  s.el = (int*)take(sizeof(int) * K);
-  s.grp = (int*)take(sizeof(int) * K);
-  s.grpk = (int*)take(sizeof(int) * K);
-  s.grp_off = (int*)take(sizeof(int) * (M + 1));
-  s.wcnt = (int*)take(sizeof(int) * (kBlock / 64) * M);
-  s.gcur = (int*)take(sizeof(int) * M);
-  s.Hc = (double*)take(sizeof(double) * TK);
-  s.pic = (double*)take(sizeof(double) * TK);
-  s.rk = (double*)take(sizeof(double) * TK);
-  s.rhk = (double*)take(sizeof(double) * TK);
-  s.su = (int*)take(sizeof(int) * TML);
-  s.sp = (double*)take(sizeof(double) * TML);
-  s.sal = (double*)take(sizeof(double) * TML);
-  s.sbe = (double*)take(sizeof(double) * TML);
-  s.szs = (double*)take(sizeof(double) * TML * L);
-  s.szn = (double*)take(sizeof(double) * TML * L);
-  s.vcnt = (int*)take(sizeof(int) * TM);
-  s.vslot = (int*)take(sizeof(int) * TML);
-  s.vuser = (int*)take(sizeof(int) * TML);
-  s.vu = (double*)take(sizeof(double) * TML);
-  s.vpre = (double*)take(sizeof(double) * TM * (L + 1));
-  s.vc = (double*)take(sizeof(double) * TML);
-  s.vcg = (double*)take(sizeof(double) * TML);
-  s.vr = (double*)take(sizeof(double) * TML);
-  s.vT = (double*)take(sizeof(double) * TM * (L + 1));
-  s.Ptot = (double*)take(sizeof(double) * TM);
-  s.pinter = (double*)take(sizeof(double) * TM);
-  s.psic = (double*)take(sizeof(double) * TM);
-  s.tps = (double*)take(sizeof(double) * TM);
-  s.tpe = (double*)take(sizeof(double) * TM);
-  s.tR = (double*)take(sizeof(double) * TM);
-  s.frozen = (int*)take(sizeof(int) * TM);
-  s.churn = (int*)take(sizeof(int) * TM);
-  s.np = (int*)take(sizeof(int) * TM);
-  s.pij = (double*)take(sizeof(double) * TM * M);
-  s.contrib = (double*)take(sizeof(double) * TM * M);
-  s.chosen = (int*)take(sizeof(int) * TML);
-  s.nold = (int*)take(sizeof(int) * TML);
-  s.dmi = (double*)take(sizeof(double) * TML);
-  s.xi = (double*)take(sizeof(double) * M);
-  s.eta = (double*)take(sizeof(double) * M);
-  s.pmask = (double*)take(sizeof(double) * M);
-  s.psacc = (double*)take(sizeof(double) * M);
-  s.peacc = (double*)take(sizeof(double) * M);
-  s.Racc = (double*)take(sizeof(double) * M);
-  s.dmax = (double*)take(sizeof(double) * M);
-  s.red = (double*)take(sizeof(double) * kBlock);
-  s.tmp = (double*)take(sizeof(double) * (M + 2));
+  s.g = (LDS float*)take(sizeof(float) * TM * K);
+  s.u = (LDS double*)take(sizeof(double) * TM * K);
+  s.Sacc = (LDS double*)take(sizeof(double) * M * K);
+  s.mu = (LDS double*)take(sizeof(double) * K);
+  s.racc = (LDS double*)take(sizeof(double) * K);
+  s.rhacc = (LDS double*)take(sizeof(double) * K);
+  s.Al = (LDS int*)take(sizeof(int) * K);
+  s.el = (LDS int*)take(sizeof(int) * K);
+  s.grp = (LDS int*)take(sizeof(int) * K);
+  s.grpk = (LDS int*)take(sizeof(int) * K);
+  s.grp_off = (LDS int*)take(sizeof(int) * (M + 1));
+  s.wcnt = (LDS int*)take(sizeof(int) * (kBlock / 64) * M);
+  s.gcur = (LDS int*)take(sizeof(int) * M);
+  s.Hc = (LDS double*)take(sizeof(double) * TK);
+  s.pic = (LDS double*)take(sizeof(double) * TK);
+  s.rk = (LDS double*)take(sizeof(double) * TK);
+  s.rhk = (LDS double*)take(sizeof(double) * TK);
+  s.su = (LDS int*)take(sizeof(int) * TML);
+  s.sp = (LDS double*)take(sizeof(double) * TML);
+  s.sal = (LDS double*)take(sizeof(double) * TML);
+  s.sbe = (LDS double*)take(sizeof(double) * TML);
+  s.szs = (LDS double*)take(sizeof(double) * TML * L);
+  s.szn = (LDS double*)take(sizeof(double) * TML * L);
+  s.vcnt = (LDS int*)take(sizeof(int) * TM);
+  s.vslot = (LDS int*)take(sizeof(int) * TML);
+  s.vuser = (LDS int*)take(sizeof(int) * TML);
+  s.vu = (LDS double*)take(sizeof(double) * TML);
+  s.vpre = (LDS double*)take(sizeof(double) * TM * (L + 1));
+  s.vc = (LDS double*)take(sizeof(double) * TML);
+  s.vcg = (LDS double*)take(sizeof(double) * TML);
+  s.vr = (LDS double*)take(sizeof(double) * TML);
+  s.vT = (LDS double*)take(sizeof(double) * TM * (L + 1));
+  s.Ptot = (LDS double*)take(sizeof(double) * TM);
+  s.pinter = (LDS double*)take(sizeof(double) * TM);
+  s.psic = (LDS double*)take(sizeof(double) * TM);
+  s.tps = (LDS double*)take(sizeof(double) * TM);
+  s.tpe = (LDS double*)take(sizeof(double) * TM);
+  s.tR = (LDS double*)take(sizeof(double) * TM);
+  s.frozen = (LDS int*)take(sizeof(int) * TM);
+  s.churn = (LDS int*)take(sizeof(int) * TM);
+  s.np = (LDS int*)take(sizeof(int) * TM);
+  s.pij = (LDS double*)take(sizeof(double) * TM * M);
+  s.contrib = (LDS double*)take(sizeof(double) * TM * M);
+  s.chosen = (LDS int*)take(sizeof(int) * TML);
+  s.nold = (LDS int*)take(sizeof(int) * TML);
+  s.dmi = (LDS double*)take(sizeof(double) * TML);
+  s.xi = (LDS double*)take(sizeof(double) * M);
+  s.eta = (LDS double*)take(sizeof(double) * M);
+  s.pmask = (LDS double*)take(sizeof(double) * M);
+  s.psacc = (LDS double*)take(sizeof(double) * M);
+  s.peacc = (LDS double*)take(sizeof(double) * M);
+  s.Racc = (LDS double*)take(sizeof(double) * M);
+  s.dmax = (LDS double*)take(sizeof(double) * M);
+  s.red = (LDS double*)take(sizeof(double) * kBlock);
+  s.tmp = (LDS double*)take(sizeof(double) * (M + 2));
   if (out) *out = s;
   return o;
 }
@@ -755,7 +760,7 @@ __device__ void write_partials(const Drop& d, const Lds& s, int b) {
 // over chunks.  Result in out[m] (LDS), visible to all threads on return.
 template <bool kMax>
 __device__ void reduce_groups(Lds& s, const double* base, int G, int M, size_t gs, size_t ms,
-                              double* out) {
+                              LDS double* out) {
   const int tid = threadIdx.x, nth = blockDim.x;
   const int chunks = nth / M;
   if (tid < M * chunks) {
@@ -900,8 +905,10 @@ __device__ void control(const Drop& d, const Sched& sc, Ctrl& c) {
 
 __global__ void __launch_bounds__(kBlock) solve_kernel(Drop d, Sched sc) {
   extern __shared__ __align__(16) char smem[];
-  Lds s;
-  carve_lds(smem, d.M, d.K, d.L, sc.tile, &s);
+  __shared__ Lds s_tab;
+  if (threadIdx.x == 0) carve_lds((LDS char*)smem, d.M, d.K, d.L, sc.tile, &s_tab);
+  __syncthreads();
+  Lds& s = s_tab;
   cg::grid_group grid = cg::this_grid();
   const int b = blockIdx.x, G = gridDim.x;
   Ctrl c = *d.ctrl;
@@ -1037,11 +1044,12 @@ __device__ void block_reduce(const Drop& d, const Sched& sc, const Ctrl& c, Lds&
 
 // Persistent batched solver: workgroups take drops from an atomic queue (in
 // the host's order: largest estimated work first) and solve each completely.
-__global__ void __launch_bounds__(kBlock) batch_kernel(const Drop* drops, const int* order, int B,
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) batch_kernel(const Drop* drops, const int* order, int B,
                                                       Sched sc, int* queue, Ctrl* ctrls) {
   extern __shared__ __align__(16) char smem[];
   __shared__ int s_idx, s_changes;
   __shared__ Ctrl s_c;
+  __shared__ Lds s_tab;
   for (;;) {
     if (threadIdx.x == 0) s_idx = atomicAdd(queue, 1);
     __syncthreads();
@@ -1051,8 +1059,9 @@ __global__ void __launch_bounds__(kBlock) batch_kernel(const Drop* drops, const 
     const Drop& d = drops[order[idx]];
     Sched sd = sc;
     sd.tile = d.tile;
-    Lds s;
-    carve_lds(smem, d.M, d.K, d.L, sd.tile, &s);
+    if (threadIdx.x == 0) carve_lds((LDS char*)smem, d.M, d.K, d.L, sd.tile, &s_tab);
+    __syncthreads();
+    Lds& s = s_tab;
     if (!d.preset) block_cold_start(d, s);
     if (threadIdx.x == 0) {
       Ctrl c0;
@@ -1244,7 +1253,8 @@ int validate(const alloc_problem* pb, const alloc_params* prm) {
   if (!(pb->noise_w > 0) || !(pb->bw_hz > 0) || !(pb->packet_bits > 0)) return ALLOC_EINVAL;
   if (!std::isfinite(pb->noise_w)) return ALLOC_EINVAL;
   if (pb->M > kMaxM || pb->l > kMaxL || pb->K > kMaxK || pb->M * pb->K > kMaxMK) return ALLOC_ETOOBIG;
-  if (prm->sweeps_per_dinkelbach < 1 || prm->max_dinkelbach < 1 || prm->max_groups < 0 || prm->tile < 0)
+  if (prm->sweeps_per_dinkelbach < 1 || prm->max_dinkelbach < 1 || prm->max_groups < 0 || prm->tile < 0 ||
+      prm->lds_kb < 0)
     return ALLOC_EINVAL;
   for (int m = 0; m < pb->M; ++m) {
     if (!(pb->pmax_w[m] > 0) || !std::isfinite(pb->pmax_w[m])) return ALLOC_EINVAL;
@@ -1293,6 +1303,7 @@ void alloc_params_default(alloc_params* p) {
   p->flags = 0;
   p->max_groups = 0;
   p->tile = 0;
+  p->lds_kb = 0;
 }
 
 int alloc_ctx_set_timing(alloc_ctx* ctx, int enable) {
@@ -1333,7 +1344,7 @@ int alloc_ctx_create(int device, void* hip_stream, alloc_ctx** out) {
     return ALLOC_EDEVICE;
   }
   if (hipFuncSetAttribute((const void*)solve_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)c->lds_max) != hipSuccess) {
+                          (int)c->lds_max - 1024) != hipSuccess) {
     delete c;
     return ALLOC_EDEVICE;
   }
@@ -1361,7 +1372,8 @@ int solve_one(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, 
   int rc = validate(pb, prm);
   if (rc != ALLOC_OK) return rc;
   const int M = pb->M, N = pb->N, K = pb->K, L = pb->l, NP = L * (L - 1) / 2;
-  if (carve_lds(nullptr, M, K, L, 1, nullptr) > ctx->lds_max) return ALLOC_ETOOBIG;
+  const size_t budget = ctx->lds_max - 1024;  // the kernel's static LDS stays below 1 KB
+  if (carve_lds(nullptr, M, K, L, 1, nullptr) > budget) return ALLOC_ETOOBIG;
   if (hipSetDevice(ctx->device) != hipSuccess) return ALLOC_EDEVICE;
   const bool gain_dev = prm->flags & ALLOC_GAIN_ON_DEVICE;
   const bool out_dev = prm->flags & ALLOC_OUT_ON_DEVICE;
@@ -1377,7 +1389,7 @@ int solve_one(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, 
   if (prm->max_groups > 0) G = std::min(G, prm->max_groups);
   const int nb = (N + G - 1) / G;
   int T = prm->tile > 0 ? std::min(prm->tile, nb) : nb;
-  while (T > 1 && carve_lds(nullptr, M, K, L, T, nullptr) > ctx->lds_max) --T;
+  while (T > 1 && carve_lds(nullptr, M, K, L, T, nullptr) > budget) --T;
   const size_t lds = carve_lds(nullptr, M, K, L, T, nullptr);
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)solve_kernel, kBlock, lds) !=
@@ -1591,10 +1603,39 @@ int solve_one(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, 
   return ALLOC_OK;
 }
 
-int solve_batch(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc_params* prm,
-                const alloc_warm* warms, const WarmFn* fn, alloc_result* results) {
-  if (!ctx || !probs || !results || B < 1 || !prm) return ALLOC_EINVAL;
-  if (warms && fn) return ALLOC_EINVAL;
+// Host side of one batched solve: the packed device layout of every drop's
+// inputs, state and outputs, the drop descriptors and the launch shape.
+struct BatchOff {
+  size_t G, psi, el, pmax, eta, pmask, w, A, sel, p, al, be, zs, xi, zeta, chs, cha, ur, os, op, oz;
+};
+
+struct BatchPlan {
+  int B = 0;
+  char* ws = nullptr;
+  bool gain_dev = false;
+  size_t oDrops = 0, oOrder = 0, oQueue = 0, oCtrls = 0, out_begin = 0, out_end = 0;
+  size_t oISnr = 0, oIP0s = 0, oIP0 = 0, oIXi = 0, oIZ = 0;
+  std::vector<BatchOff> off;
+  std::vector<Drop> drops;
+  std::vector<int> order;
+  std::vector<std::vector<double>> psis;
+  std::vector<std::vector<uint8_t>> els;
+  std::vector<int> Ms, Ns, Ks, Ls;
+  Sched sc;
+  int grid = 0;
+  size_t lds = 0;
+};
+
+__global__ void reset_queue_kernel(int* q) {
+  if (threadIdx.x == 0) *q = 0;
+}
+
+// Validates, lays out and uploads the drops' inputs into *buf (grown to fit,
+// *bytes its size); warm-start scratch is reserved when `warm` is set
+// (host_n3: largest p0 staged from the host, host_mult: multipliers staged).
+int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc_params* prm, bool warm,
+                  size_t host_n3, bool host_mult, char** buf, size_t* bytes, BatchPlan& P) {
+  if (!ctx || !probs || B < 1 || !prm) return ALLOC_EINVAL;
   if (prm->flags & ALLOC_OUT_ON_DEVICE) return ALLOC_EINVAL;
   const bool gain_dev = prm->flags & ALLOC_GAIN_ON_DEVICE;
   for (int b = 0; b < B; ++b) {
@@ -1608,203 +1649,160 @@ int solve_batch(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc_p
     }
   }
   if (hipSetDevice(ctx->device) != hipSuccess) return ALLOC_EDEVICE;
-  const size_t budget = ctx->lds_max - 1024;  // the kernel's static LDS stays below 1 KB
+  // LDS per workgroup: the whole CU unless capped (the kernel's static LDS stays below 1 KB)
+  size_t budget = ctx->lds_max - 1024;
+  if (prm->lds_kb > 0) budget = std::min(budget, (size_t)prm->lds_kb * 1024 - 1024);
   for (int b = 0; b < B; ++b)
     if (carve_lds(nullptr, probs[b].M, probs[b].K, probs[b].l, 1, nullptr) > budget) return ALLOC_ETOOBIG;
 
-  // workspace: per drop inputs, state and outputs, packed
-  struct Off {
-    size_t G, psi, el, pmax, eta, pmask, w, A, sel, p, al, be, zs, xi, zeta, chs, cha, ur, os, op, oz;
-  };
-  std::vector<Off> off(B);
+  P.B = B;
+  P.gain_dev = gain_dev;
+  P.off.assign(B, BatchOff{});
   size_t tot = 0;
-  auto add = [&](size_t bytes) {
+  auto add = [&](size_t n) {
     const size_t o = tot;
-    tot += (bytes + 255) & ~size_t(255);
+    tot += (n + 255) & ~size_t(255);
     return o;
   };
-  const size_t oDrops = add(sizeof(Drop) * B);
-  const size_t oOrder = add(sizeof(int) * B);
-  const size_t oQueue = add(sizeof(int));
-  const size_t oCtrls = add(sizeof(Ctrl) * B);
+  P.oDrops = add(sizeof(Drop) * B);
+  P.oOrder = add(sizeof(int) * B);
+  P.oQueue = add(sizeof(int));
+  P.oCtrls = add(sizeof(Ctrl) * B);
   const size_t small_begin = tot;
   for (int b = 0; b < B; ++b) {
     const alloc_problem& pb = probs[b];
     const size_t M = pb.M, K = pb.K;
-    off[b].psi = add(sizeof(double) * K);
-    off[b].el = add(K);
-    off[b].pmax = add(sizeof(double) * M);
-    off[b].eta = add(sizeof(double) * M);
-    off[b].pmask = add(sizeof(double) * M);
-    off[b].w = add(pb.weight ? sizeof(double) * M * K : 0);
+    P.off[b].psi = add(sizeof(double) * K);
+    P.off[b].el = add(K);
+    P.off[b].pmax = add(sizeof(double) * M);
+    P.off[b].eta = add(sizeof(double) * M);
+    P.off[b].pmask = add(sizeof(double) * M);
+    P.off[b].w = add(pb.weight ? sizeof(double) * M * K : 0);
   }
   const size_t small_end = tot;
-  const size_t out_begin = tot;
+  P.out_begin = tot;
   for (int b = 0; b < B; ++b) {
     const alloc_problem& pb = probs[b];
     const size_t M = pb.M, N = pb.N, K = pb.K, L = pb.l, NP = L * (L - 1) / 2;
-    off[b].os = add(sizeof(int) * M * N * L);
-    off[b].op = add(sizeof(double) * M * N * L);
-    off[b].oz = add(sizeof(double) * M * N * (NP > 0 ? NP : 1));
-    off[b].A = add(sizeof(int) * K);
-    off[b].xi = add(sizeof(double) * M);
-    off[b].zeta = add(sizeof(double) * K);
-    off[b].ur = add(sizeof(double) * K);
+    P.off[b].os = add(sizeof(int) * M * N * L);
+    P.off[b].op = add(sizeof(double) * M * N * L);
+    P.off[b].oz = add(sizeof(double) * M * N * (NP > 0 ? NP : 1));
+    P.off[b].A = add(sizeof(int) * K);
+    P.off[b].xi = add(sizeof(double) * M);
+    P.off[b].zeta = add(sizeof(double) * K);
+    P.off[b].ur = add(sizeof(double) * K);
   }
-  const size_t out_end = tot;
-  // scratch of the warm-start initialisation, reused drop after drop
-  size_t max_mk = 1, max_m = 1, max_k = 1, max_n3 = 0;
+  P.out_end = tot;
+  size_t max_mk = 1, max_m = 1, max_k = 1;
   for (int b = 0; b < B; ++b) {
     max_mk = std::max(max_mk, (size_t)probs[b].M * probs[b].K);
     max_m = std::max(max_m, (size_t)probs[b].M);
     max_k = std::max(max_k, (size_t)probs[b].K);
-    if (warms && warms[b].p0) max_n3 = std::max(max_n3, (size_t)probs[b].M * probs[b].N * probs[b].K);
   }
-  const bool any_warm = warms || fn;
-  const size_t oISnr = add(any_warm ? sizeof(double) * max_mk : 0);
-  const size_t oIP0s = add(any_warm ? sizeof(double) * max_mk : 0);
-  const size_t oIP0 = add(sizeof(double) * max_n3);
-  const size_t oIXi = add(warms ? sizeof(double) * max_m : 0);
-  const size_t oIZ = add(warms ? sizeof(double) * max_k : 0);
+  P.oISnr = add(warm ? sizeof(double) * max_mk : 0);
+  P.oIP0s = add(warm ? sizeof(double) * max_mk : 0);
+  P.oIP0 = add(sizeof(double) * host_n3);
+  P.oIXi = add(host_mult ? sizeof(double) * max_m : 0);
+  P.oIZ = add(host_mult ? sizeof(double) * max_k : 0);
   for (int b = 0; b < B; ++b) {
     const alloc_problem& pb = probs[b];
     const size_t M = pb.M, N = pb.N, K = pb.K, L = pb.l;
-    off[b].sel = add(sizeof(int) * M * N * L);
-    off[b].p = add(sizeof(double) * M * N * L);
-    off[b].al = add(sizeof(double) * M * N * L);
-    off[b].be = add(sizeof(double) * M * N * L);
-    off[b].zs = add(sizeof(double) * M * N * L * L);
-    off[b].chs = add(sizeof(int) * M * N);
-    off[b].cha = add(sizeof(int) * K);
-    off[b].G = add(gain_dev ? 0 : sizeof(float) * M * N * K);
+    P.off[b].sel = add(sizeof(int) * M * N * L);
+    P.off[b].p = add(sizeof(double) * M * N * L);
+    P.off[b].al = add(sizeof(double) * M * N * L);
+    P.off[b].be = add(sizeof(double) * M * N * L);
+    P.off[b].zs = add(sizeof(double) * M * N * L * L);
+    P.off[b].chs = add(sizeof(int) * M * N);
+    P.off[b].cha = add(sizeof(int) * K);
+    P.off[b].G = add(gain_dev ? 0 : sizeof(float) * M * N * K);
   }
-  if (tot > ctx->ws_bytes) {
-    if (ctx->ws) (void)hipFree(ctx->ws);
-    ctx->ws = nullptr;
-    ctx->ws_bytes = 0;
-    if (hipMalloc((void**)&ctx->ws, tot) != hipSuccess) return ALLOC_ENOMEM;
-    ctx->ws_bytes = tot;
+  if (tot > *bytes) {
+    if (*buf) (void)hipFree(*buf);
+    *buf = nullptr;
+    *bytes = 0;
+    if (hipMalloc((void**)buf, tot) != hipSuccess) return ALLOC_ENOMEM;
+    *bytes = tot;
   }
-  char* ws = ctx->ws;
+  char* ws = *buf;
+  P.ws = ws;
   hipStream_t st = ctx->stream;
 
   // host image of the small inputs and the drop descriptors
   std::vector<char> img(small_end - small_begin, 0);
-  std::vector<Drop> drops(B);
-  std::vector<double> psi_all;
-  std::vector<std::vector<double>> psis(B);
-  std::vector<std::vector<uint8_t>> els(B);
+  P.drops.assign(B, Drop{});
+  P.psis.assign(B, {});
+  P.els.assign(B, {});
+  P.Ms.resize(B);
+  P.Ns.resize(B);
+  P.Ks.resize(B);
+  P.Ls.resize(B);
   for (int b = 0; b < B; ++b) {
     const alloc_problem& pb = probs[b];
     const int M = pb.M, N = pb.N, K = pb.K, L = pb.l;
-    double* psi = (double*)(img.data() + off[b].psi - small_begin);
-    uint8_t* el = (uint8_t*)(img.data() + off[b].el - small_begin);
-    psis[b].assign(K, 0.0);
-    els[b].assign(K, 0);
+    const BatchOff& o = P.off[b];
+    P.Ms[b] = M;
+    P.Ns[b] = N;
+    P.Ks[b] = K;
+    P.Ls[b] = L;
+    double* psi = (double*)(img.data() + o.psi - small_begin);
+    uint8_t* el = (uint8_t*)(img.data() + o.el - small_begin);
+    P.psis[b].assign(K, 0.0);
+    P.els[b].assign(K, 0);
     for (int k = 0; k < K; ++k) {
       el[k] = pb.user_type[k] == 0;
       psi[k] = el[k] ? 0.0 : min_rate(pb.arrival_bps[k], pb.delay_s[k], pb.packet_bits, pb.bw_hz);
-      psis[b][k] = psi[k];
-      els[b][k] = el[k];
+      P.psis[b][k] = psi[k];
+      P.els[b][k] = el[k];
     }
-    memcpy(img.data() + off[b].pmax - small_begin, pb.pmax_w, sizeof(double) * M);
-    memcpy(img.data() + off[b].eta - small_begin, pb.eta, sizeof(double) * M);
-    double* pm = (double*)(img.data() + off[b].pmask - small_begin);
+    memcpy(img.data() + o.pmax - small_begin, pb.pmax_w, sizeof(double) * M);
+    memcpy(img.data() + o.eta - small_begin, pb.eta, sizeof(double) * M);
+    double* pm = (double*)(img.data() + o.pmask - small_begin);
     for (int m = 0; m < M; ++m) pm[m] = pb.pmask_w ? pb.pmask_w[m] : pb.pmax_w[m] / N;
-    if (pb.weight) memcpy(img.data() + off[b].w - small_begin, pb.weight, sizeof(double) * M * K);
-    Drop& d = drops[b];
+    if (pb.weight) memcpy(img.data() + o.w - small_begin, pb.weight, sizeof(double) * M * K);
+    Drop& d = P.drops[b];
     memset(&d, 0, sizeof d);
     d.M = M; d.N = N; d.K = K; d.L = L; d.NP = L * (L - 1) / 2;
-    d.G = gain_dev ? pb.gain : (const float*)(ws + off[b].G);
-    d.psi = (const double*)(ws + off[b].psi);
-    d.elastic = (const uint8_t*)(ws + off[b].el);
-    d.pmax = (const double*)(ws + off[b].pmax);
-    d.eta = (const double*)(ws + off[b].eta);
-    d.pmask = (const double*)(ws + off[b].pmask);
-    d.w = pb.weight ? (const double*)(ws + off[b].w) : nullptr;
+    d.G = gain_dev ? pb.gain : (const float*)(ws + o.G);
+    d.psi = (const double*)(ws + o.psi);
+    d.elastic = (const uint8_t*)(ws + o.el);
+    d.pmax = (const double*)(ws + o.pmax);
+    d.eta = (const double*)(ws + o.eta);
+    d.pmask = (const double*)(ws + o.pmask);
+    d.w = pb.weight ? (const double*)(ws + o.w) : nullptr;
     d.sigma = pb.noise_w;
     d.pstatic = pb.p_fiber_hpn + (M - 1) * pb.p_fiber_lpn + (M - 1) * pb.p_circuit_lpn + pb.p_circuit_hpn;
-    d.A = (int*)(ws + off[b].A);
-    d.sel = (int*)(ws + off[b].sel);
-    d.p = (double*)(ws + off[b].p);
-    d.al = (double*)(ws + off[b].al);
-    d.be = (double*)(ws + off[b].be);
-    d.zs = (double*)(ws + off[b].zs);
-    d.xi = (double*)(ws + off[b].xi);
-    d.zeta = (double*)(ws + off[b].zeta);
-    d.churn_sel = (int*)(ws + off[b].chs);
-    d.churn_A = (int*)(ws + off[b].cha);
-    d.user_rate = (double*)(ws + off[b].ur);
-    d.out_sel = (int*)(ws + off[b].os);
-    d.out_p = (double*)(ws + off[b].op);
-    d.out_zs = (double*)(ws + off[b].oz);
+    d.A = (int*)(ws + o.A);
+    d.sel = (int*)(ws + o.sel);
+    d.p = (double*)(ws + o.p);
+    d.al = (double*)(ws + o.al);
+    d.be = (double*)(ws + o.be);
+    d.zs = (double*)(ws + o.zs);
+    d.xi = (double*)(ws + o.xi);
+    d.zeta = (double*)(ws + o.zeta);
+    d.churn_sel = (int*)(ws + o.chs);
+    d.churn_A = (int*)(ws + o.cha);
+    d.user_rate = (double*)(ws + o.ur);
+    d.out_sel = (int*)(ws + o.os);
+    d.out_p = (double*)(ws + o.op);
+    d.out_zs = (double*)(ws + o.oz);
     int T = prm->tile > 0 ? std::min(prm->tile, N) : N;
     while (T > 1 && carve_lds(nullptr, M, K, L, T, nullptr) > budget) --T;
     d.tile = T;
   }
   // largest estimated work first
-  std::vector<int> order(B);
-  for (int b = 0; b < B; ++b) order[b] = b;
-  std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+  P.order.resize(B);
+  for (int b = 0; b < B; ++b) P.order[b] = b;
+  std::stable_sort(P.order.begin(), P.order.end(), [&](int x, int y) {
     return (double)probs[x].M * probs[x].N * probs[x].K > (double)probs[y].M * probs[y].N * probs[y].K;
   });
   bool ok = hipMemcpyAsync(ws + small_begin, img.data(), img.size(), hipMemcpyHostToDevice, st) == hipSuccess;
   if (!gain_dev)
     for (int b = 0; b < B && ok; ++b)
-      ok = hipMemcpyAsync(ws + off[b].G, probs[b].gain,
-                          sizeof(float) * probs[b].M * probs[b].N * probs[b].K, hipMemcpyHostToDevice,
-                          st) == hipSuccess;
+      ok = hipMemcpyAsync(ws + P.off[b].G, probs[b].gain, sizeof(float) * probs[b].M * probs[b].N * probs[b].K,
+                          hipMemcpyHostToDevice, st) == hipSuccess;
   if (!ok) return ALLOC_EDEVICE;
 
-  // warm starts: the initial state of such drops is written here, in order,
-  // with the single-drop initialisation kernels
-  for (int b = 0; b < B && any_warm; ++b) {
-    DevWarm w{nullptr, nullptr, nullptr};
-    if (fn) {
-      const int rc = (*fn)(b, &w);
-      if (rc != ALLOC_OK) return rc;
-    } else {
-      const alloc_problem& pb = probs[b];
-      const size_t n3 = (size_t)pb.M * pb.N * pb.K;
-      auto up = [&](size_t o, const double* src, size_t n) {
-        return hipMemcpyAsync(ws + o, src, sizeof(double) * n, hipMemcpyHostToDevice, st) == hipSuccess;
-      };
-      if (warms[b].p0) {
-        if (!up(oIP0, warms[b].p0, n3)) return ALLOC_EDEVICE;
-        w.p0 = (const double*)(ws + oIP0);
-      }
-      if (warms[b].xi0) {
-        if (!up(oIXi, warms[b].xi0, pb.M)) return ALLOC_EDEVICE;
-        w.xi0 = (const double*)(ws + oIXi);
-      }
-      if (warms[b].zeta0) {
-        if (!up(oIZ, warms[b].zeta0, pb.K)) return ALLOC_EDEVICE;
-        w.zeta0 = (const double*)(ws + oIZ);
-      }
-    }
-    if (!w.p0 && !w.xi0 && !w.zeta0) continue;
-    Drop& d = drops[b];
-    const int tb = 256, M = d.M, N = d.N, K = d.K;
-    double* snr = (double*)(ws + oISnr);
-    double* p0s = w.p0 ? (double*)(ws + oIP0s) : nullptr;
-    hipLaunchKernelGGL(cold_assoc_kernel, dim3((M * K + tb - 1) / tb), dim3(tb), 0, st, d, snr);
-    if (w.p0) hipLaunchKernelGGL(p0_sum_kernel, dim3((M * K + tb - 1) / tb), dim3(tb), 0, st, d, w.p0, p0s);
-    hipLaunchKernelGGL(cold_pick_kernel, dim3((K + tb - 1) / tb), dim3(tb), 0, st, d, (const double*)snr,
-                       (const double*)p0s);
-    hipLaunchKernelGGL(cold_select_kernel, dim3((M * N + tb - 1) / tb), dim3(tb), 0, st, d, w.p0);
-    hipLaunchKernelGGL(init_mult_kernel, dim3((std::max(M, K) + tb - 1) / tb), dim3(tb), 0, st, d, w.xi0,
-                       w.zeta0);
-    if (hipGetLastError() != hipSuccess) return ALLOC_EDEVICE;
-    d.preset = 1;
-    d.start_eval = w.p0 != nullptr;
-  }
-  static const int zero = 0;
-  ok = hipMemcpyAsync(ws + oDrops, drops.data(), sizeof(Drop) * B, hipMemcpyHostToDevice, st) == hipSuccess &&
-       hipMemcpyAsync(ws + oOrder, order.data(), sizeof(int) * B, hipMemcpyHostToDevice, st) == hipSuccess &&
-       hipMemcpyAsync(ws + oQueue, &zero, sizeof(int), hipMemcpyHostToDevice, st) == hipSuccess;
-  if (!ok) return ALLOC_EDEVICE;
-
-  Sched sc;
+  Sched& sc = P.sc;
   sc.max_d = prm->max_dinkelbach;
   sc.sweeps = prm->sweeps_per_dinkelbach;
   sc.refit_period = prm->refit_period;
@@ -1816,49 +1814,109 @@ int solve_batch(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc_p
   sc.tile = 1;
   int per_cu = 0;
   if (hipFuncSetAttribute((const void*)batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)budget) != hipSuccess ||
+                          (int)(ctx->lds_max - 1024)) != hipSuccess ||
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)batch_kernel, kBlock, budget) !=
           hipSuccess)
     return ALLOC_EDEVICE;
   if (per_cu < 1) return ALLOC_ETOOBIG;
-  int grid = std::min(B, per_cu * ctx->cus);
-  if (prm->max_groups > 0) grid = std::min(grid, prm->max_groups);
-  if (ctx->timing && hipEventRecord(ctx->ev0, st) != hipSuccess) return ALLOC_EDEVICE;
-  hipLaunchKernelGGL(batch_kernel, dim3(grid), dim3(kBlock), budget, st, (const Drop*)(ws + oDrops),
-                     (const int*)(ws + oOrder), B, sc, (int*)(ws + oQueue), (Ctrl*)(ws + oCtrls));
-  if (hipGetLastError() != hipSuccess) return ALLOC_EDEVICE;
-  if (ctx->timing && hipEventRecord(ctx->ev1, st) != hipSuccess) return ALLOC_EDEVICE;
+  P.lds = budget;
+  P.grid = std::min(B, per_cu * ctx->cus);
+  if (prm->max_groups > 0) P.grid = std::min(P.grid, prm->max_groups);
+  return ALLOC_OK;
+}
 
-  // outputs: one copy of the packed region, scattered on the host
-  std::vector<char> out(out_end - out_begin);
-  std::vector<Ctrl> ctrls(B);
-  if (hipMemcpyAsync(out.data(), ws + out_begin, out.size(), hipMemcpyDeviceToHost, st) != hipSuccess ||
-      hipMemcpyAsync(ctrls.data(), ws + oCtrls, sizeof(Ctrl) * B, hipMemcpyDeviceToHost, st) != hipSuccess ||
+// Writes the initial state of warm-started drops with the single-drop
+// initialisation kernels, in drop order (before the descriptors go up).
+int batch_warm(alloc_ctx* ctx, const alloc_problem* probs, const alloc_warm* warms, const WarmFn* fn,
+               BatchPlan& P) {
+  hipStream_t st = ctx->stream;
+  char* ws = P.ws;
+  for (int b = 0; b < P.B; ++b) {
+    DevWarm w{nullptr, nullptr, nullptr};
+    if (fn) {
+      const int rc = (*fn)(b, &w);
+      if (rc != ALLOC_OK) return rc;
+    } else {
+      const alloc_problem& pb = probs[b];
+      const size_t n3 = (size_t)pb.M * pb.N * pb.K;
+      auto up = [&](size_t o, const double* src, size_t n) {
+        return hipMemcpyAsync(ws + o, src, sizeof(double) * n, hipMemcpyHostToDevice, st) == hipSuccess;
+      };
+      if (warms[b].p0) {
+        if (!up(P.oIP0, warms[b].p0, n3)) return ALLOC_EDEVICE;
+        w.p0 = (const double*)(ws + P.oIP0);
+      }
+      if (warms[b].xi0) {
+        if (!up(P.oIXi, warms[b].xi0, pb.M)) return ALLOC_EDEVICE;
+        w.xi0 = (const double*)(ws + P.oIXi);
+      }
+      if (warms[b].zeta0) {
+        if (!up(P.oIZ, warms[b].zeta0, pb.K)) return ALLOC_EDEVICE;
+        w.zeta0 = (const double*)(ws + P.oIZ);
+      }
+    }
+    if (!w.p0 && !w.xi0 && !w.zeta0) continue;
+    Drop& d = P.drops[b];
+    const int tb = 256, M = d.M, N = d.N, K = d.K;
+    double* snr = (double*)(ws + P.oISnr);
+    double* p0s = w.p0 ? (double*)(ws + P.oIP0s) : nullptr;
+    hipLaunchKernelGGL(cold_assoc_kernel, dim3((M * K + tb - 1) / tb), dim3(tb), 0, st, d, snr);
+    if (w.p0) hipLaunchKernelGGL(p0_sum_kernel, dim3((M * K + tb - 1) / tb), dim3(tb), 0, st, d, w.p0, p0s);
+    hipLaunchKernelGGL(cold_pick_kernel, dim3((K + tb - 1) / tb), dim3(tb), 0, st, d, (const double*)snr,
+                       (const double*)p0s);
+    hipLaunchKernelGGL(cold_select_kernel, dim3((M * N + tb - 1) / tb), dim3(tb), 0, st, d, w.p0);
+    hipLaunchKernelGGL(init_mult_kernel, dim3((std::max(M, K) + tb - 1) / tb), dim3(tb), 0, st, d, w.xi0,
+                       w.zeta0);
+    if (hipGetLastError() != hipSuccess) return ALLOC_EDEVICE;
+    d.preset = 1;
+    d.start_eval = w.p0 != nullptr;
+  }
+  return ALLOC_OK;
+}
+
+int batch_upload(hipStream_t st, const BatchPlan& P) {
+  const bool ok =
+      hipMemcpyAsync(P.ws + P.oDrops, P.drops.data(), sizeof(Drop) * P.B, hipMemcpyHostToDevice, st) ==
+          hipSuccess &&
+      hipMemcpyAsync(P.ws + P.oOrder, P.order.data(), sizeof(int) * P.B, hipMemcpyHostToDevice, st) == hipSuccess;
+  return ok ? ALLOC_OK : ALLOC_EDEVICE;
+}
+
+// The batched solve proper: queue reset and the persistent kernel (no host
+// copies or memsets, so the pair can be captured into a graph).
+int batch_enqueue(hipStream_t st, const BatchPlan& P) {
+  hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, st, (int*)(P.ws + P.oQueue));
+  hipLaunchKernelGGL(batch_kernel, dim3(P.grid), dim3(kBlock), P.lds, st, (const Drop*)(P.ws + P.oDrops),
+                     (const int*)(P.ws + P.oOrder), P.B, P.sc, (int*)(P.ws + P.oQueue),
+                     (Ctrl*)(P.ws + P.oCtrls));
+  return hipGetLastError() == hipSuccess ? ALLOC_OK : ALLOC_EDEVICE;
+}
+
+// Outputs: one copy of the packed region, scattered on the host.
+int batch_collect(hipStream_t st, const BatchPlan& P, alloc_result* results) {
+  std::vector<char> out(P.out_end - P.out_begin);
+  std::vector<Ctrl> ctrls(P.B);
+  if (hipMemcpyAsync(out.data(), P.ws + P.out_begin, out.size(), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(ctrls.data(), P.ws + P.oCtrls, sizeof(Ctrl) * P.B, hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return ALLOC_EDEVICE;
-  ctx->last_ms = -1.0;
-  if (ctx->timing) {
-    float ms = 0.0f;
-    if (hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1) != hipSuccess) return ALLOC_EDEVICE;
-    ctx->last_ms = ms;
-  }
-  for (int b = 0; b < B; ++b) {
-    const alloc_problem& pb = probs[b];
+  for (int b = 0; b < P.B; ++b) {
     alloc_result& r = results[b];
-    const size_t M = pb.M, N = pb.N, K = pb.K, L = pb.l, NP = L * (L - 1) / 2;
-    auto src = [&](size_t o) { return out.data() + (o - out_begin); };
-    if (r.sel) memcpy(r.sel, src(off[b].os), sizeof(int) * M * N * L);
-    if (r.slot_power) memcpy(r.slot_power, src(off[b].op), sizeof(double) * M * N * L);
-    if (r.zeta_sic && NP > 0) memcpy(r.zeta_sic, src(off[b].oz), sizeof(double) * M * N * NP);
-    if (r.rrh_of_user) memcpy(r.rrh_of_user, src(off[b].A), sizeof(int) * K);
-    if (r.xi) memcpy(r.xi, src(off[b].xi), sizeof(double) * M);
-    if (r.zeta) memcpy(r.zeta, src(off[b].zeta), sizeof(double) * K);
-    const double* ur = (const double*)src(off[b].ur);
+    const size_t M = P.Ms[b], N = P.Ns[b], K = P.Ks[b], L = P.Ls[b], NP = L * (L - 1) / 2;
+    const BatchOff& o = P.off[b];
+    auto src = [&](size_t off) { return out.data() + (off - P.out_begin); };
+    if (r.sel) memcpy(r.sel, src(o.os), sizeof(int) * M * N * L);
+    if (r.slot_power) memcpy(r.slot_power, src(o.op), sizeof(double) * M * N * L);
+    if (r.zeta_sic && NP > 0) memcpy(r.zeta_sic, src(o.oz), sizeof(double) * M * N * NP);
+    if (r.rrh_of_user) memcpy(r.rrh_of_user, src(o.A), sizeof(int) * K);
+    if (r.xi) memcpy(r.xi, src(o.xi), sizeof(double) * M);
+    if (r.zeta) memcpy(r.zeta, src(o.zeta), sizeof(double) * K);
+    const double* ur = (const double*)src(o.ur);
     if (r.user_rate) memcpy(r.user_rate, ur, sizeof(double) * K);
     if (r.power) {
       memset(r.power, 0, sizeof(float) * M * N * K);
-      const int* os = (const int*)src(off[b].os);
-      const double* op = (const double*)src(off[b].op);
+      const int* os = (const int*)src(o.os);
+      const double* op = (const double*)src(o.op);
       for (size_t i = 0; i < M * N; ++i)
         for (size_t a = 0; a < L; ++a)
           if (os[i * L + a] >= 0) r.power[i * K + os[i * L + a]] = (float)op[i * L + a];
@@ -1866,7 +1924,7 @@ int solve_batch(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc_p
     const Ctrl& cf = ctrls[b];
     uint32_t flags = cf.flags;
     for (size_t k = 0; k < K; ++k) {
-      if (!els[b][k] && ur[k] < psis[b][k] * (1.0 - 1e-6)) flags |= ALLOC_QOS_INFEASIBLE;
+      if (!P.els[b][k] && ur[k] < P.psis[b][k] * (1.0 - 1e-6)) flags |= ALLOC_QOS_INFEASIBLE;
       if (!std::isfinite(ur[k])) flags |= ALLOC_NONFINITE;
     }
     r.ee = cf.P > 0.0 ? cf.R / cf.P : 0.0;
@@ -1875,6 +1933,33 @@ int solve_batch(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc_p
     r.dinkelbach_iters = cf.i;
     r.sweeps = cf.total;
     r.status_flags = flags;
+  }
+  return ALLOC_OK;
+}
+
+int solve_batch(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc_params* prm,
+                const alloc_warm* warms, const WarmFn* fn, alloc_result* results) {
+  if (!ctx || !probs || !results || B < 1 || !prm) return ALLOC_EINVAL;
+  if (warms && fn) return ALLOC_EINVAL;
+  size_t host_n3 = 0;
+  if (warms)
+    for (int b = 0; b < B; ++b)
+      if (warms[b].p0) host_n3 = std::max(host_n3, (size_t)probs[b].M * probs[b].N * probs[b].K);
+  BatchPlan P;
+  int rc = batch_prepare(ctx, B, probs, prm, warms || fn, host_n3, warms != nullptr, &ctx->ws, &ctx->ws_bytes, P);
+  if (rc) return rc;
+  if ((warms || fn) && (rc = batch_warm(ctx, probs, warms, fn, P))) return rc;
+  hipStream_t st = ctx->stream;
+  if ((rc = batch_upload(st, P))) return rc;
+  if (ctx->timing && hipEventRecord(ctx->ev0, st) != hipSuccess) return ALLOC_EDEVICE;
+  if ((rc = batch_enqueue(st, P))) return rc;
+  if (ctx->timing && hipEventRecord(ctx->ev1, st) != hipSuccess) return ALLOC_EDEVICE;
+  if ((rc = batch_collect(st, P, results))) return rc;
+  ctx->last_ms = -1.0;
+  if (ctx->timing) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1) != hipSuccess) return ALLOC_EDEVICE;
+    ctx->last_ms = ms;
   }
   return ALLOC_OK;
 }
@@ -1892,6 +1977,79 @@ int alloc_solve(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm
   }
   return alloc_internal::solve_one(ctx, pb, prm, warm, nullptr, res);
 }
+
+struct alloc_batch {
+  alloc_ctx* ctx;
+  char* buf;
+  size_t bytes;
+  alloc_internal::BatchPlan plan;
+  hipStream_t cap;
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+  double last_ms;
+};
+
+void alloc_batch_destroy(alloc_batch* b) {
+  if (!b) return;
+  (void)hipSetDevice(b->ctx->device);
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  if (b->cap) (void)hipStreamDestroy(b->cap);
+  if (b->buf) (void)hipFree(b->buf);
+  delete b;
+}
+
+int alloc_batch_create(alloc_ctx* ctx, int32_t B, const alloc_problem* probs, const alloc_params* prm,
+                       alloc_batch** out) {
+  if (!ctx || !out) return ALLOC_EINVAL;
+  alloc_batch* b = new alloc_batch();
+  b->ctx = ctx;
+  b->last_ms = -1.0;
+  int rc = alloc_internal::batch_prepare(ctx, B, probs, prm, false, 0, false, &b->buf, &b->bytes, b->plan);
+  if (rc == ALLOC_OK) rc = alloc_internal::batch_upload(ctx->stream, b->plan);
+  if (rc == ALLOC_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) rc = ALLOC_EDEVICE;
+  // capture on a stream of our own (the context's may be the null stream)
+  if (rc == ALLOC_OK && hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess) rc = ALLOC_EDEVICE;
+  if (rc == ALLOC_OK && hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+    rc = ALLOC_EDEVICE;
+  if (rc == ALLOC_OK) {
+    const int erc = alloc_internal::batch_enqueue(b->cap, b->plan);
+    const bool end_ok = hipStreamEndCapture(b->cap, &b->graph) == hipSuccess;
+    rc = erc ? erc : (end_ok ? ALLOC_OK : ALLOC_EDEVICE);
+  }
+  if (rc == ALLOC_OK && hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0) != hipSuccess)
+    rc = ALLOC_EDEVICE;
+  if (rc) {
+    alloc_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return ALLOC_OK;
+}
+
+int alloc_batch_run(alloc_batch* b) {
+  if (!b) return ALLOC_EINVAL;
+  alloc_ctx* c = b->ctx;
+  if (hipSetDevice(c->device) != hipSuccess) return ALLOC_EDEVICE;
+  if (c->timing && hipEventRecord(c->ev0, c->stream) != hipSuccess) return ALLOC_EDEVICE;
+  if (hipGraphLaunch(b->exec, c->stream) != hipSuccess) return ALLOC_EDEVICE;
+  if (c->timing && hipEventRecord(c->ev1, c->stream) != hipSuccess) return ALLOC_EDEVICE;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return ALLOC_EDEVICE;
+  b->last_ms = -1.0;
+  if (c->timing) {
+    float ms = 0.0f;
+    if (hipEventElapsedTime(&ms, c->ev0, c->ev1) != hipSuccess) return ALLOC_EDEVICE;
+    b->last_ms = ms;
+  }
+  return ALLOC_OK;
+}
+
+int alloc_batch_results(alloc_batch* b, alloc_result* results) {
+  if (!b || !results) return ALLOC_EINVAL;
+  return alloc_internal::batch_collect(b->ctx->stream, b->plan, results);
+}
+
+double alloc_batch_last_ms(alloc_batch* b) { return b ? b->last_ms : -1.0; }
 
 int alloc_solve_batch(alloc_ctx* ctx, int32_t B, const alloc_problem* probs, const alloc_params* prm,
                       const alloc_warm* warms, alloc_result* results) {

@@ -154,3 +154,55 @@ def test_batch_warm_starts_match_oracle(ctx):
         print(info, flush=True)
         chaotic += bool(info.get("skipped"))
     assert chaotic <= 2
+
+
+def _same(a, b):
+    assert a.ee == b.ee and a.status_flags == b.status_flags
+    assert a.sweeps == b.sweeps and a.dinkelbach_iters == b.dinkelbach_iters
+    assert np.array_equal(a.sel, b.sel) and np.array_equal(a.slot_power, b.slot_power)
+    assert np.array_equal(a.rrh_of_user, b.rrh_of_user) and np.array_equal(a.xi, b.xi)
+
+
+def test_graph_batch_replays_match_eager(ctx):
+    """The captured batch (alloc_batch_*) replayed three times, with eager
+    solves in between: every replay equals the eager batched solve."""
+    import torch
+
+    import paper_1803_07772_amd as pa
+    drops = _mixed_batch()
+    p = pa.Params(fixed_count=0, sweeps_per_dinkelbach=60)
+    gains = [torch.from_numpy(d.gain).cuda() for d in drops]
+    print(f"[gpu case] graph batch of {len(drops)} drops, 3 replays", flush=True)
+    eager = ctx.solve_batch(drops, p, gains=gains)
+    bt = pa.Batch(ctx, drops, p, gains=gains)
+    for rep in range(3):
+        bt.run()
+        got = bt.results()
+        for a, b in zip(got, eager):
+            _same(a, b)
+        ctx.solve(drops[rep], p)  # eager work between replays
+        torch.cuda.synchronize()
+    bt.close()
+    # host gains are copied in at creation
+    bh = pa.Batch(ctx, drops[:4], p)
+    bh.run()
+    for a, b in zip(bh.results(), eager[:4]):
+        _same(a, b)
+    bh.close()
+
+
+def test_lds_cap_shares_compute_units(ctx):
+    """A smaller LDS share per workgroup (smaller tiles, two workgroups per
+    compute unit) gives the same allocations up to the order of the tile sums."""
+    import paper_1803_07772_amd as pa
+    drops = [synth.make_drop(synth.CFG2, 60 + i, i) for i in range(6)]
+    p = pa.Params(fixed_count=0, sweeps_per_dinkelbach=60)
+    print("[gpu case] batch with lds_kb=64", flush=True)
+    full = ctx.solve_batch(drops, p)
+    capped = ctx.solve_batch(drops, dataclasses.replace(p, lds_kb=64))
+    for a, b in zip(capped, full):
+        assert abs(a.ee - b.ee) <= 1e-9 * abs(b.ee)
+        assert np.array_equal(a.sel, b.sel) and np.array_equal(a.rrh_of_user, b.rrh_of_user)
+    import pytest as _pt
+    with _pt.raises(pa.AllocError, match="-27"):
+        ctx.solve_batch(drops[:1], dataclasses.replace(p, lds_kb=2))
