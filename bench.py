@@ -2,8 +2,10 @@
 
 Workload (value): batches of drops of the 5-RRH, 64-subcarrier, 32-user
 configuration (24 elastic, 8 streaming users, l=2), converge mode with caps,
-solved by the batched persistent solver (one alloc_solve_batch per step) with
-the gains resident in HBM.  Beside it, on the same GPU:
+solved by the batched persistent solver with the gains resident in HBM; one
+step is one replay of the graph-captured batched solve of every drop, in the
+launch shape the autotuner chose for the bucket.  Beside it, on the same GPU:
+* batched_call: the same batch through one alloc_solve_batch call;
 * plain: the same drops through alloc_solve, one after another;
 * large_drop: the 17-RRH, 1024-subcarrier, 256-user drop (l=3, exactly 200
   sweeps per Dinkelbach step) through alloc_solve;
@@ -16,6 +18,7 @@ HIP-event duration.  The FP64 oracle is timed on a bounded sample of the same
 drops on the host.
 """
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -93,23 +96,35 @@ def main():
     print(f"[bench] {a.batch} drops of M=5 N=64 K=32 resident; warmup {a.warmup}, steps {a.steps}",
           flush=True)
 
-    def batched_step():
-        res = ctx.solve_batch(drops, params, gains=gains)
-        return res, ctx.last_kernel_ms()
+    # launch shape: the autotuner's cached choice for this size bucket, or
+    # measured now on a sample of the batch
+    from paper_1803_07772_amd import tune
+    cache = tune.load_cache()
+    key = tune.batch_key(drops)
+    if key in cache:
+        params_b, tuned_from = tune.tuned(drops, params, cache), "cache"
+    else:
+        best, _ = tune.tune(ctx, drops, params, gains=gains, sample=256, cache=cache)
+        params_b, tuned_from = dataclasses.replace(params, **best), "measured"
+    print(f"[bench] launch shape {key}: lds_kb={params_b.lds_kb} tile={params_b.tile} ({tuned_from})", flush=True)
 
+    # one step = one replay of the graph-captured batched solve of all drops
+    bt = pa.Batch(ctx, drops, params_b, gains=gains)
     for _ in range(a.warmup):
-        batched_step()
+        bt.run()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    runs = []
+    kms_runs = []
     for _ in range(a.steps):
-        runs.append(batched_step())
+        bt.run()
+        kms_runs.append(bt.last_ms())
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     print(f"[bench] batched: {dt / a.steps * 1e3:.1f} ms per step", flush=True)
     value = a.batch * a.steps / dt
-    kms = float(np.mean([k for _, k in runs]))
-    res0 = runs[-1][0]
+    kms = float(np.mean(kms_runs))
+    res0 = bt.results()
+    bt.close()
     bytes_launch = float(sum(4.0 * d.M * d.N * d.K * r.sweeps for d, r in zip(drops, res0)))
     line = {
         "metric": METRIC, "value": value, "unit": "allocations/s", "n_gpus": 1,
@@ -117,12 +132,18 @@ def main():
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic (seeded generator: 3GPP-style path loss, shadowing, Rayleigh)",
         "config": {"workload": "batched solver, drops of M=5 N=64 K=32 (24 elastic, 8 streaming) l=2, "
-                               "converge with caps", "drops_per_step": a.batch, "mode": "batched"},
+                               "converge with caps", "drops_per_step": a.batch, "mode": "batched",
+                   "launch": {"graph": True, "lds_kb": params_b.lds_kb, "tile": params_b.tile,
+                              "tuned_from": tuned_from, "bucket": key}},
         "roofline": roofline("batch_kernel", bytes_launch, kms),
         "sweeps_mean": float(np.mean([r.sweeps for r in res0])),
         "ee_mean": float(np.mean([r.ee for r in res0])),
     }
-    modes = {"batched": {"allocations_per_s": value, "kernel_ms": kms}}
+    modes = {"batched": {"allocations_per_s": value, "kernel_ms": kms, "graph": True}}
+    t0 = time.perf_counter()
+    ctx.solve_batch(drops, params_b, gains=gains)
+    modes["batched_call"] = {"allocations_per_s": a.batch / (time.perf_counter() - t0),
+                             "note": "one alloc_solve_batch call (descriptors uploaded, results copied back)"}
 
     if not a.no_plain:
         sub = list(zip(drops, gains))[:a.plain_drops]
@@ -164,10 +185,10 @@ def main():
         cfg = warm.TrainConfig(steps=a.train_steps)
         net, info = warm.fit(ctx, tdrops, params, cfg, gains=tg)
         print(f"[bench] trained: {info}", flush=True)
-        net.solve_batch(drops[:64], params, gains=gains[:64])
+        net.solve_batch(drops[:64], params_b, gains=gains[:64])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        wr = net.solve_batch(drops, params, gains=gains)
+        wr = net.solve_batch(drops, params_b, gains=gains)
         dtw = time.perf_counter() - t0
         mlp_ms = net.last_ms()
         rows = sum(d.M * d.N * d.K for d in drops)

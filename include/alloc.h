@@ -61,6 +61,9 @@ extern "C" {
 #define ALLOC_NOT_CONVERGED 1u  /* Dinkelbach stopped at max_dinkelbach */
 #define ALLOC_QOS_INFEASIBLE 2u /* a streaming user ends below (1-1e-6) of its minimum rate */
 #define ALLOC_NONFINITE 8u      /* a non-finite rate or power appeared */
+#define ALLOC_GROUP_TIMEOUT 32u /* batched solver: the workgroups sharing this drop did not
+                                   meet within 20 s (never expected: the persistent grid
+                                   stays resident); the result is not valid */
 
 typedef struct alloc_ctx alloc_ctx;
 
@@ -104,9 +107,11 @@ typedef struct {
                                     (0 = one per compute unit, <= N) */
   int32_t tile;                  /* 0: subcarriers a workgroup processes together
                                     (0 = as many as its LDS holds) */
-  int32_t lds_kb;                /* 0: batched solver only: LDS per workgroup in KiB
-                                    (0 = a whole compute unit's; smaller values let
-                                    several workgroups share a compute unit) */
+  int32_t lds_kb;                /* 0: batched solver only: requested LDS per workgroup
+                                    in KiB (0 = a whole compute unit's); smaller shares
+                                    let several workgroups share a compute unit.  Raised
+                                    to what the batch's largest drop needs for a
+                                    one-subcarrier tile. */
 } alloc_params;
 
 ALLOC_API void alloc_params_default(alloc_params* p);

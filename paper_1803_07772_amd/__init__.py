@@ -234,10 +234,12 @@ class Context:
         _check(lib.alloc_ctx_create(device, ctypes.c_void_p(stream), ctypes.byref(h)))
         self._h = h
         self.device = device
+        self.timing = False
 
     def set_timing(self, enable: bool = True):
         """Record HIP events around the solve kernel of each call."""
         _check(load().alloc_ctx_set_timing(self._h, int(enable)))
+        self.timing = bool(enable)
 
     def last_kernel_ms(self) -> float:
         return load().alloc_ctx_last_kernel_ms(self._h)

@@ -102,6 +102,8 @@ struct Drop {
   int tile;                // subcarriers per LDS tile (batched solver)
   int preset;              // batched solver: the initial state is already written
   int start_eval;          // the initial allocation is Dinkelbach's p^0 (warm start)
+  int group;               // batched solver: workgroups that solve the drop together
+  unsigned* bar;           // [3] their barrier: arrivals, generation, broken
 };
 
 // Pointers into the workgroup's LDS: 32-bit addresses, direct LDS access.
@@ -1042,10 +1044,145 @@ __device__ void block_reduce(const Drop& d, const Sched& sc, const Ctrl& c, Lds&
   __syncthreads();
 }
 
-// Persistent batched solver: workgroups take drops from an atomic queue (in
-// the host's order: largest estimated work first) and solve each completely.
-__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))) batch_kernel(const Drop* drops, const int* order, int B,
-                                                      Sched sc, int* queue, Ctrl* ctrls) {
+// Barrier of the G workgroups that solve one drop together.  All of them
+// are resident (the persistent grid never exceeds what the device holds at
+// once), so every wait ends; as a safety net a wait longer than
+// kGroupWaitTicks of the 100 MHz constant clock marks the drop broken
+// (bar[2]) and every rank leaves.  Returns false once the drop is broken.
+constexpr unsigned long long kGroupWaitTicks = 2000000000ull;  // 20 s
+
+__device__ bool group_sync(unsigned* bar, int G) {
+  __shared__ int s_ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int ok = 1;
+    const unsigned gen = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    const unsigned arrived = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (arrived == (unsigned)G - 1) {
+      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      const unsigned long long t0 = wall_clock64();
+      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == gen) {
+        if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+          ok = 0;
+          break;
+        }
+        if (wall_clock64() - t0 > kGroupWaitTicks) {
+          __hip_atomic_store(&bar[2], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(2);
+      }
+    }
+    if (__hip_atomic_load(&bar[2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) ok = 0;
+    __threadfence();
+    s_ok = ok;
+  }
+  __syncthreads();
+  return s_ok != 0;
+}
+
+__device__ inline Ctrl initial_ctrl(const Drop& d) {
+  Ctrl c0;
+  c0.E = 0.0;
+  c0.R = 0.0;
+  c0.P = d.pstatic;
+  c0.i = 0;
+  c0.v = 0;
+  c0.mode = d.start_eval ? kEval : kSweep;
+  c0.total = 0;
+  c0.reset = 1;
+  c0.pass = 0;
+  c0.flags = 0;
+  return c0;
+}
+
+// A drop solved by one workgroup, every reduction inside it.
+__device__ void solve_single(const Drop& d, const Sched& sd, Lds& s, Ctrl& s_c, int& s_changes, Ctrl* out) {
+  if (!d.preset) block_cold_start(d, s);
+  if (threadIdx.x == 0) s_c = initial_ctrl(d);
+  __syncthreads();
+  while (s_c.mode != kDone) {
+    const Ctrl c = s_c;
+    const bool update = c.mode == kSweep;
+    PassConst pc;
+    pc.E = c.E;
+    pc.delta_v = sd.step0 / sqrt(1.0 + (double)c.v);
+    pc.refit = update && sd.refit_period > 0 && (c.v % sd.refit_period) == 0;
+    pc.reset = update && c.reset;
+    pc.update = update;
+    pc.write_out = !update;
+    if (threadIdx.x == 0) s_changes = 0;
+    begin_pass(d, s);
+    for (int n0 = 0; n0 < d.N; n0 += sd.tile) tile<true>(d, sd, pc, s, n0, 1, min(sd.tile, d.N - n0));
+    block_reduce(d, sd, c, s, update, pc.delta_v, &s_changes);
+    if (threadIdx.x == 0) {
+      double R = 0.0, P = d.pstatic, dm = 0.0;
+      for (int m = 0; m < d.M; ++m) {
+        R += s.Racc[m];
+        P += d.eta[m] * s.peacc[m];
+        dm = fmax(dm, s.dmax[m]);
+      }
+      Ctrl cn = c;
+      advance(sd, cn, R, P, dm, s_changes);
+      s_c = cn;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = s_c;
+  __syncthreads();
+}
+
+// A drop solved by G workgroups together, this one of rank r: the grid
+// solver's pass (subcarriers r, r+G, ..., partials, fixed-order reductions)
+// with the group barrier in place of the grid barrier.
+__device__ void solve_group(const Drop& d, const Sched& sd, Lds& s, int r, int G, Ctrl* out) {
+  if (r == 0) {
+    if (threadIdx.x == 0) {
+      store_shared(&d.chg_count[0], 0);
+      store_shared(&d.chg_count[1], 0);
+    }
+    if (!d.preset) block_cold_start(d, s);
+  }
+  Ctrl c = initial_ctrl(d);
+  bool ok = group_sync(d.bar, G);
+  while (ok && c.mode != kDone) {
+    const bool update = c.mode == kSweep;
+    PassConst pc;
+    pc.E = c.E;
+    pc.delta_v = sd.step0 / sqrt(1.0 + (double)c.v);
+    pc.refit = update && sd.refit_period > 0 && (c.v % sd.refit_period) == 0;
+    pc.reset = update && c.reset;
+    pc.update = update;
+    pc.write_out = !update;
+    begin_pass(d, s);
+    const int nb = (d.N - r + G - 1) / G;
+    for (int j = 0; j < nb; j += sd.tile) tile<false>(d, sd, pc, s, r + j * G, G, min(sd.tile, nb - j));
+    write_partials(d, s, r);
+    if (!(ok = group_sync(d.bar, G))) break;
+    reduce_pass(d, sd, c, s, r, G, update, pc.delta_v);
+    if (!(ok = group_sync(d.bar, G))) break;
+    control(d, sd, c);
+  }
+  if (!ok) {
+    c.flags |= ALLOC_GROUP_TIMEOUT;
+    c.mode = kDone;
+  }
+  if ((r == 0 || !ok) && threadIdx.x == 0) *out = c;
+  __syncthreads();
+}
+
+// Persistent batched solver.  Workgroups take slots from an atomic queue in
+// the host's order (largest work per slot first); a slot is (drop, rank).  A
+// drop with one slot is solved inside one workgroup; a drop with G slots by
+// the G workgroups that take them, which meet at the drop's group barrier.
+// Slots go out in order and every workgroup is resident, so the earliest
+// unfinished drop always has all its ranks running: no group waits forever.
+__global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
+batch_kernel(const Drop* drops, const int2* slots, int S, Sched sc, int* queue, Ctrl* ctrls) {
   extern __shared__ __align__(16) char smem[];
   __shared__ int s_idx, s_changes;
   __shared__ Ctrl s_c;
@@ -1055,58 +1192,17 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
     __syncthreads();
     const int idx = s_idx;
     __syncthreads();
-    if (idx >= B) break;
-    const Drop& d = drops[order[idx]];
+    if (idx >= S) break;
+    const int2 sl = slots[idx];
+    const Drop& d = drops[sl.x];
     Sched sd = sc;
     sd.tile = d.tile;
     if (threadIdx.x == 0) carve_lds((LDS char*)smem, d.M, d.K, d.L, sd.tile, &s_tab);
     __syncthreads();
-    Lds& s = s_tab;
-    if (!d.preset) block_cold_start(d, s);
-    if (threadIdx.x == 0) {
-      Ctrl c0;
-      c0.E = 0.0;
-      c0.R = 0.0;
-      c0.P = d.pstatic;
-      c0.i = 0;
-      c0.v = 0;
-      c0.mode = d.start_eval ? kEval : kSweep;
-      c0.total = 0;
-      c0.reset = 1;
-      c0.pass = 0;
-      c0.flags = 0;
-      s_c = c0;
-    }
-    __syncthreads();
-    while (s_c.mode != kDone) {
-      const Ctrl c = s_c;
-      const bool update = c.mode == kSweep;
-      PassConst pc;
-      pc.E = c.E;
-      pc.delta_v = sd.step0 / sqrt(1.0 + (double)c.v);
-      pc.refit = update && sd.refit_period > 0 && (c.v % sd.refit_period) == 0;
-      pc.reset = update && c.reset;
-      pc.update = update;
-      pc.write_out = !update;
-      if (threadIdx.x == 0) s_changes = 0;
-      begin_pass(d, s);
-      for (int n0 = 0; n0 < d.N; n0 += sd.tile) tile<true>(d, sd, pc, s, n0, 1, min(sd.tile, d.N - n0));
-      block_reduce(d, sd, c, s, update, pc.delta_v, &s_changes);
-      if (threadIdx.x == 0) {
-        double R = 0.0, P = d.pstatic, dm = 0.0;
-        for (int m = 0; m < d.M; ++m) {
-          R += s.Racc[m];
-          P += d.eta[m] * s.peacc[m];
-          dm = fmax(dm, s.dmax[m]);
-        }
-        Ctrl cn = c;
-        advance(sd, cn, R, P, dm, s_changes);
-        s_c = cn;
-      }
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) ctrls[order[idx]] = s_c;
-    __syncthreads();
+    if (d.group <= 1)
+      solve_single(d, sd, s_tab, s_c, s_changes, ctrls + sl.x);
+    else
+      solve_group(d, sd, s_tab, sl.y, d.group, ctrls + sl.x);
   }
 }
 
@@ -1607,17 +1703,20 @@ int solve_one(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, 
 // inputs, state and outputs, the drop descriptors and the launch shape.
 struct BatchOff {
   size_t G, psi, el, pmax, eta, pmask, w, A, sel, p, al, be, zs, xi, zeta, chs, cha, ur, os, op, oz;
+  size_t Sp, rp, rhp, psp, pep, Rp, dp, chg, red, bar;  // group drops only
 };
 
 struct BatchPlan {
   int B = 0;
   char* ws = nullptr;
   bool gain_dev = false;
-  size_t oDrops = 0, oOrder = 0, oQueue = 0, oCtrls = 0, out_begin = 0, out_end = 0;
+  size_t oDrops = 0, oSlots = 0, oQueue = 0, oCtrls = 0, out_begin = 0, out_end = 0;
+  size_t bar_begin = 0, bar_end = 0;
   size_t oISnr = 0, oIP0s = 0, oIP0 = 0, oIXi = 0, oIZ = 0;
   std::vector<BatchOff> off;
   std::vector<Drop> drops;
-  std::vector<int> order;
+  std::vector<int2> slots;  // (drop, rank), largest work per slot first
+  std::vector<int> group;
   std::vector<std::vector<double>> psis;
   std::vector<std::vector<uint8_t>> els;
   std::vector<int> Ms, Ns, Ks, Ls;
@@ -1649,11 +1748,37 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
     }
   }
   if (hipSetDevice(ctx->device) != hipSuccess) return ALLOC_EDEVICE;
-  // LDS per workgroup: the whole CU unless capped (the kernel's static LDS stays below 1 KB)
-  size_t budget = ctx->lds_max - 1024;
-  if (prm->lds_kb > 0) budget = std::min(budget, (size_t)prm->lds_kb * 1024 - 1024);
-  for (int b = 0; b < B; ++b)
-    if (carve_lds(nullptr, probs[b].M, probs[b].K, probs[b].l, 1, nullptr) > budget) return ALLOC_ETOOBIG;
+  // LDS per workgroup: the whole CU (the kernel's static LDS stays below
+  // 1 KB), or the requested share, raised to what the largest drop needs
+  const size_t full = ctx->lds_max - 1024;
+  size_t need = 0;
+  for (int b = 0; b < B; ++b) need = std::max(need, carve_lds(nullptr, probs[b].M, probs[b].K, probs[b].l, 1, nullptr));
+  if (need > full) return ALLOC_ETOOBIG;
+  size_t budget = full;
+  if (prm->lds_kb > 0) budget = std::max(need, std::min(full, (size_t)prm->lds_kb * 1024 - std::min<size_t>(1024, (size_t)prm->lds_kb * 1024)));
+
+  int per_cu = 0;
+  if (hipFuncSetAttribute((const void*)batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                          (int)(ctx->lds_max - 1024)) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)batch_kernel, kBlock, budget) !=
+          hipSuccess)
+    return ALLOC_EDEVICE;
+  if (per_cu < 1) return ALLOC_ETOOBIG;
+  int cap = per_cu * ctx->cus;  // workgroups resident at once
+  if (prm->max_groups > 0) cap = std::min(cap, prm->max_groups);
+
+  // workgroups per drop: a drop with more work than the average share of a
+  // resident workgroup is split over about work/average of them (at most
+  // one per subcarrier), so no slot holds much more than the average
+  P.group.assign(B, 1);
+  double wsum = 0.0;
+  for (int b = 0; b < B; ++b) wsum += (double)probs[b].M * probs[b].N * probs[b].K;
+  const double avg = wsum / cap;
+  for (int b = 0; b < B; ++b) {
+    const double w = (double)probs[b].M * probs[b].N * probs[b].K;
+    if (w > 1.5 * avg) P.group[b] = (int)std::min<double>({std::floor(w / avg + 0.5), (double)cap, (double)probs[b].N});
+    P.group[b] = std::max(1, P.group[b]);
+  }
 
   P.B = B;
   P.gain_dev = gain_dev;
@@ -1664,8 +1789,10 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
     tot += (n + 255) & ~size_t(255);
     return o;
   };
+  int S = 0;
+  for (int b = 0; b < B; ++b) S += P.group[b];
   P.oDrops = add(sizeof(Drop) * B);
-  P.oOrder = add(sizeof(int) * B);
+  P.oSlots = add(sizeof(int2) * S);
   P.oQueue = add(sizeof(int));
   P.oCtrls = add(sizeof(Ctrl) * B);
   const size_t small_begin = tot;
@@ -1715,7 +1842,23 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
     P.off[b].chs = add(sizeof(int) * M * N);
     P.off[b].cha = add(sizeof(int) * K);
     P.off[b].G = add(gain_dev ? 0 : sizeof(float) * M * N * K);
+    const size_t g = P.group[b];
+    if (g > 1) {
+      P.off[b].Sp = add(sizeof(double) * g * M * K);
+      P.off[b].rp = add(sizeof(double) * g * K);
+      P.off[b].rhp = add(sizeof(double) * g * K);
+      P.off[b].psp = add(sizeof(double) * g * M);
+      P.off[b].pep = add(sizeof(double) * g * M);
+      P.off[b].Rp = add(sizeof(double) * g);
+      P.off[b].dp = add(sizeof(double) * g);
+      P.off[b].chg = add(sizeof(int) * 2);
+      P.off[b].red = add(sizeof(double) * 4);
+    }
   }
+  P.bar_begin = tot;
+  for (int b = 0; b < B; ++b)
+    if (P.group[b] > 1) P.off[b].bar = add(sizeof(unsigned) * 3);
+  P.bar_end = tot;
   if (tot > *bytes) {
     if (*buf) (void)hipFree(*buf);
     *buf = nullptr;
@@ -1785,21 +1928,41 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
     d.out_sel = (int*)(ws + o.os);
     d.out_p = (double*)(ws + o.op);
     d.out_zs = (double*)(ws + o.oz);
-    int T = prm->tile > 0 ? std::min(prm->tile, N) : N;
+    const int g = P.group[b];
+    d.group = g;
+    if (g > 1) {
+      d.S_part = (double*)(ws + o.Sp);
+      d.r_part = (double*)(ws + o.rp);
+      d.rh_part = (double*)(ws + o.rhp);
+      d.psum_part = (double*)(ws + o.psp);
+      d.pel_part = (double*)(ws + o.pep);
+      d.R_part = (double*)(ws + o.Rp);
+      d.d_part = (double*)(ws + o.dp);
+      d.chg_count = (int*)(ws + o.chg);
+      d.red = (double*)(ws + o.red);
+      d.bar = (unsigned*)(ws + o.bar);
+    }
+    const int nb = (N + g - 1) / g;  // subcarriers of one rank
+    int T = prm->tile > 0 ? std::min(prm->tile, nb) : nb;
     while (T > 1 && carve_lds(nullptr, M, K, L, T, nullptr) > budget) --T;
     d.tile = T;
   }
-  // largest estimated work first
-  P.order.resize(B);
-  for (int b = 0; b < B; ++b) P.order[b] = b;
-  std::stable_sort(P.order.begin(), P.order.end(), [&](int x, int y) {
-    return (double)probs[x].M * probs[x].N * probs[x].K > (double)probs[y].M * probs[y].N * probs[y].K;
-  });
+  // slots, largest work per slot first; a drop's slots are consecutive
+  std::vector<int> order(B);
+  for (int b = 0; b < B; ++b) order[b] = b;
+  auto per_slot = [&](int b) { return (double)probs[b].M * probs[b].N * probs[b].K / P.group[b]; };
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return per_slot(x) > per_slot(y); });
+  P.slots.clear();
+  for (int b : order)
+    for (int r = 0; r < P.group[b]; ++r) P.slots.push_back(make_int2(b, r));
   bool ok = hipMemcpyAsync(ws + small_begin, img.data(), img.size(), hipMemcpyHostToDevice, st) == hipSuccess;
   if (!gain_dev)
     for (int b = 0; b < B && ok; ++b)
       ok = hipMemcpyAsync(ws + P.off[b].G, probs[b].gain, sizeof(float) * probs[b].M * probs[b].N * probs[b].K,
                           hipMemcpyHostToDevice, st) == hipSuccess;
+  // group barriers start at zero (each solve leaves its arrival count at zero)
+  if (ok && P.bar_end > P.bar_begin)
+    ok = hipMemsetAsync(ws + P.bar_begin, 0, P.bar_end - P.bar_begin, st) == hipSuccess;
   if (!ok) return ALLOC_EDEVICE;
 
   Sched& sc = P.sc;
@@ -1812,16 +1975,8 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
   sc.tol_dual = prm->tol_dual;
   sc.step0 = prm->step0;
   sc.tile = 1;
-  int per_cu = 0;
-  if (hipFuncSetAttribute((const void*)batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)(ctx->lds_max - 1024)) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)batch_kernel, kBlock, budget) !=
-          hipSuccess)
-    return ALLOC_EDEVICE;
-  if (per_cu < 1) return ALLOC_ETOOBIG;
   P.lds = budget;
-  P.grid = std::min(B, per_cu * ctx->cus);
-  if (prm->max_groups > 0) P.grid = std::min(P.grid, prm->max_groups);
+  P.grid = std::min(S, cap);
   return ALLOC_OK;
 }
 
@@ -1878,7 +2033,8 @@ int batch_upload(hipStream_t st, const BatchPlan& P) {
   const bool ok =
       hipMemcpyAsync(P.ws + P.oDrops, P.drops.data(), sizeof(Drop) * P.B, hipMemcpyHostToDevice, st) ==
           hipSuccess &&
-      hipMemcpyAsync(P.ws + P.oOrder, P.order.data(), sizeof(int) * P.B, hipMemcpyHostToDevice, st) == hipSuccess;
+      hipMemcpyAsync(P.ws + P.oSlots, P.slots.data(), sizeof(int2) * P.slots.size(), hipMemcpyHostToDevice, st) ==
+          hipSuccess;
   return ok ? ALLOC_OK : ALLOC_EDEVICE;
 }
 
@@ -1887,7 +2043,7 @@ int batch_upload(hipStream_t st, const BatchPlan& P) {
 int batch_enqueue(hipStream_t st, const BatchPlan& P) {
   hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, st, (int*)(P.ws + P.oQueue));
   hipLaunchKernelGGL(batch_kernel, dim3(P.grid), dim3(kBlock), P.lds, st, (const Drop*)(P.ws + P.oDrops),
-                     (const int*)(P.ws + P.oOrder), P.B, P.sc, (int*)(P.ws + P.oQueue),
+                     (const int2*)(P.ws + P.oSlots), (int)P.slots.size(), P.sc, (int*)(P.ws + P.oQueue),
                      (Ctrl*)(P.ws + P.oCtrls));
   return hipGetLastError() == hipSuccess ? ALLOC_OK : ALLOC_EDEVICE;
 }

@@ -1,0 +1,95 @@
+"""Autotuner of the batched solver's launch shape.
+
+The choices are the LDS share of a workgroup (``lds_kb``: a whole compute
+unit, or a half or a third so that two or three workgroups share one) and the
+cap on subcarriers per LDS tile (``tile``).  They change only the order of
+floating-point sums inside a drop, not the method.  Candidates are timed on
+the GPU (the batched kernel's HIP-event duration) on a seeded sample of the
+batch; the fastest per size bucket is kept in a JSON cache that later batches
+of the same bucket reuse.
+"""
+from __future__ import annotations
+
+import dataclasses
+import json
+import math
+import os
+
+import numpy as np
+
+from . import Params
+
+CANDIDATES = (
+    {"lds_kb": 0, "tile": 0},
+    {"lds_kb": 79, "tile": 0},
+    {"lds_kb": 52, "tile": 0},
+    {"lds_kb": 0, "tile": 8},
+    {"lds_kb": 79, "tile": 8},
+    {"lds_kb": 79, "tile": 16},
+)
+DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
+
+
+def _up2(x: int) -> int:
+    return 1 << max(0, math.ceil(math.log2(max(1, x))))
+
+
+def bucket(M: int, N: int, K: int, l: int) -> str:
+    """Size class: M, N and K rounded up to powers of two, and l."""
+    return f"M{_up2(M)}-N{_up2(N)}-K{_up2(K)}-l{l}"
+
+
+def batch_key(drops) -> str:
+    """Bucket of the drop at the middle of the batch's work (M N K)."""
+    w = np.array([d.M * d.N * d.K for d in drops], float)
+    order = np.argsort(w, kind="stable")
+    c = np.cumsum(w[order])
+    mid = drops[int(order[np.searchsorted(c, 0.5 * c[-1])])]
+    return bucket(mid.M, mid.N, mid.K, mid.l)
+
+
+def load_cache(path: str = DEFAULT_CACHE) -> dict:
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
+
+
+def save_cache(cache: dict, path: str = DEFAULT_CACHE):
+    with open(path, "w") as f:
+        json.dump(cache, f, indent=1, sort_keys=True)
+        f.write("\n")
+
+
+def tuned(drops, params: Params, cache: dict | None = None) -> Params:
+    """params with the cached launch shape of the batch's bucket (unchanged
+    when the bucket was never tuned)."""
+    cache = load_cache() if cache is None else cache
+    e = cache.get(batch_key(drops))
+    if not e:
+        return params
+    return dataclasses.replace(params, lds_kb=int(e["lds_kb"]), tile=int(e["tile"]))
+
+
+def tune(ctx, drops, params: Params, gains=None, sample: int = 256, seed: int = 0,
+         candidates=CANDIDATES, cache: dict | None = None):
+    """Times every candidate on a sample of the batch; returns (best, timings)
+    and records the best under the batch's bucket in ``cache`` if given."""
+    rng = np.random.default_rng(seed)
+    idx = np.sort(rng.choice(len(drops), min(sample, len(drops)), replace=False))
+    sub = [drops[i] for i in idx]
+    gsub = None if gains is None else [gains[i] for i in idx]
+    was = ctx.timing
+    ctx.set_timing(True)
+    times = []
+    for cand in candidates:
+        p = dataclasses.replace(params, **cand)
+        ctx.solve_batch(sub[: max(1, len(sub) // 4)], p, gains=None if gsub is None else gsub[: max(1, len(sub) // 4)])
+        ctx.solve_batch(sub, p, gains=gsub)
+        times.append((ctx.last_kernel_ms(), cand))
+    ctx.set_timing(was)
+    best = min(times, key=lambda t: t[0])[1]
+    if cache is not None:
+        cache[batch_key(drops)] = dict(best, ms={f"{c['lds_kb']}/{c['tile']}": round(t, 3) for t, c in times},
+                                      sample=len(sub))
+    return best, times
