@@ -6,6 +6,8 @@ solved by the batched persistent solver with the gains resident in HBM; one
 step is one replay of the graph-captured batched solve of every drop, in the
 launch shape the autotuner chose for the bucket.  Beside it, on the same GPU:
 * batched_call: the same batch through one alloc_solve_batch call;
+* cfg4_ragged: the first drops of the ragged 4096-drop batch (one graph
+  replay; large drops split over several workgroups);
 * plain: the same drops through alloc_solve, one after another;
 * large_drop: the 17-RRH, 1024-subcarrier, 256-user drop (l=3, exactly 200
   sweeps per Dinkelbach step) through alloc_solve;
@@ -47,6 +49,14 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-nn", action="store_true")
+    ap.add_argument("--no-cfg4", action="store_true")
+    ap.add_argument("--cfg4-drops", type=int, default=1024,
+                    help="drops of the ragged 4096-drop batch timed in the cfg4 leg")
+    ap.add_argument("--save-tune", metavar="PATH", default=None,
+                    help="run the autotuner for every workload here and save its cache to PATH")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy 256 MiB device to device three times (a kernel of known "
+                         "traffic, for scaling memory counters)")
     return ap.parse_args()
 
 
@@ -87,6 +97,13 @@ def main():
     import synth
 
     dev = torch.device("cuda:0")
+    if a.calibrate_copy:
+        src = torch.ones(1 << 26, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     ctx = pa.Context(0)
     ctx.set_timing(True)
     params = pa.Params(fixed_count=0)  # converge with caps: 200 sweeps per step, 20 steps
@@ -101,10 +118,10 @@ def main():
     from paper_1803_07772_amd import tune
     cache = tune.load_cache()
     key = tune.batch_key(drops)
-    if key in cache:
+    if key in cache and not a.save_tune:
         params_b, tuned_from = tune.tuned(drops, params, cache), "cache"
     else:
-        best, _ = tune.tune(ctx, drops, params, gains=gains, sample=256, cache=cache)
+        best, _ = tune.tune(ctx, drops, params, gains=gains, cache=cache)
         params_b, tuned_from = dataclasses.replace(params, **best), "measured"
     print(f"[bench] launch shape {key}: lds_kb={params_b.lds_kb} tile={params_b.tile} ({tuned_from})", flush=True)
 
@@ -144,6 +161,38 @@ def main():
     ctx.solve_batch(drops, params_b, gains=gains)
     modes["batched_call"] = {"allocations_per_s": a.batch / (time.perf_counter() - t0),
                              "note": "one alloc_solve_batch call (descriptors uploaded, results copied back)"}
+
+    if not a.no_cfg4:
+        # the ragged batch (M-1 LPNs uniform in 2..16, N in {64..1024}, K in
+        # 16..256, a quarter streaming): the first cfg4_drops of its 4096 drops
+        d4 = synth.make_batch(4096, seed=0)[:a.cfg4_drops]
+        g4 = [torch.from_numpy(d.gain).to(dev) for d in d4]
+        k4 = tune.batch_key(d4)
+        if k4 in cache and not a.save_tune:
+            p4, t4 = tune.tuned(d4, params, cache), "cache"
+        else:
+            best4, _ = tune.tune(ctx, d4, params, gains=g4, cache=cache)
+            p4, t4 = dataclasses.replace(params, **best4), "measured"
+        b4 = pa.Batch(ctx, d4, p4, gains=g4)
+        t0 = time.perf_counter()
+        b4.run()
+        dt4 = time.perf_counter() - t0
+        r4 = b4.results()
+        ms4 = b4.last_ms()
+        b4.close()
+        by4 = float(sum(4.0 * d.M * d.N * d.K * r.sweeps for d, r in zip(d4, r4)))
+        modes["cfg4_ragged"] = {
+            "workload": f"first {len(d4)} drops of the ragged 4096-drop batch (seed 0), one graph replay",
+            "allocations_per_s": len(d4) / dt4, "triples": int(sum(d.M * d.N * d.K for d in d4)),
+            "sweeps_mean": float(np.mean([r.sweeps for r in r4])),
+            "groups_timeout": int(sum(bool(r.status_flags & 32) for r in r4)),
+            "launch": {"lds_kb": p4.lds_kb, "tile": p4.tile, "tuned_from": t4, "bucket": k4},
+            "roofline": roofline("batch_kernel", by4, ms4)}
+        del g4
+        print(f"[bench] cfg4 ragged: {len(d4) / dt4:.1f} allocations/s", flush=True)
+    if a.save_tune:
+        tune.save_cache(cache, a.save_tune)
+        print(f"[bench] saved the autotuner cache ({len(cache)} buckets)", flush=True)
 
     if not a.no_plain:
         sub = list(zip(drops, gains))[:a.plain_drops]

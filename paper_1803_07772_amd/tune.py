@@ -4,9 +4,11 @@ The choices are the LDS share of a workgroup (``lds_kb``: a whole compute
 unit, or a half or a third so that two or three workgroups share one) and the
 cap on subcarriers per LDS tile (``tile``).  They change only the order of
 floating-point sums inside a drop, not the method.  Candidates are timed on
-the GPU (the batched kernel's HIP-event duration) on a seeded sample of the
-batch; the fastest per size bucket is kept in a JSON cache that later batches
-of the same bucket reuse.
+the GPU (the batched kernel's HIP-event duration) on the whole batch, so the
+load per workgroup (and which drops are split over several workgroups) is the
+real one, but with a short fixed schedule (a few sweeps, every drop the same
+count) to keep tuning cheap; the fastest per size bucket is kept in a JSON
+cache that later batches of the same bucket reuse.
 """
 from __future__ import annotations
 
@@ -71,25 +73,23 @@ def tuned(drops, params: Params, cache: dict | None = None) -> Params:
     return dataclasses.replace(params, lds_kb=int(e["lds_kb"]), tile=int(e["tile"]))
 
 
-def tune(ctx, drops, params: Params, gains=None, sample: int = 256, seed: int = 0,
+def tune(ctx, drops, params: Params, gains=None, sweeps: int = 12,
          candidates=CANDIDATES, cache: dict | None = None):
-    """Times every candidate on a sample of the batch; returns (best, timings)
-    and records the best under the batch's bucket in ``cache`` if given."""
-    rng = np.random.default_rng(seed)
-    idx = np.sort(rng.choice(len(drops), min(sample, len(drops)), replace=False))
-    sub = [drops[i] for i in idx]
-    gsub = None if gains is None else [gains[i] for i in idx]
+    """Times every candidate on the batch with a fixed schedule of ``sweeps``
+    sweeps in each of two Dinkelbach steps; returns (best, timings) and
+    records the best under the batch's bucket in ``cache`` if given."""
+    short = dataclasses.replace(params, fixed_count=1, sweeps_per_dinkelbach=sweeps, max_dinkelbach=2)
     was = ctx.timing
     ctx.set_timing(True)
     times = []
     for cand in candidates:
-        p = dataclasses.replace(params, **cand)
-        ctx.solve_batch(sub[: max(1, len(sub) // 4)], p, gains=None if gsub is None else gsub[: max(1, len(sub) // 4)])
-        ctx.solve_batch(sub, p, gains=gsub)
+        p = dataclasses.replace(short, **cand)
+        ctx.solve_batch(drops, dataclasses.replace(p, sweeps_per_dinkelbach=1, max_dinkelbach=1), gains=gains)
+        ctx.solve_batch(drops, p, gains=gains)
         times.append((ctx.last_kernel_ms(), cand))
     ctx.set_timing(was)
     best = min(times, key=lambda t: t[0])[1]
     if cache is not None:
         cache[batch_key(drops)] = dict(best, ms={f"{c['lds_kb']}/{c['tile']}": round(t, 3) for t, c in times},
-                                      sample=len(sub))
+                                      drops=len(drops), sweeps=sweeps)
     return best, times

@@ -224,7 +224,7 @@ def test_autotuner_picks_a_candidate(ctx):
     p = pa.Params(fixed_count=0, sweeps_per_dinkelbach=40)
     print("[gpu case] autotuner on 24 drops", flush=True)
     cache = {}
-    best, times = tune.tune(ctx, drops, p, sample=16, cache=cache)
+    best, times = tune.tune(ctx, drops, p, sweeps=4, cache=cache)
     assert best in tune.CANDIDATES and len(times) == len(tune.CANDIDATES)
     assert all(t > 0 for t, _ in times)
     key = tune.batch_key(drops)
