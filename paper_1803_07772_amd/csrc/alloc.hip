@@ -100,7 +100,9 @@ struct Drop {
   double* out_zs;          // [M][N][NP]
   Ctrl* ctrl;              // final control state for the host
   int tile;                // subcarriers per LDS tile (batched solver)
-  int preset;              // batched solver: the initial state is already written
+  const double* p0;        // batched solver, warm start (device, may be null):
+  const double* xi0;       //   initial powers [M][N][K], xi' [M], zeta' [K]
+  const double* zeta0;
   int start_eval;          // the initial allocation is Dinkelbach's p^0 (warm start)
   int group;               // batched solver: workgroups that solve the drop together
   unsigned* bar;           // [3] their barrier: arrivals, generation, broken
@@ -937,18 +939,26 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(Drop d, Sched sc) {
 
 // ---------------------------------------------------------- batched solver
 
-// Cold start of one drop inside a workgroup (same rules as the grid solver's
-// initial-point kernels): association by the summed log2(1 + Gamma pmask /
-// sigma) over n in increasing n, the l strongest users of each (m,n),
-// p = pmax/(N l).
-__device__ void block_cold_start(const Drop& d, Lds& s) {
+// Initial state of one drop inside a workgroup, by the same rules as the
+// single-drop initial-point kernels.  Cold (no p0): association by the
+// summed log2(1 + Gamma pmask / sigma) over n in increasing n, the l
+// strongest users of each (m,n), p = pmax/(N l).  Warm (initial powers p0):
+// the RRH of largest positive sum over n of p0 (else the cold one), the l
+// users of largest positive p0 at min(p0, pmask).  xi' = max(xi0, 0) (else
+// 0); zeta' = max(zeta0, 0) (else 1) for streaming users, 0 for elastic.
+__device__ void block_start(const Drop& d, Lds& s) {
   const int M = d.M, N = d.N, K = d.K, L = d.L, tid = threadIdx.x, nth = blockDim.x;
+  const double* p0 = d.p0;
   for (int i = tid; i < M * K; i += nth) {
     const int m = i / K, k = i - m * K;
-    double acc = 0.0;
-    for (int n = 0; n < N; ++n)
-      acc += log2_1p((double)d.G[((size_t)m * N + n) * K + k] * d.pmask[m] / d.sigma);
+    double acc = 0.0, pacc = 0.0;
+    for (int n = 0; n < N; ++n) {
+      const size_t gi = ((size_t)m * N + n) * K + k;
+      acc += log2_1p((double)d.G[gi] * d.pmask[m] / d.sigma);
+      if (p0) pacc += p0[gi];
+    }
     s.Sacc[i] = acc;
+    s.u[i] = pacc;  // the tile arrays are free before the first pass
   }
   __syncthreads();
   for (int k = tid; k < K; k += nth) {
@@ -959,11 +969,21 @@ __device__ void block_cold_start(const Drop& d, Lds& s) {
         bv = s.Sacc[m * K + k];
         best = m;
       }
+    if (p0) {
+      int wb = -1;
+      double wv = 0.0;
+      for (int m = 0; m < M; ++m)
+        if (s.u[m * K + k] > wv) {
+          wv = s.u[m * K + k];
+          wb = m;
+        }
+      if (wb >= 0) best = wb;
+    }
     d.A[k] = best;
     d.churn_A[k] = 0;
-    d.zeta[k] = d.elastic[k] ? 0.0 : 1.0;
+    d.zeta[k] = d.elastic[k] ? 0.0 : (d.zeta0 ? fmax(d.zeta0[k], 0.0) : 1.0);
   }
-  for (int m = tid; m < M; m += nth) d.xi[m] = 0.0;
+  for (int m = tid; m < M; m += nth) d.xi[m] = d.xi0 ? fmax(d.xi0[m], 0.0) : 0.0;
   __syncthreads();
   for (int i = tid; i < M * N; i += nth) {
     const int m = i / N, n = i - m * N;
@@ -972,7 +992,14 @@ __device__ void block_cold_start(const Drop& d, Lds& s) {
     int cnt = 0;
     for (int k = 0; k < K; ++k) {
       if (d.A[k] != m) continue;
-      const double v = d.G[((size_t)m * N + n) * K + k];
+      const size_t gi = ((size_t)m * N + n) * K + k;
+      double v;
+      if (p0) {
+        v = p0[gi];
+        if (!(v > 0.0)) continue;
+      } else {
+        v = d.G[gi];
+      }
       int t = cnt < L ? cnt : L;
       while (t > 0 && (bv[t - 1] < v || (bv[t - 1] == v && bk[t - 1] > k))) {
         if (t < L) {
@@ -990,7 +1017,7 @@ __device__ void block_cold_start(const Drop& d, Lds& s) {
     const size_t base = ((size_t)m * N + n) * L;
     for (int a = 0; a < L; ++a) {
       d.sel[base + a] = a < cnt ? bk[a] : -1;
-      d.p[base + a] = a < cnt ? d.pmax[m] / ((double)N * L) : 0.0;
+      d.p[base + a] = a < cnt ? (p0 ? fmin(bv[a], d.pmask[m]) : d.pmax[m] / ((double)N * L)) : 0.0;
       d.al[base + a] = 1.0;
       d.be[base + a] = 0.0;
       for (int b = 0; b < L; ++b) d.zs[(base + a) * L + b] = 0.0;
@@ -1102,7 +1129,7 @@ __device__ inline Ctrl initial_ctrl(const Drop& d) {
 
 // A drop solved by one workgroup, every reduction inside it.
 __device__ void solve_single(const Drop& d, const Sched& sd, Lds& s, Ctrl& s_c, int& s_changes, Ctrl* out) {
-  if (!d.preset) block_cold_start(d, s);
+  block_start(d, s);
   if (threadIdx.x == 0) s_c = initial_ctrl(d);
   __syncthreads();
   while (s_c.mode != kDone) {
@@ -1145,7 +1172,7 @@ __device__ void solve_group(const Drop& d, const Sched& sd, Lds& s, int r, int G
       store_shared(&d.chg_count[0], 0);
       store_shared(&d.chg_count[1], 0);
     }
-    if (!d.preset) block_cold_start(d, s);
+    block_start(d, s);
   }
   Ctrl c = initial_ctrl(d);
   bool ok = group_sync(d.bar, G);
@@ -1704,6 +1731,7 @@ int solve_one(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, 
 struct BatchOff {
   size_t G, psi, el, pmax, eta, pmask, w, A, sel, p, al, be, zs, xi, zeta, chs, cha, ur, os, op, oz;
   size_t Sp, rp, rhp, psp, pep, Rp, dp, chg, red, bar;  // group drops only
+  size_t wp0, wxi, wz;                                  // host warm starts, staged
 };
 
 struct BatchPlan {
@@ -1712,7 +1740,6 @@ struct BatchPlan {
   bool gain_dev = false;
   size_t oDrops = 0, oSlots = 0, oQueue = 0, oCtrls = 0, out_begin = 0, out_end = 0;
   size_t bar_begin = 0, bar_end = 0;
-  size_t oISnr = 0, oIP0s = 0, oIP0 = 0, oIXi = 0, oIZ = 0;
   std::vector<BatchOff> off;
   std::vector<Drop> drops;
   std::vector<int2> slots;  // (drop, rank), largest work per slot first
@@ -1730,10 +1757,9 @@ __global__ void reset_queue_kernel(int* q) {
 }
 
 // Validates, lays out and uploads the drops' inputs into *buf (grown to fit,
-// *bytes its size); warm-start scratch is reserved when `warm` is set
-// (host_n3: largest p0 staged from the host, host_mult: multipliers staged).
-int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc_params* prm, bool warm,
-                  size_t host_n3, bool host_mult, char** buf, size_t* bytes, BatchPlan& P) {
+// *bytes its size); host warm starts (hw, [B] or null) are staged per drop.
+int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc_params* prm,
+                  const alloc_warm* hw, char** buf, size_t* bytes, BatchPlan& P) {
   if (!ctx || !probs || B < 1 || !prm) return ALLOC_EINVAL;
   if (prm->flags & ALLOC_OUT_ON_DEVICE) return ALLOC_EINVAL;
   const bool gain_dev = prm->flags & ALLOC_GAIN_ON_DEVICE;
@@ -1820,17 +1846,13 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
     P.off[b].ur = add(sizeof(double) * K);
   }
   P.out_end = tot;
-  size_t max_mk = 1, max_m = 1, max_k = 1;
-  for (int b = 0; b < B; ++b) {
-    max_mk = std::max(max_mk, (size_t)probs[b].M * probs[b].K);
-    max_m = std::max(max_m, (size_t)probs[b].M);
-    max_k = std::max(max_k, (size_t)probs[b].K);
-  }
-  P.oISnr = add(warm ? sizeof(double) * max_mk : 0);
-  P.oIP0s = add(warm ? sizeof(double) * max_mk : 0);
-  P.oIP0 = add(sizeof(double) * host_n3);
-  P.oIXi = add(host_mult ? sizeof(double) * max_m : 0);
-  P.oIZ = add(host_mult ? sizeof(double) * max_k : 0);
+  if (hw)
+    for (int b = 0; b < B; ++b) {
+      const alloc_problem& pb = probs[b];
+      P.off[b].wp0 = add(hw[b].p0 ? sizeof(double) * pb.M * pb.N * pb.K : 0);
+      P.off[b].wxi = add(hw[b].xi0 ? sizeof(double) * pb.M : 0);
+      P.off[b].wz = add(hw[b].zeta0 ? sizeof(double) * pb.K : 0);
+    }
   for (int b = 0; b < B; ++b) {
     const alloc_problem& pb = probs[b];
     const size_t M = pb.M, N = pb.N, K = pb.K, L = pb.l;
@@ -1980,8 +2002,9 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
   return ALLOC_OK;
 }
 
-// Writes the initial state of warm-started drops with the single-drop
-// initialisation kernels, in drop order (before the descriptors go up).
+// Points warm-started drops at their initial powers and multipliers (the
+// batched kernel builds the initial state from them); host arrays are copied
+// into the drop's staging area first.
 int batch_warm(alloc_ctx* ctx, const alloc_problem* probs, const alloc_warm* warms, const WarmFn* fn,
                BatchPlan& P) {
   hipStream_t st = ctx->stream;
@@ -1993,37 +2016,27 @@ int batch_warm(alloc_ctx* ctx, const alloc_problem* probs, const alloc_warm* war
       if (rc != ALLOC_OK) return rc;
     } else {
       const alloc_problem& pb = probs[b];
-      const size_t n3 = (size_t)pb.M * pb.N * pb.K;
-      auto up = [&](size_t o, const double* src, size_t n) {
-        return hipMemcpyAsync(ws + o, src, sizeof(double) * n, hipMemcpyHostToDevice, st) == hipSuccess;
+      const BatchOff& o = P.off[b];
+      auto up = [&](size_t off, const double* src, size_t n) {
+        return hipMemcpyAsync(ws + off, src, sizeof(double) * n, hipMemcpyHostToDevice, st) == hipSuccess;
       };
       if (warms[b].p0) {
-        if (!up(P.oIP0, warms[b].p0, n3)) return ALLOC_EDEVICE;
-        w.p0 = (const double*)(ws + P.oIP0);
+        if (!up(o.wp0, warms[b].p0, (size_t)pb.M * pb.N * pb.K)) return ALLOC_EDEVICE;
+        w.p0 = (const double*)(ws + o.wp0);
       }
       if (warms[b].xi0) {
-        if (!up(P.oIXi, warms[b].xi0, pb.M)) return ALLOC_EDEVICE;
-        w.xi0 = (const double*)(ws + P.oIXi);
+        if (!up(o.wxi, warms[b].xi0, pb.M)) return ALLOC_EDEVICE;
+        w.xi0 = (const double*)(ws + o.wxi);
       }
       if (warms[b].zeta0) {
-        if (!up(P.oIZ, warms[b].zeta0, pb.K)) return ALLOC_EDEVICE;
-        w.zeta0 = (const double*)(ws + P.oIZ);
+        if (!up(o.wz, warms[b].zeta0, pb.K)) return ALLOC_EDEVICE;
+        w.zeta0 = (const double*)(ws + o.wz);
       }
     }
-    if (!w.p0 && !w.xi0 && !w.zeta0) continue;
     Drop& d = P.drops[b];
-    const int tb = 256, M = d.M, N = d.N, K = d.K;
-    double* snr = (double*)(ws + P.oISnr);
-    double* p0s = w.p0 ? (double*)(ws + P.oIP0s) : nullptr;
-    hipLaunchKernelGGL(cold_assoc_kernel, dim3((M * K + tb - 1) / tb), dim3(tb), 0, st, d, snr);
-    if (w.p0) hipLaunchKernelGGL(p0_sum_kernel, dim3((M * K + tb - 1) / tb), dim3(tb), 0, st, d, w.p0, p0s);
-    hipLaunchKernelGGL(cold_pick_kernel, dim3((K + tb - 1) / tb), dim3(tb), 0, st, d, (const double*)snr,
-                       (const double*)p0s);
-    hipLaunchKernelGGL(cold_select_kernel, dim3((M * N + tb - 1) / tb), dim3(tb), 0, st, d, w.p0);
-    hipLaunchKernelGGL(init_mult_kernel, dim3((std::max(M, K) + tb - 1) / tb), dim3(tb), 0, st, d, w.xi0,
-                       w.zeta0);
-    if (hipGetLastError() != hipSuccess) return ALLOC_EDEVICE;
-    d.preset = 1;
+    d.p0 = w.p0;
+    d.xi0 = w.xi0;
+    d.zeta0 = w.zeta0;
     d.start_eval = w.p0 != nullptr;
   }
   return ALLOC_OK;
@@ -2097,12 +2110,8 @@ int solve_batch(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc_p
                 const alloc_warm* warms, const WarmFn* fn, alloc_result* results) {
   if (!ctx || !probs || !results || B < 1 || !prm) return ALLOC_EINVAL;
   if (warms && fn) return ALLOC_EINVAL;
-  size_t host_n3 = 0;
-  if (warms)
-    for (int b = 0; b < B; ++b)
-      if (warms[b].p0) host_n3 = std::max(host_n3, (size_t)probs[b].M * probs[b].N * probs[b].K);
   BatchPlan P;
-  int rc = batch_prepare(ctx, B, probs, prm, warms || fn, host_n3, warms != nullptr, &ctx->ws, &ctx->ws_bytes, P);
+  int rc = batch_prepare(ctx, B, probs, prm, warms, &ctx->ws, &ctx->ws_bytes, P);
   if (rc) return rc;
   if ((warms || fn) && (rc = batch_warm(ctx, probs, warms, fn, P))) return rc;
   hipStream_t st = ctx->stream;
@@ -2161,7 +2170,7 @@ int alloc_batch_create(alloc_ctx* ctx, int32_t B, const alloc_problem* probs, co
   alloc_batch* b = new alloc_batch();
   b->ctx = ctx;
   b->last_ms = -1.0;
-  int rc = alloc_internal::batch_prepare(ctx, B, probs, prm, false, 0, false, &b->buf, &b->bytes, b->plan);
+  int rc = alloc_internal::batch_prepare(ctx, B, probs, prm, nullptr, &b->buf, &b->bytes, b->plan);
   if (rc == ALLOC_OK) rc = alloc_internal::batch_upload(ctx->stream, b->plan);
   if (rc == ALLOC_OK && hipStreamSynchronize(ctx->stream) != hipSuccess) rc = ALLOC_EDEVICE;
   // capture on a stream of our own (the context's may be the null stream)

@@ -375,6 +375,91 @@ __global__ void __launch_bounds__(256) zeta_pool_kernel(FeatDrop d, const float*
     zeta0[k] = d.f1[k] != 0.0f ? expm1(fmin(fmax(red[0] / (double)MN, 0.0), kLogClip)) : 0.0;
 }
 
+// One drop of a batched inference: its rows are [row0, row0 + M N K) of the
+// batch, its multipliers start at moff (xi) and koff (zeta).
+struct BatchFeat {
+  int64_t row0, moff, koff;
+  FeatDrop fd;
+};
+
+// Largest b with tab[b].row0 <= r (tab sorted by row0).
+__device__ inline int find_drop(const BatchFeat* tab, int B, int64_t r) {
+  int lo = 0, hi = B - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (tab[mid].row0 <= r)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// bf16 features of batch rows [r0, r0 + n).
+__global__ void features_batch_kernel(const BatchFeat* tab, int B, int64_t r0, int64_t n, bf16* out) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int64_t r = r0 + t;
+  const int b = find_drop(tab, B, r);
+  float f[4];
+  triple_features(tab[b].fd, r - tab[b].row0, f);
+  for (int c = 0; c < 4; ++c) out[t * 4 + c] = to_bf16(f[c]);
+}
+
+// Initial powers of batch rows [r0, r0 + n); y holds rows from y0.
+__global__ void p0_batch_kernel(const BatchFeat* tab, int B, int64_t r0, int64_t n, const float* y, int64_t y0,
+                                double* p0) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n) return;
+  const int64_t r = r0 + t;
+  const int b = find_drop(tab, B, r);
+  const FeatDrop& d = tab[b].fd;
+  const int m = (int)((r - tab[b].row0) / ((int64_t)d.N * d.K));
+  const double q = 1.0 / (1.0 + exp(-(double)y[(r - y0) * 3]));
+  p0[r] = q >= kQMin ? d.pmask[m] * exp10(kDecades * (q - 1.0)) : 0.0;
+}
+
+// xi0 of item (drop b, RRH m) per workgroup: mean over (n,k), fixed order.
+__global__ void __launch_bounds__(256) xi_pool_batch_kernel(const BatchFeat* tab, const int2* items,
+                                                            const float* y, int64_t y0, double* xi0) {
+  __shared__ double red[256];
+  const int2 it = items[blockIdx.x];
+  const BatchFeat& e = tab[it.x];
+  const int64_t NK = (int64_t)e.fd.N * e.fd.K;
+  const float* yb = y + (e.row0 - y0 + (int64_t)it.y * NK) * 3;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < NK; i += 256) s += (double)yb[i * 3 + 1];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if (threadIdx.x < k) red[threadIdx.x] += red[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) xi0[e.moff + it.y] = expm1(fmin(fmax(red[0] / (double)NK, 0.0), kLogClip));
+}
+
+// zeta0 of item (drop b, user k): mean over (m,n), 0 for elastic users.
+__global__ void __launch_bounds__(256) zeta_pool_batch_kernel(const BatchFeat* tab, const int2* items,
+                                                              const float* y, int64_t y0, double* zeta0) {
+  __shared__ double red[256];
+  const int2 it = items[blockIdx.x];
+  const BatchFeat& e = tab[it.x];
+  const int K = e.fd.K;
+  const int64_t MN = (int64_t)e.fd.M * e.fd.N;
+  const float* yb = y + (e.row0 - y0) * 3;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < MN; i += 256) s += (double)yb[(i * K + it.y) * 3 + 2];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int q = 128; q > 0; q >>= 1) {
+    if (threadIdx.x < q) red[threadIdx.x] += red[threadIdx.x + q];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0)
+    zeta0[e.koff + it.y] =
+        e.fd.f1[it.y] != 0.0f ? expm1(fmin(fmax(red[0] / (double)MN, 0.0), kLogClip)) : 0.0;
+}
+
 double min_rate(double arrival_bps, double delay_s, double packet_bits, double bw_hz) {
   const double lambda = arrival_bps / packet_bits;
   const double x = lambda * delay_s;
@@ -643,6 +728,152 @@ int feat_drop(alloc_mlp* net, const alloc_problem* pb, uint32_t flags, size_t of
 }
 
 size_t feat_bytes(int M, int K) { return sizeof(double) * 2 * M + sizeof(float) * (M + 2 * K) + 64; }
+
+// Host image of one drop's feature constants (layout of feat_bytes):
+// snr_scale [M], pmask [M] (double), f3 [M], f1 [K], f2 [K] (float).
+int feat_image(const alloc_problem* pb, char* img) {
+  const int M = pb->M, N = pb->N, K = pb->K;
+  if (M < 1 || N < 1 || K < 1 || !pb->gain || !pb->user_type || !pb->pmax_w) return ALLOC_EINVAL;
+  if (!(pb->noise_w > 0) || !(pb->bw_hz > 0) || !(pb->packet_bits > 0)) return ALLOC_EINVAL;
+  double* sc = (double*)img;
+  double* pm = sc + M;
+  float* f3 = (float*)(pm + M);
+  float* f1 = f3 + M;
+  float* f2 = f1 + K;
+  for (int m = 0; m < M; ++m) {
+    if (!(pb->pmax_w[m] > 0)) return ALLOC_EINVAL;
+    pm[m] = pb->pmask_w ? pb->pmask_w[m] : pb->pmax_w[m] / N;
+    sc[m] = pm[m] / pb->noise_w;
+    f3[m] = (float)((10.0 * log10(1000.0 * pb->pmax_w[m]) - 40.0) / 10.0);
+  }
+  for (int k = 0; k < K; ++k) {
+    const bool st = pb->user_type[k] == 1;
+    if (st && (!pb->arrival_bps || !pb->delay_s || !(pb->arrival_bps[k] > 0) || !(pb->delay_s[k] > 0)))
+      return ALLOC_EINVAL;
+    f1[k] = st ? 1.0f : 0.0f;
+    f2[k] = st ? (float)min_rate(pb->arrival_bps[k], pb->delay_s[k], pb->packet_bits, pb->bw_hz) : 0.0f;
+  }
+  return ALLOC_OK;
+}
+
+void feat_ptrs(const alloc_problem* pb, const char* base, const float* gain, FeatDrop* d) {
+  d->M = pb->M;
+  d->N = pb->N;
+  d->K = pb->K;
+  d->G = gain;
+  d->snr_scale = (const double*)base;
+  d->pmask = (const double*)base + pb->M;
+  d->f3 = (const float*)((const double*)base + 2 * pb->M);
+  d->f1 = d->f3 + pb->M;
+  d->f2 = d->f1 + pb->K;
+}
+
+// Warm-start arrays of a whole batch, from one inference pass over every
+// drop's rows (drops in groups of at most kGroupRows rows share the output
+// buffer).  Offsets into the network's scratch; per drop its first row and
+// multiplier offsets.
+constexpr int64_t kGroupRows = int64_t(1) << 26;
+
+struct WarmBatch {
+  size_t p0 = 0, xi = 0, zeta = 0;
+  std::vector<int64_t> row0, moff, koff;
+};
+
+int warm_batch(alloc_mlp* net, int B, const alloc_problem* probs, uint32_t gflag, WarmBatch* wb) {
+  std::vector<int64_t>& row0 = wb->row0;
+  std::vector<int64_t>& moff = wb->moff;
+  std::vector<int64_t>& koff = wb->koff;
+  row0.assign(B + 1, 0);
+  moff.assign(B + 1, 0);
+  koff.assign(B + 1, 0);
+  std::vector<size_t> cimg(B + 1, 0);
+  for (int b = 0; b < B; ++b) {
+    const alloc_problem& pb = probs[b];
+    if (pb.M < 1 || pb.N < 1 || pb.K < 1) return ALLOC_EINVAL;
+    row0[b + 1] = row0[b] + (int64_t)pb.M * pb.N * pb.K;
+    moff[b + 1] = moff[b] + pb.M;
+    koff[b + 1] = koff[b] + pb.K;
+    cimg[b + 1] = cimg[b] + ((feat_bytes(pb.M, pb.K) + 255) & ~size_t(255));
+  }
+  const int64_t R = row0[B];
+  // groups of consecutive drops
+  std::vector<int> gstart{0};
+  int64_t ymax = 0;
+  for (int b = 0; b < B; ++b) {
+    const int g0 = gstart.back();
+    if (b > g0 && row0[b + 1] - row0[g0] > kGroupRows) gstart.push_back(b);
+  }
+  gstart.push_back(B);
+  for (size_t g = 0; g + 1 < gstart.size(); ++g) ymax = std::max(ymax, row0[gstart[g + 1]] - row0[gstart[g]]);
+  const int64_t chunk = std::min<int64_t>(ymax, kChunk);
+
+  Scratch L;
+  const size_t oC = L.add(cimg[B]);
+  const size_t oTab = L.add(sizeof(BatchFeat) * B);
+  const size_t oMi = L.add(sizeof(int2) * moff[B]);
+  const size_t oKi = L.add(sizeof(int2) * koff[B]);
+  const size_t oG = L.add(gflag ? 0 : sizeof(float) * R);
+  const size_t oX0 = L.add(sizeof(bf16) * chunk * kIn);
+  const size_t oA1 = L.add(sizeof(bf16) * chunk * kHid);
+  const size_t oA2 = L.add(sizeof(bf16) * chunk * kHid);
+  const size_t oY = L.add(sizeof(float) * ymax * kOut);
+  wb->p0 = L.add(sizeof(double) * R);
+  wb->xi = L.add(sizeof(double) * moff[B]);
+  wb->zeta = L.add(sizeof(double) * koff[B]);
+  int rc = ensure_ws(net, L.total);
+  if (rc) return rc;
+  char* w = net->ws;
+  hipStream_t st = net->ctx->stream;
+
+  std::vector<char> img(cimg[B], 0);
+  std::vector<BatchFeat> tab(B);
+  std::vector<int2> mi(moff[B]), ki(koff[B]);
+  for (int b = 0; b < B; ++b) {
+    const alloc_problem& pb = probs[b];
+    if ((rc = feat_image(&pb, img.data() + cimg[b]))) return rc;
+    const float* g = gflag ? pb.gain : (const float*)(w + oG) + row0[b];
+    tab[b].row0 = row0[b];
+    tab[b].moff = moff[b];
+    tab[b].koff = koff[b];
+    feat_ptrs(&pb, w + oC + cimg[b], g, &tab[b].fd);
+    for (int m = 0; m < pb.M; ++m) mi[moff[b] + m] = make_int2(b, m);
+    for (int k = 0; k < pb.K; ++k) ki[koff[b] + k] = make_int2(b, k);
+    if (!gflag && hipMemcpyAsync((float*)(w + oG) + row0[b], pb.gain, sizeof(float) * (row0[b + 1] - row0[b]),
+                                 hipMemcpyHostToDevice, st) != hipSuccess)
+      return ALLOC_EDEVICE;
+  }
+  if (hipMemcpyAsync(w + oC, img.data(), img.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(w + oTab, tab.data(), sizeof(BatchFeat) * B, hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(w + oMi, mi.data(), sizeof(int2) * mi.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+      hipMemcpyAsync(w + oKi, ki.data(), sizeof(int2) * ki.size(), hipMemcpyHostToDevice, st) != hipSuccess)
+    return ALLOC_EDEVICE;
+  const BatchFeat* dtab = (const BatchFeat*)(w + oTab);
+  Acts s;
+  s.A[0] = (bf16*)(w + oX0);
+  s.A[1] = (bf16*)(w + oA1);
+  s.A[2] = (bf16*)(w + oA2);
+  s.A[3] = s.A[1];
+  for (int l = 0; l < 4; ++l) s.Z[l] = nullptr;
+  float* y = (float*)(w + oY);
+  for (size_t g = 0; g + 1 < gstart.size(); ++g) {
+    const int ga = gstart[g], gb = gstart[g + 1];
+    const int64_t R0 = row0[ga], R1 = row0[gb];
+    for (int64_t r0 = R0; r0 < R1; r0 += chunk) {
+      const int64_t n = std::min(chunk, R1 - r0);
+      hipLaunchKernelGGL(features_batch_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, dtab, B, r0, n,
+                         s.A[0]);
+      if ((rc = forward_rows(net, n, s.A[0], s, false, y + (r0 - R0) * kOut))) return rc;
+    }
+    hipLaunchKernelGGL(p0_batch_kernel, dim3((unsigned)cdiv(R1 - R0, 256)), dim3(256), 0, st, dtab, B, R0, R1 - R0,
+                       (const float*)y, R0, (double*)(w + wb->p0));
+    const int64_t nm = moff[gb] - moff[ga], nk = koff[gb] - koff[ga];
+    hipLaunchKernelGGL(xi_pool_batch_kernel, dim3((unsigned)nm), dim3(256), 0, st, dtab,
+                       (const int2*)(w + oMi) + moff[ga], (const float*)y, R0, (double*)(w + wb->xi));
+    hipLaunchKernelGGL(zeta_pool_batch_kernel, dim3((unsigned)nk), dim3(256), 0, st, dtab,
+                       (const int2*)(w + oKi) + koff[ga], (const float*)y, R0, (double*)(w + wb->zeta));
+  }
+  return hipGetLastError() == hipSuccess ? ALLOC_OK : ALLOC_EDEVICE;
+}
 
 // Scratch of warm_drop from offset base: feature constants, optional host
 // gain staging, chunk activations, y [n3][3].
@@ -931,44 +1162,33 @@ int alloc_solve_mlp(alloc_mlp* net, const alloc_problem* pb, const alloc_params*
 int alloc_solve_batch_mlp(alloc_mlp* net, int32_t B, const alloc_problem* probs, const alloc_params* prm,
                           alloc_result* results) {
   if (!net || B < 1 || !probs || !prm || !results) return ALLOC_EINVAL;
-  // scratch: one drop's warm-start arrays below `need`, warm_drop's area
-  // above it; sized once, so nothing moves while work is queued
-  const uint32_t gflag = prm->flags & ALLOC_GAIN_ON_DEVICE;
-  size_t need = 0, total = 0;
-  for (int b = 0; b < B; ++b) {
-    if (probs[b].M < 1 || probs[b].N < 1 || probs[b].K < 1) return ALLOC_EINVAL;
-    need = std::max(need, warm_arrays((int64_t)probs[b].M * probs[b].N * probs[b].K, probs[b].M, probs[b].K).end);
-  }
-  for (int b = 0; b < B; ++b) total = std::max(total, warm_scratch(&probs[b], gflag, need).end);
-  int rc = ensure_ws(net, total);
-  if (rc) return rc;
   alloc_ctx* c = net->ctx;
-  double mlp_ms = 0.0;
-  const alloc_internal::WarmFn fn = [&](int b, alloc_internal::DevWarm* w) {
-    const alloc_problem& pb = probs[b];
-    const WarmArrays wa = warm_arrays((int64_t)pb.M * pb.N * pb.K, pb.M, pb.K);
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    if (c->timing && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) return ALLOC_EDEVICE;
-    if (e0 && hipEventRecord(e0, c->stream) != hipSuccess) return ALLOC_EDEVICE;
-    int r = warm_drop(net, &pb, gflag, (double*)(net->ws + wa.p0),
-                      (double*)(net->ws + wa.xi0), (double*)(net->ws + wa.zeta0), need);
-    if (r == ALLOC_OK && e1) {
-      float ms = 0.0f;
-      if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-          hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
-        r = ALLOC_EDEVICE;
-      mlp_ms += ms;
-    }
-    if (e0) (void)hipEventDestroy(e0);
-    if (e1) (void)hipEventDestroy(e1);
-    w->p0 = (const double*)(net->ws + wa.p0);
-    w->xi0 = (const double*)(net->ws + wa.xi0);
-    w->zeta0 = (const double*)(net->ws + wa.zeta0);
-    return r;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c->timing && (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)) return ALLOC_EDEVICE;
+  if (e0 && hipEventRecord(e0, c->stream) != hipSuccess) return ALLOC_EDEVICE;
+  WarmBatch wb;
+  int rc = warm_batch(net, B, probs, prm->flags & ALLOC_GAIN_ON_DEVICE, &wb);
+  double mlp_ms = -1.0;
+  if (rc == ALLOC_OK && e1) {
+    float ms = 0.0f;
+    if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      rc = ALLOC_EDEVICE;
+    mlp_ms = ms;
+  }
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  net->last_ms = mlp_ms;
+  const char* w = net->ws;
+  const alloc_internal::WarmFn fn = [&](int b, alloc_internal::DevWarm* dw) {
+    dw->p0 = (const double*)(w + wb.p0) + wb.row0[b];
+    dw->xi0 = (const double*)(w + wb.xi) + wb.moff[b];
+    dw->zeta0 = (const double*)(w + wb.zeta) + wb.koff[b];
+    return ALLOC_OK;
   };
   rc = alloc_internal::solve_batch(c, B, probs, prm, nullptr, &fn, results);
   if (rc) return rc;
-  net->last_ms = c->timing ? mlp_ms : -1.0;
   std::vector<int> redo;
   for (int b = 0; b < B; ++b)
     if (needs_fallback(results[b])) redo.push_back(b);
