@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--batch", type=int, default=1024, help="drops per step")
+    ap.add_argument("--batch", type=int, default=4096, help="drops per step")
     ap.add_argument("--plain-drops", type=int, default=16)
     ap.add_argument("--train-drops", type=int, default=512)
     ap.add_argument("--train-steps", type=int, default=300)

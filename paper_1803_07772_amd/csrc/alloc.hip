@@ -62,9 +62,49 @@ struct Sched {
   double tol_d, tol_dual, step0;
 };
 
+// Division by a run-time invariant d by multiply-high and shifts
+// (Granlund and Montgomery, "Division by invariant integers using
+// multiplication", PLDI 1994, Fig. 4.1): exact for every 32-bit numerator.
+struct Div {
+  uint32_t m, s1, s2;
+  __host__ __device__ uint32_t div(uint32_t n) const {
+    const uint32_t t = (uint32_t)(((uint64_t)m * n) >> 32);
+    return (t + ((n - t) >> s1)) >> s2;
+  }
+};
+
+__host__ __device__ inline Div make_div(uint32_t d) {
+  uint32_t l = 0;
+  while ((uint64_t(1) << l) < d) ++l;  // ceil(log2 d)
+  Div r;
+  r.m = (uint32_t)(((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1);
+  r.s1 = l < 1 ? l : 1;
+  r.s2 = l > 0 ? l - 1 : 0;
+  return r;
+}
+
+// Divisors of the per-subcarrier item loops of one drop.
+struct Divs {
+  Div K, M, L, MK, ML, MLL, LL, MM;
+};
+
+inline Divs make_divs(int M, int K, int L) {
+  Divs v;
+  v.K = make_div(K);
+  v.M = make_div(M);
+  v.L = make_div(L);
+  v.MK = make_div(M * K);
+  v.ML = make_div(M * L);
+  v.MLL = make_div(M * L * L);
+  v.LL = make_div(L * L);
+  v.MM = make_div(M * M);
+  return v;
+}
+
 // Device view of one drop: inputs, state, per-workgroup partials.
 struct Drop {
   int M, N, K, L, NP;
+  Divs dv;                 // divisors of the item loops
   const float* G;          // [M][N][K]
   const double* psi;       // [K] minimum rate (0 elastic)
   const uint8_t* elastic;  // [K]
@@ -355,16 +395,17 @@ template <bool kItemH>
 __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s, int n0, int nstep,
                      int ns) {
   const int M = d.M, N = d.N, K = d.K, L = d.L, tid = threadIdx.x, nth = blockDim.x;
+  const Divs& dv = d.dv;
   const double sg = d.sigma;
 #define NOF(t) (n0 + (t) * nstep)
 
   // 1. gains, slot state and per-RRH totals into LDS
   for (int i = tid; i < ns * M * K; i += nth) {
-    const int t = i / (M * K), r = i - t * M * K, m = r / K, k = r - m * K;
+    const int t = dv.MK.div(i), r = i - t * M * K, m = dv.K.div(r), k = r - m * K;
     s.g[i] = d.G[((size_t)m * N + NOF(t)) * K + k];
   }
   for (int i = tid; i < ns * M * L; i += nth) {
-    const int t = i / (M * L), r = i - t * M * L, m = r / L, q = r - m * L;
+    const int t = dv.ML.div(i), r = i - t * M * L, m = dv.L.div(r), q = r - m * L;
     const size_t gi = ((size_t)m * N + NOF(t)) * L + q;
     s.su[i] = d.sel[gi];
     s.sp[i] = d.p[gi];
@@ -373,12 +414,12 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
     s.chosen[i] = -1;
   }
   for (int i = tid; i < ns * M * L * L; i += nth) {
-    const int t = i / (M * L * L), r = i - t * M * L * L, m = r / (L * L), ab = r - m * L * L;
+    const int t = dv.MLL.div(i), r = i - t * M * L * L, m = dv.LL.div(r), ab = r - m * L * L;
     s.szs[i] = d.zs[((size_t)m * N + NOF(t)) * L * L + ab];
     s.szn[i] = 0.0;
   }
   for (int i = tid; i < ns * M; i += nth) {
-    const int t = i / M, m = i - t * M;
+    const int t = dv.M.div(i), m = i - t * M;
     s.churn[i] = pc.reset ? 0 : d.churn_sel[(size_t)m * N + NOF(t)];
     double acc = 0.0;  // total power of RRH m on the subcarrier
     for (int q = 0; q < L; ++q) {
@@ -396,7 +437,7 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
   // 2. inter-cell interference as exclusive prefix + suffix over RRHs (no
   //    subtraction), stored as u = (sigma + ICI)/Gamma
   for (int i = tid; i < ns * K; i += nth) {
-    const int t = i / K, k = i - t * K;
+    const int t = dv.K.div(i), k = i - t * K;
     double suf = 0.0;
     for (int m = M - 1; m >= 0; --m) {
       s.u[IX_MK(t, m, k)] = suf;
@@ -415,7 +456,7 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
   // 3. SIC decoding order of each RRH's users: normalised gain descending
   //    (u ascending), ties to the lower user; position by rank
   for (int i = tid; i < ns * M * L; i += nth) {
-    const int t = i / (M * L), r = i - t * M * L, m = r / L, q = r - m * L;
+    const int t = dv.ML.div(i), r = i - t * M * L, m = dv.L.div(r), q = r - m * L;
     const int k = s.su[i];
     if (k < 0) continue;
     const double uq = s.u[IX_MK(t, m, k)];
@@ -439,7 +480,7 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
 
   // 4. per selected user: SINR, rate, SCALE refit and surrogate, price c
   for (int i = tid; i < ns * M * L; i += nth) {
-    const int t = i / (M * L), r = i - t * M * L, m = r / L, a = r - m * L;
+    const int t = dv.ML.div(i), r = i - t * M * L, m = dv.L.div(r), a = r - m * L;
     if (a >= s.vcnt[IX_SM(t, m)]) continue;
     double pre = 0.0;
     for (int a2 = 0; a2 < a; ++a2) pre += s.sp[IX_ML(t, m, s.vslot[IX_ML(t, m, a2)])];
@@ -472,7 +513,7 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
   }
   __syncthreads();
   for (int i = tid; i < ns * M; i += nth) {
-    const int t = i / M, m = i - t * M;
+    const int t = dv.M.div(i), m = i - t * M;
     const int cnt = s.vcnt[i];
     double ps = 0.0, pe = 0.0, Rm = 0.0;
     for (int a = 0; a < cnt; ++a) {
@@ -525,7 +566,7 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
 
   // 5. inter-cell price and C14 terms per (RRH m, other RRH j)
   for (int i = tid; i < ns * M * M; i += nth) {
-    const int t = i / (M * M), r = i - t * M * M, m = r / M, j = r - m * M;
+    const int t = dv.MM.div(i), r = i - t * M * M, m = dv.M.div(r), j = r - m * M;
     double inter = 0.0, sic = 0.0;
     if (j != m) {
       const int cj = s.vcnt[IX_SM(t, j)];
@@ -552,7 +593,8 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
   }
   // subgradient step of each pair's C14 multiplier on the margin Omega/nu
   for (int i = tid; i < ns * M * L * L; i += nth) {
-    const int t = i / (M * L * L), r = i - t * M * L * L, m = r / (L * L), a = (r / L) % L, b = r % L;
+    const int t = dv.MLL.div(i), r = i - t * M * L * L, m = dv.LL.div(r), rl = dv.L.div(r), a = rl - dv.L.div(rl) * L,
+              b = r - rl * L;
     if (!(a < b && b < s.vcnt[IX_SM(t, m)])) continue;
     const int ka = s.vuser[IX_ML(t, m, a)], kb = s.vuser[IX_ML(t, m, b)];
     const double ga = s.g[IX_MK(t, m, ka)], gb = s.g[IX_MK(t, m, kb)];
@@ -567,7 +609,7 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
   }
   __syncthreads();
   for (int i = tid; i < ns * M; i += nth) {
-    const int t = i / M, m = i - t * M;
+    const int t = dv.M.div(i), m = i - t * M;
     double inter = 0.0, sic = 0.0;
     for (int j = 0; j < M; ++j) {
       inter += s.pij[IX_SMM(t, m, j)];
@@ -618,7 +660,7 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
   if (kItemH) {
     // H replaces the triple's own u (nothing later in the pass reads u)
     for (int i = tid; i < ns * M * K; i += nth) {
-      const int t = i / (M * K), r = i - t * M * K, m = r / K, k = r - m * K;
+      const int t = dv.MK.div(i), r = i - t * M * K, m = dv.K.div(r), k = r - m * K;
       s.u[i] = h_item(t, m, k, s.u[i]);
     }
     __syncthreads();
@@ -629,7 +671,7 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
     }
   } else {
     for (int i = tid; i < M * K; i += nth) {
-      const int m = i / K, k = i - m * K;
+      const int m = dv.K.div(i), k = i - m * K;
       double Hsum = 0.0;
       for (int t = 0; t < ns; ++t) Hsum += h_item(t, m, k, s.u[IX_MK(t, m, k)]);
       s.Sacc[i] += Hsum;
@@ -640,7 +682,7 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
   // 7. selection: the l best of RRH m's users with H > 0 (H desc, user asc),
   //    by each candidate's rank within its group
   for (int i = tid; i < ns * K; i += nth) {
-    const int t = i / K, k = i - t * K;
+    const int t = dv.K.div(i), k = i - t * K;
     const int m = s.Al[k];
     if (m < 0 || s.frozen[IX_SM(t, m)]) continue;
     const double h = s.Hc[i];
@@ -655,7 +697,7 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
   }
   __syncthreads();
   for (int i = tid; i < ns * M; i += nth) {
-    const int t = i / M, m = i - t * M;
+    const int t = dv.M.div(i), m = i - t * M;
     const int cnt = s.vcnt[i];
     int np = 0;
     if (s.frozen[i]) {  // churn cap reached: keep the incumbents still associated with m
@@ -677,7 +719,7 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
   __syncthreads();
   // closed-form powers of the new selection
   for (int i = tid; i < ns * M * L; i += nth) {
-    const int t = i / (M * L), r = i - t * M * L, m = r / L, a = r - m * L;
+    const int t = dv.ML.div(i), r = i - t * M * L, m = dv.L.div(r), a = r - m * L;
     const int cnt = s.vcnt[IX_SM(t, m)], np = s.np[IX_SM(t, m)];
     double dm = 0.0;
     int k = -1, old = -1;
@@ -719,7 +761,8 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
   __syncthreads();
   // C14 multipliers follow their user pair into the new slots
   for (int i = tid; i < ns * M * L * L; i += nth) {
-    const int t = i / (M * L * L), r = i - t * M * L * L, m = r / (L * L), a = (r / L) % L, b = r % L;
+    const int t = dv.MLL.div(i), r = i - t * M * L * L, m = dv.LL.div(r), rl = dv.L.div(r), a = rl - dv.L.div(rl) * L,
+              b = r - rl * L;
     const int np = s.np[IX_SM(t, m)];
     double z = 0.0;
     if (a < np && b < np && a != b && s.nold[IX_ML(t, m, a)] >= 0 && s.nold[IX_ML(t, m, b)] >= 0)
@@ -1607,6 +1650,7 @@ int solve_one(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, 
   Drop d;
   memset(&d, 0, sizeof d);
   d.M = M; d.N = N; d.K = K; d.L = L; d.NP = NP;
+  d.dv = make_divs(M, K, L);
   d.G = gain_dev ? pb->gain : (const float*)(ws + oG);
   d.psi = (const double*)(ws + oPsi);
   d.elastic = (const uint8_t*)(ws + oEl);
@@ -1927,6 +1971,7 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
     Drop& d = P.drops[b];
     memset(&d, 0, sizeof d);
     d.M = M; d.N = N; d.K = K; d.L = L; d.NP = L * (L - 1) / 2;
+    d.dv = make_divs(M, K, L);
     d.G = gain_dev ? pb.gain : (const float*)(ws + o.G);
     d.psi = (const double*)(ws + o.psi);
     d.elastic = (const uint8_t*)(ws + o.el);
