@@ -188,6 +188,165 @@ __global__ void __launch_bounds__(256) gemm_kernel(GemmArgs a) {
       }
 }
 
+// ------------------------------------------------------ fused inference
+//
+// One wave carries 32 rows (two blocks of 16) through all four layers with
+// the activations in registers.  Each product is computed transposed,
+// H^T = W A^T: the weights are the matrix cores' A operand (16 outputs x 32
+// inputs) and the activations the B operand (32 inputs x 16 rows).  A 16x16
+// output block leaves lane l holding outputs 4(l/16)+q (q < 4) of row l%16;
+// two consecutive blocks give that lane 8 values of one row, which is its B
+// operand for a 32-input chunk of the next layer once the chunk's inputs are
+// taken in the order (32c + 4g + j, j < 4; 32c + 16 + 4g + j - 4, j >= 4),
+// g = l/16.  The weight fragments are stored in that order, 16 bytes per
+// lane, so each operand is one coalesced load.
+
+// Input of k-slot j of lane group g in chunk c.
+__host__ __device__ inline int frag_in(int c, int g, int j) {
+  return 32 * c + (j < 4 ? 4 * g + j : 16 + 4 * g + j - 4);
+}
+
+constexpr int64_t kFragHid = 16 * 8 * 64;  // bf16x8 fragments of a 256x256 layer
+constexpr int64_t kFragOut = 8 * 64;       // of the 256 -> 3 layer, outputs padded to 16
+
+// Fragments of W2, W3 (kFragHid each) and W4 (kFragOut) from the master weights.
+__global__ void pack_frags_kernel(const float* master, bf16x8* frag) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * kFragHid + kFragOut) return;
+  int layer;
+  int64_t f;
+  if (t < 2 * kFragHid) {
+    layer = t < kFragHid ? 2 : 3;
+    f = t % kFragHid;
+  } else {
+    layer = 4;
+    f = t - 2 * kFragHid;
+  }
+  const int lane = (int)(f % 64), c = (int)((f / 64) % 8), ob = layer == 4 ? 0 : (int)(f / (64 * 8));
+  const int g = lane >> 4, out = 16 * ob + (lane & 15);
+  bf16x8 v;
+  for (int j = 0; j < 8; ++j) {
+    const int in = frag_in(c, g, j);
+    float w = 0.0f;
+    if (layer < 4)
+      w = master[kOW[layer] + (int64_t)out * kHid + in];
+    else if (out < kOut)
+      w = master[kOW[4] + (int64_t)out * kHid + in];
+    v[j] = to_bf16(w);
+  }
+  frag[t] = v;
+}
+
+// GELU of the fused inference: the same tanh form with a hardware reciprocal.
+__device__ inline float gelu_rcp(float z) {
+  const float u = kGc * (z + 0.044715f * z * z * z);
+  return z * __frcp_rn(1.0f + __expf(-2.0f * u));
+}
+
+__device__ inline f32x4 mfma16(const bf16x8& a, const bf16x8& b, const f32x4& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// One hidden layer on kR row blocks: out[r][chunk] from in[r][chunk].
+template <int kR>
+__device__ inline void fused_hidden(const bf16x8* __restrict__ wl, const float* __restrict__ bias, int lane,
+                                    const bf16x8 (&in)[kR][8], bf16x8 (&out)[kR][8]) {
+  const int g = lane >> 4;
+#pragma unroll
+  for (int ob = 0; ob < 16; ++ob) {
+    f32x4 acc[kR];
+#pragma unroll
+    for (int r = 0; r < kR; ++r) acc[r] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const bf16x8 a = wl[(ob * 8 + c) * 64];
+#pragma unroll
+      for (int r = 0; r < kR; ++r) acc[r] = mfma16(a, in[r][c], acc[r]);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const float b = bias[16 * ob + 4 * g + q];
+#pragma unroll
+      for (int r = 0; r < kR; ++r) out[r][ob >> 1][(ob & 1) * 4 + q] = to_bf16(gelu_rcp(acc[r][q] + b));
+    }
+    // keep each output block's fragment loads next to their products (the
+    // unrolled layer would otherwise hoist all 128 loads and spill)
+    __builtin_amdgcn_sched_barrier(0);
+  }
+}
+
+constexpr int kFusedR = 1;  // row blocks of 16 per wave
+
+// y [n][3] from bf16 inputs x0 [n][4]; persistent over blocks of 16 kFusedR
+// rows per wave.
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) mlp_fused_kernel(const bf16* __restrict__ x0, int64_t n,
+                                                        const float* __restrict__ master,
+                                                        const bf16x8* __restrict__ frag, float* __restrict__ y) {
+  constexpr int R = kFusedR, RB = 16 * kFusedR;
+  const int lane = threadIdx.x & 63, g = lane >> 4, rl = lane & 15;
+  const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6), nw = (int64_t)gridDim.x * 4;
+  const float* W1 = master + kOW[1];
+  const float* b1 = master + kOB[1];
+  for (int64_t base = wave * RB; base < n; base += nw * RB) {
+    // the weights are invariant in this loop: a compiler barrier keeps them
+    // loaded where they are used instead of hoisted (and spilled) ahead of it
+    asm volatile("" ::: "memory");
+    // the lane's fragment offset, opaque to the compiler inside each pass:
+    // addresses are formed where they are used
+    int lo = lane;
+    asm volatile("" : "+v"(lo));
+    const bf16x8* wl = frag + lo;
+    bf16x8 a[R][8], b[R][8];
+    // layer 1 (4 inputs) on the vector units, into the B-operand layout
+    float x[R][4];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const int64_t row = base + 16 * r + rl;
+#pragma unroll
+      for (int p = 0; p < 4; ++p) x[r][p] = row < n ? (float)x0[row * 4 + p] : 0.0f;
+    }
+#pragma unroll
+    for (int f = 0; f < 16; ++f) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int o = 16 * f + 4 * g + q;
+        const float4 w = *reinterpret_cast<const float4*>(W1 + o * 4);
+        const float wb[4] = {(float)to_bf16(w.x), (float)to_bf16(w.y), (float)to_bf16(w.z), (float)to_bf16(w.w)};
+        const float bo = b1[o];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          float z = bo;
+#pragma unroll
+          for (int p = 0; p < 4; ++p) z = fmaf(wb[p], x[r][p], z);
+          a[r][f >> 1][(f & 1) * 4 + q] = to_bf16(gelu_rcp(z));
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    fused_hidden<R>(wl, master + kOB[2], lane, a, b);
+    fused_hidden<R>(wl + kFragHid, master + kOB[3], lane, b, a);
+    // layer 4: outputs padded to 16, the first three kept
+    f32x4 acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const bf16x8 w = wl[2 * kFragHid + c * 64];
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] = mfma16(w, a[r][c], acc[r]);
+    }
+    if (g == 0) {
+      const float* b4 = master + kOB[4];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int64_t row = base + 16 * r + rl;
+        if (row < n)
+          for (int q = 0; q < kOut; ++q) y[row * 3 + q] = acc[r][q] + b4[q];
+      }
+    }
+  }
+}
+
 // Weight gradient of one layer from its split partials [S][out][in+1], summed
 // in split order; column `in` is the bias gradient.
 __global__ void reduce_split_kernel(const float* part, int S, int out, int in, float* gW, float* gb) {
@@ -478,7 +637,8 @@ struct alloc_mlp {
   float* grad;    // [kNP]
   float* m1;      // [kNP] AdamW first moment
   float* m2;      // [kNP] second moment
-  bf16* q;        // [kNQ] bf16 weight matrices
+  bf16* q;        // [kNQ] bf16 weight matrices (training GEMMs)
+  bf16x8* frag;   // [2 kFragHid + kFragOut] fused-inference weight fragments
   int64_t step;
   char* ws;       // scratch (rows, activations, partials, warm-start arrays)
   size_t ws_bytes;
@@ -659,6 +819,23 @@ int grad_rows(alloc_mlp* net, int64_t R, const float* feat, const float* target,
   return ALLOC_OK;
 }
 
+// bf16 copies of the weights for the training GEMMs and the fused inference.
+void refresh_weights(alloc_mlp* net, hipStream_t st) {
+  hipLaunchKernelGGL(cast_weights_kernel, dim3((unsigned)cdiv((int64_t)kHid * kHid, 256)), dim3(256), 0, st,
+                     (const float*)net->master, net->q);
+  hipLaunchKernelGGL(pack_frags_kernel, dim3((unsigned)cdiv(2 * kFragHid + kFragOut, 256)), dim3(256), 0, st,
+                     (const float*)net->master, net->frag);
+}
+
+// Inference of n rows (bf16 inputs x0 [n][4]) into y [n][3] by the fused kernel.
+int infer_rows(alloc_mlp* net, int64_t n, const bf16* x0, float* y) {
+  if (n <= 0) return ALLOC_OK;
+  const int64_t grid = std::min<int64_t>(cdiv(n, 4 * 16 * kFusedR), (int64_t)net->ctx->cus * 8);
+  hipLaunchKernelGGL(mlp_fused_kernel, dim3((unsigned)grid), dim3(256), 0, net->ctx->stream, x0, n,
+                     (const float*)net->master, (const bf16x8*)net->frag, y);
+  return hipGetLastError() == hipSuccess ? ALLOC_OK : ALLOC_EDEVICE;
+}
+
 int adamw(alloc_mlp* net, const float* g, const alloc_mlp_opt* o) {
   if (!net || !g || !o) return ALLOC_EINVAL;
   hipStream_t st = net->ctx->stream;
@@ -667,8 +844,7 @@ int adamw(alloc_mlp* net, const float* g, const alloc_mlp_opt* o) {
   const double bc2 = 1.0 - pow((double)o->beta2, (double)net->step);
   hipLaunchKernelGGL(adamw_kernel, dim3((unsigned)cdiv(kNP, 256)), dim3(256), 0, st, net->master, net->m1,
                      net->m2, g, o->lr, o->beta1, o->beta2, o->eps, o->weight_decay, (float)bc1, (float)bc2);
-  hipLaunchKernelGGL(cast_weights_kernel, dim3((unsigned)cdiv((int64_t)kHid * kHid, 256)), dim3(256), 0, st,
-                     (const float*)net->master, net->q);
+  refresh_weights(net, st);
   return hipGetLastError() == hipSuccess ? ALLOC_OK : ALLOC_EDEVICE;
 }
 
@@ -862,7 +1038,7 @@ int warm_batch(alloc_mlp* net, int B, const alloc_problem* probs, uint32_t gflag
       const int64_t n = std::min(chunk, R1 - r0);
       hipLaunchKernelGGL(features_batch_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, dtab, B, r0, n,
                          s.A[0]);
-      if ((rc = forward_rows(net, n, s.A[0], s, false, y + (r0 - R0) * kOut))) return rc;
+      if ((rc = infer_rows(net, n, s.A[0], y + (r0 - R0) * kOut))) return rc;
     }
     hipLaunchKernelGGL(p0_batch_kernel, dim3((unsigned)cdiv(R1 - R0, 256)), dim3(256), 0, st, dtab, B, R0, R1 - R0,
                        (const float*)y, R0, (double*)(w + wb->p0));
@@ -922,7 +1098,7 @@ int warm_drop(alloc_mlp* net, const alloc_problem* pb, uint32_t flags, double* p
     const int64_t n = std::min(chunk, n3 - r0);
     hipLaunchKernelGGL(features_kernel, dim3((unsigned)cdiv(n, 256)), dim3(256), 0, st, d, r0, n,
                        (float*)nullptr, s.A[0]);
-    if ((rc = forward_rows(net, n, s.A[0], s, false, y + r0 * kOut))) return rc;
+    if ((rc = infer_rows(net, n, s.A[0], y + r0 * kOut))) return rc;
   }
   hipLaunchKernelGGL(p0_kernel, dim3((unsigned)cdiv(n3, 256)), dim3(256), 0, st, d, (const float*)y, p0);
   hipLaunchKernelGGL(xi_pool_kernel, dim3(pb->M), dim3(256), 0, st, d, (const float*)y, xi0);
@@ -961,7 +1137,8 @@ int alloc_mlp_create(alloc_ctx* ctx, alloc_mlp** out) {
   memset(n, 0, sizeof *n);
   n->ctx = ctx;
   n->last_ms = -1.0;
-  const size_t bytes = sizeof(float) * kNP * 4 + sizeof(bf16) * kNQ;
+  const size_t fbytes = sizeof(bf16x8) * (2 * kFragHid + kFragOut);
+  const size_t bytes = sizeof(float) * kNP * 4 + sizeof(bf16) * kNQ + 256 + fbytes;
   char* p = nullptr;
   if (hipMalloc((void**)&p, bytes) != hipSuccess) {
     delete n;
@@ -972,6 +1149,7 @@ int alloc_mlp_create(alloc_ctx* ctx, alloc_mlp** out) {
   n->m1 = n->grad + kNP;
   n->m2 = n->m1 + kNP;
   n->q = (bf16*)(n->m2 + kNP);
+  n->frag = (bf16x8*)(((uintptr_t)(n->q + kNQ) + 255) & ~(uintptr_t)255);
   if (hipMemsetAsync(p, 0, bytes, ctx->stream) != hipSuccess || hipStreamSynchronize(ctx->stream) != hipSuccess) {
     (void)hipFree(p);
     delete n;
@@ -998,8 +1176,7 @@ int alloc_mlp_set_params(alloc_mlp* net, const float* host, int64_t n) {
       hipMemsetAsync(net->m1, 0, sizeof(float) * kNP * 2, st) != hipSuccess)
     return ALLOC_EDEVICE;
   net->step = 0;
-  hipLaunchKernelGGL(cast_weights_kernel, dim3((unsigned)cdiv((int64_t)kHid * kHid, 256)), dim3(256), 0, st,
-                     (const float*)net->master, net->q);
+  refresh_weights(net, st);
   if (hipGetLastError() != hipSuccess || hipStreamSynchronize(st) != hipSuccess) return ALLOC_EDEVICE;
   return ALLOC_OK;
 }
@@ -1052,7 +1229,7 @@ int alloc_mlp_forward(alloc_mlp* net, int64_t R, const float* feat, float* y) {
     const int64_t n = std::min(chunk, R - r0);
     hipLaunchKernelGGL(cast_rows_kernel, dim3((unsigned)cdiv(n * kIn, 256)), dim3(256), 0, st, feat + r0 * kIn,
                        s.A[0], n * kIn);
-    if ((rc = forward_rows(net, n, s.A[0], s, false, y + r0 * kOut))) return rc;
+    if ((rc = infer_rows(net, n, s.A[0], y + r0 * kOut))) return rc;
   }
   if (c->timing && hipEventRecord(c->ev1, st) != hipSuccess) return ALLOC_EDEVICE;
   if (hipStreamSynchronize(st) != hipSuccess) return ALLOC_EDEVICE;
