@@ -60,27 +60,27 @@ def parse():
     return ap.parse_args()
 
 
-def traffic_for(kernel: str, launches_bytes=None):
+def traffic_for(kernel: str, drops: int | None):
     """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel source (else None)."""
+    taken on the current kernel source and the same batch size (else None)."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
-    if not os.path.exists(path):
+    if not os.path.exists(path) or drops is None:
         return None
     try:
         t = json.load(open(path))
         src = open(os.path.join(ROOT, "paper_1803_07772_amd", "csrc", "alloc.hip"), "rb").read()
         e = t[kernel]
-        if e["src_sha256"] != hashlib.sha256(src).hexdigest():
+        if e["src_sha256"] != hashlib.sha256(src).hexdigest() or e["drops_per_step"] != drops:
             return None
         return e["hbm_bytes_per_launch"]
     except (KeyError, ValueError, OSError):
         return None
 
 
-def roofline(kernel, bytes_per_launch, ms_per_launch):
+def roofline(kernel, bytes_per_launch, ms_per_launch, drops=None):
     ach = bytes_per_launch / (ms_per_launch * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(ach, 4), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ach / HBM_PEAK_GBS, "traffic": traffic_for(kernel), "kernel": kernel,
+            "frac": ach / HBM_PEAK_GBS, "traffic": traffic_for(kernel, drops), "kernel": kernel,
             "algorithmic_bytes_per_launch": bytes_per_launch, "ms_per_launch": ms_per_launch}
 
 
@@ -152,7 +152,7 @@ def main():
                                "converge with caps", "drops_per_step": a.batch, "mode": "batched",
                    "launch": {"graph": True, "lds_kb": params_b.lds_kb, "tile": params_b.tile,
                               "tuned_from": tuned_from, "bucket": key}},
-        "roofline": roofline("batch_kernel", bytes_launch, kms),
+        "roofline": roofline("batch_kernel", bytes_launch, kms, a.batch),
         "sweeps_mean": float(np.mean([r.sweeps for r in res0])),
         "ee_mean": float(np.mean([r.ee for r in res0])),
     }
