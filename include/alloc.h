@@ -112,6 +112,8 @@ typedef struct {
                                     let several workgroups share a compute unit.  Raised
                                     to what the batch's largest drop needs for a
                                     one-subcarrier tile. */
+  int32_t block;                 /* 0: batched solver only: threads per workgroup,
+                                    256 or 512 (0 = 512) */
 } alloc_params;
 
 ALLOC_API void alloc_params_default(alloc_params* p);

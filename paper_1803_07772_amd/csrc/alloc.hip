@@ -1420,7 +1420,7 @@ int validate(const alloc_problem* pb, const alloc_params* prm) {
   if (!std::isfinite(pb->noise_w)) return ALLOC_EINVAL;
   if (pb->M > kMaxM || pb->l > kMaxL || pb->K > kMaxK || pb->M * pb->K > kMaxMK) return ALLOC_ETOOBIG;
   if (prm->sweeps_per_dinkelbach < 1 || prm->max_dinkelbach < 1 || prm->max_groups < 0 || prm->tile < 0 ||
-      prm->lds_kb < 0)
+      prm->lds_kb < 0 || !(prm->block == 0 || prm->block == 256 || prm->block == 512))
     return ALLOC_EINVAL;
   for (int m = 0; m < pb->M; ++m) {
     if (!(pb->pmax_w[m] > 0) || !std::isfinite(pb->pmax_w[m])) return ALLOC_EINVAL;
@@ -1470,6 +1470,7 @@ void alloc_params_default(alloc_params* p) {
   p->max_groups = 0;
   p->tile = 0;
   p->lds_kb = 0;
+  p->block = 0;
 }
 
 int alloc_ctx_set_timing(alloc_ctx* ctx, int enable) {
@@ -1793,6 +1794,7 @@ struct BatchPlan {
   std::vector<int> Ms, Ns, Ks, Ls;
   Sched sc;
   int grid = 0;
+  int threads = kBlock;
   size_t lds = 0;
 };
 
@@ -1827,10 +1829,12 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
   size_t budget = full;
   if (prm->lds_kb > 0) budget = std::max(need, std::min(full, (size_t)prm->lds_kb * 1024 - std::min<size_t>(1024, (size_t)prm->lds_kb * 1024)));
 
+  const int nthreads = prm->block > 0 ? prm->block : kBlock;
+  P.threads = nthreads;
   int per_cu = 0;
   if (hipFuncSetAttribute((const void*)batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                           (int)(ctx->lds_max - 1024)) != hipSuccess ||
-      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)batch_kernel, kBlock, budget) !=
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)batch_kernel, nthreads, budget) !=
           hipSuccess)
     return ALLOC_EDEVICE;
   if (per_cu < 1) return ALLOC_ETOOBIG;
@@ -2100,7 +2104,7 @@ int batch_upload(hipStream_t st, const BatchPlan& P) {
 // copies or memsets, so the pair can be captured into a graph).
 int batch_enqueue(hipStream_t st, const BatchPlan& P) {
   hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, st, (int*)(P.ws + P.oQueue));
-  hipLaunchKernelGGL(batch_kernel, dim3(P.grid), dim3(kBlock), P.lds, st, (const Drop*)(P.ws + P.oDrops),
+  hipLaunchKernelGGL(batch_kernel, dim3(P.grid), dim3(P.threads), P.lds, st, (const Drop*)(P.ws + P.oDrops),
                      (const int2*)(P.ws + P.oSlots), (int)P.slots.size(), P.sc, (int*)(P.ws + P.oQueue),
                      (Ctrl*)(P.ws + P.oCtrls));
   return hipGetLastError() == hipSuccess ? ALLOC_OK : ALLOC_EDEVICE;

@@ -210,6 +210,13 @@ def test_lds_cap_shares_compute_units(ctx):
     for a, b in zip(capped, full):
         assert abs(a.ee - b.ee) <= 1e-9 * abs(b.ee)
         assert np.array_equal(a.sel, b.sel) and np.array_equal(a.rrh_of_user, b.rrh_of_user)
+    # 256-thread workgroups (more, smaller workgroups per compute unit)
+    for blk in (256,):
+        for a, b in zip(ctx.solve_batch(drops, dataclasses.replace(p, block=blk, lds_kb=39)), full):
+            assert abs(a.ee - b.ee) <= 1e-9 * abs(b.ee)
+            assert np.array_equal(a.sel, b.sel) and np.array_equal(a.rrh_of_user, b.rrh_of_user)
+    with pytest.raises(pa.AllocError, match="-22"):
+        ctx.solve_batch(drops[:1], dataclasses.replace(p, block=128))
     # a share below what a drop needs is raised to that need
     tiny = ctx.solve_batch(drops[:2], dataclasses.replace(p, lds_kb=2))
     for a, b in zip(tiny, full[:2]):
