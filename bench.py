@@ -123,7 +123,7 @@ def main():
     else:
         best, _ = tune.tune(ctx, drops, params, gains=gains, cache=cache)
         params_b, tuned_from = dataclasses.replace(params, **best), "measured"
-    print(f"[bench] launch shape {key}: lds_kb={params_b.lds_kb} tile={params_b.tile} block={params_b.block or 512} "
+    print(f"[bench] launch shape {key}: lds_kb={params_b.lds_kb} tile={params_b.tile} block={params_b.block or 512} wave={params_b.wave} "
           f"({tuned_from})", flush=True)
 
     # one step = one replay of the graph-captured batched solve of all drops
@@ -152,7 +152,7 @@ def main():
         "config": {"workload": "batched solver, drops of M=5 N=64 K=32 (24 elastic, 8 streaming) l=2, "
                                "converge with caps", "drops_per_step": a.batch, "mode": "batched",
                    "launch": {"graph": True, "lds_kb": params_b.lds_kb, "tile": params_b.tile,
-                              "block": params_b.block or 512, "tuned_from": tuned_from, "bucket": key}},
+                              "block": params_b.block or 512, "wave": params_b.wave, "tuned_from": tuned_from, "bucket": key}},
         "roofline": roofline("batch_kernel", bytes_launch, kms, a.batch),
         "sweeps_mean": float(np.mean([r.sweeps for r in res0])),
         "ee_mean": float(np.mean([r.ee for r in res0])),
@@ -187,7 +187,7 @@ def main():
             "allocations_per_s": len(d4) / dt4, "triples": int(sum(d.M * d.N * d.K for d in d4)),
             "sweeps_mean": float(np.mean([r.sweeps for r in r4])),
             "groups_timeout": int(sum(bool(r.status_flags & 32) for r in r4)),
-            "launch": {"lds_kb": p4.lds_kb, "tile": p4.tile, "block": p4.block or 512, "tuned_from": t4,
+            "launch": {"lds_kb": p4.lds_kb, "tile": p4.tile, "block": p4.block or 512, "wave": p4.wave, "tuned_from": t4,
                        "bucket": k4},
             "roofline": roofline("batch_kernel", by4, ms4)}
         del g4

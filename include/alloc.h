@@ -114,6 +114,13 @@ typedef struct {
                                     one-subcarrier tile. */
   int32_t block;                 /* 0: batched solver only: threads per workgroup,
                                     256 or 512 (0 = 512) */
+  int32_t wave;                  /* 0: batched solver only, drops solved by one
+                                    workgroup: 1..16 = each 64-lane wave runs its own
+                                    subcarriers, this many at a time, with no
+                                    workgroup barrier inside a pass (a drop whose
+                                    wave tiles do not fit the LDS share keeps
+                                    workgroup tiles); 0 = workgroup tiles.  With
+                                    lds_kb = 0 the share is what the wave tiles need. */
 } alloc_params;
 
 ALLOC_API void alloc_params_default(alloc_params* p);

@@ -48,7 +48,8 @@ class _Params(ctypes.Structure):
                 ("churn_limit", ctypes.c_int32), ("tol_dinkelbach", ctypes.c_double),
                 ("tol_dual", ctypes.c_double), ("step0", ctypes.c_double),
                 ("flags", ctypes.c_uint32), ("max_groups", ctypes.c_int32),
-                ("tile", ctypes.c_int32), ("lds_kb", ctypes.c_int32), ("block", ctypes.c_int32)]
+                ("tile", ctypes.c_int32), ("lds_kb", ctypes.c_int32), ("block", ctypes.c_int32),
+                ("wave", ctypes.c_int32)]
 
 
 class _Warm(ctypes.Structure):
@@ -136,11 +137,13 @@ class Params:
     tile: int = 0
     lds_kb: int = 0
     block: int = 0
+    wave: int = 0
 
     def _c(self, flags: int) -> _Params:
         return _Params(self.max_dinkelbach, self.sweeps_per_dinkelbach, self.refit_period,
                        self.fixed_count, self.churn_limit, self.tol_dinkelbach, self.tol_dual,
-                       self.step0, flags, self.max_groups, self.tile, self.lds_kb, self.block)
+                       self.step0, flags, self.max_groups, self.tile, self.lds_kb, self.block,
+                       self.wave)
 
 
 def default_params() -> Params:
@@ -148,7 +151,7 @@ def default_params() -> Params:
     load().alloc_params_default(ctypes.byref(p))
     return Params(p.max_dinkelbach, p.sweeps_per_dinkelbach, p.refit_period, p.fixed_count,
                   p.churn_limit, p.tol_dinkelbach, p.tol_dual, p.step0, p.max_groups, p.tile, p.lds_kb,
-                  p.block)
+                  p.block, p.wave)
 
 
 @dataclasses.dataclass

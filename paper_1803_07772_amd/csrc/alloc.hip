@@ -140,6 +140,8 @@ struct Drop {
   double* out_zs;          // [M][N][NP]
   Ctrl* ctrl;              // final control state for the host
   int tile;                // subcarriers per LDS tile (batched solver)
+  int wave;                // batched solver, one-workgroup drops: subcarriers per wave tile
+                           // (each wave runs its own subcarriers), 0 = workgroup tiles
   const double* p0;        // batched solver, warm start (device, may be null):
   const double* xi0;       //   initial powers [M][N][K], xi' [M], zeta' [K]
   const double* zeta0;
@@ -150,6 +152,13 @@ struct Drop {
 
 // Pointers into the workgroup's LDS: 32-bit addresses, direct LDS access.
 #define LDS __attribute__((address_space(3)))
+// Device memory reached through the drop descriptor: global (not generic)
+// accesses, so loads complete in order and are waited for one by one.
+#define GLB __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ GLB T* gl(T* p) {
+  return (GLB T*)p;
+}
 
 // LDS carve-up for one workgroup.  The table of array pointers itself sits in
 // LDS (written once per drop by thread 0): the pointers are reloaded from
@@ -215,23 +224,38 @@ struct Lds {
 
 __host__ __device__ inline size_t align8(size_t x) { return (x + 7) & ~size_t(7); }
 
-// Lays the arrays out from `base`; returns the bytes used.  With base ==
-// nullptr it only measures (host side).
-__host__ __device__ inline size_t carve_lds(LDS char* base, int M, int K, int L, int T, Lds* out) {
+// Parts of the carve-up: arrays read by every team during a pass, the pass
+// accumulators, and the per-tile arrays.
+enum LdsPart : int { kShared = 1, kAccum = 2, kTile = 4, kAllParts = 7 };
+
+// Lays the arrays of `parts` out from `base`; returns the bytes used (the
+// other pointers are left null).  With base == nullptr it only measures
+// (host side).
+__host__ __device__ inline size_t carve_lds(LDS char* base, int M, int K, int L, int T, Lds* out,
+                                            int parts = kAllParts) {
   Lds s;
   size_t o = 0;
+  int part = kAllParts;
   auto take = [&](size_t bytes) {
+    if (!(parts & part)) return (LDS char*)nullptr;
     LDS char* p = base ? base + o : nullptr;
     o += align8(bytes);
     return p;
   };
   const size_t TM = (size_t)T * M, TML = TM * L, TK = (size_t)T * K;
+  part = kTile;
   s.g = (LDS float*)take(sizeof(float) * TM * K);
   s.u = (LDS double*)take(sizeof(double) * TM * K);
+  part = kAccum;
   s.Sacc = (LDS double*)take(sizeof(double) * M * K);
-  s.mu = (LDS double*)take(sizeof(double) * K);
   s.racc = (LDS double*)take(sizeof(double) * K);
   s.rhacc = (LDS double*)take(sizeof(double) * K);
+  s.psacc = (LDS double*)take(sizeof(double) * M);
+  s.peacc = (LDS double*)take(sizeof(double) * M);
+  s.Racc = (LDS double*)take(sizeof(double) * M);
+  s.dmax = (LDS double*)take(sizeof(double) * M);
+  part = kShared;
+  s.mu = (LDS double*)take(sizeof(double) * K);
   s.Al = (LDS int*)take(sizeof(int) * K);
   s.el = (LDS int*)take(sizeof(int) * K);
   s.grp = (LDS int*)take(sizeof(int) * K);
@@ -239,6 +263,12 @@ __host__ __device__ inline size_t carve_lds(LDS char* base, int M, int K, int L,
   s.grp_off = (LDS int*)take(sizeof(int) * (M + 1));
   s.wcnt = (LDS int*)take(sizeof(int) * (kBlock / 64) * M);
   s.gcur = (LDS int*)take(sizeof(int) * M);
+  s.xi = (LDS double*)take(sizeof(double) * M);
+  s.eta = (LDS double*)take(sizeof(double) * M);
+  s.pmask = (LDS double*)take(sizeof(double) * M);
+  s.red = (LDS double*)take(sizeof(double) * kBlock);
+  s.tmp = (LDS double*)take(sizeof(double) * (M + 2));
+  part = kTile;
   s.Hc = (LDS double*)take(sizeof(double) * TK);
   s.pic = (LDS double*)take(sizeof(double) * TK);
   s.rk = (LDS double*)take(sizeof(double) * TK);
@@ -272,16 +302,38 @@ __host__ __device__ inline size_t carve_lds(LDS char* base, int M, int K, int L,
   s.chosen = (LDS int*)take(sizeof(int) * TML);
   s.nold = (LDS int*)take(sizeof(int) * TML);
   s.dmi = (LDS double*)take(sizeof(double) * TML);
-  s.xi = (LDS double*)take(sizeof(double) * M);
-  s.eta = (LDS double*)take(sizeof(double) * M);
-  s.pmask = (LDS double*)take(sizeof(double) * M);
-  s.psacc = (LDS double*)take(sizeof(double) * M);
-  s.peacc = (LDS double*)take(sizeof(double) * M);
-  s.Racc = (LDS double*)take(sizeof(double) * M);
-  s.dmax = (LDS double*)take(sizeof(double) * M);
-  s.red = (LDS double*)take(sizeof(double) * kBlock);
-  s.tmp = (LDS double*)take(sizeof(double) * (M + 2));
   if (out) *out = s;
+  return o;
+}
+
+// Wave-tile carve-up for W waves with T subcarriers each: the shared arrays
+// and the workgroup's accumulators once, then per wave its tile arrays and
+// its own accumulators (its table points at the shared arrays).  The
+// workgroup table's u (scratch before the first pass) is wave 0's.
+__host__ __device__ inline size_t carve_waves(LDS char* base, int M, int K, int L, int T, int W, Lds* common,
+                                              Lds* waves) {
+  Lds c;
+  size_t o = carve_lds(base, M, K, L, 0, &c, kShared | kAccum);
+  for (int w = 0; w < W; ++w) {
+    Lds v;
+    o += carve_lds(base ? base + o : nullptr, M, K, L, T, &v, kTile | kAccum);
+    v.mu = c.mu;
+    v.Al = c.Al;
+    v.el = c.el;
+    v.grp = c.grp;
+    v.grpk = c.grpk;
+    v.grp_off = c.grp_off;
+    v.wcnt = c.wcnt;
+    v.gcur = c.gcur;
+    v.xi = c.xi;
+    v.eta = c.eta;
+    v.pmask = c.pmask;
+    v.red = c.red;
+    v.tmp = c.tmp;
+    if (w == 0) c.u = v.u;
+    if (waves) waves[w] = v;
+  }
+  if (common) *common = c;
   return o;
 }
 
@@ -312,17 +364,17 @@ __device__ inline int load_shared(const int* p) {
 __device__ void begin_pass(const Drop& d, Lds& s) {
   const int M = d.M, K = d.K, tid = threadIdx.x, nth = blockDim.x;
   for (int k = tid; k < K; k += nth) {
-    s.el[k] = d.elastic[k];
-    s.mu[k] = d.elastic[k] ? 1.0 : d.zeta[k];
-    s.Al[k] = d.A[k];
+    s.el[k] = gl(d.elastic)[k];
+    s.mu[k] = gl(d.elastic)[k] ? 1.0 : gl(d.zeta)[k];
+    s.Al[k] = gl(d.A)[k];
     s.racc[k] = 0.0;
     s.rhacc[k] = 0.0;
   }
   for (int i = tid; i < M * K; i += nth) s.Sacc[i] = 0.0;
   for (int m = tid; m < M; m += nth) {
-    s.xi[m] = d.xi[m];
-    s.eta[m] = d.eta[m];
-    s.pmask[m] = d.pmask[m];
+    s.xi[m] = gl(d.xi)[m];
+    s.eta[m] = gl(d.eta)[m];
+    s.pmask[m] = gl(d.pmask)[m];
     s.psacc[m] = 0.0;
     s.peacc[m] = 0.0;
     s.Racc[m] = 0.0;
@@ -375,6 +427,23 @@ struct PassConst {
   int refit, reset, update, write_out;
 };
 
+// The threads that run one tile together: the whole workgroup (barriers), or
+// one wave (lanes run in lockstep and a wave's LDS operations complete in
+// order, so a fence against compiler reordering is all it needs).
+struct BlockTeam {
+  int tid, nth;
+  __device__ void sync() const { __syncthreads(); }
+};
+struct WaveTeam {
+  int tid;
+  static constexpr int nth = 64;
+  __device__ void sync() const {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
+};
+
 // One subcarrier of a sweep (update) or of an evaluation pass (no update).
 // Indexing of the per-tile LDS arrays (s = subcarrier within the tile).
 #define IX_MK(s, m, k) ((((s) * M) + (m)) * K + (k))
@@ -391,48 +460,90 @@ struct PassConst {
 // kItemH: step 6 runs one item per (t, m, k) and sums over t afterwards (the
 // batched solver's tiles span many subcarriers); otherwise one item per
 // (m, k) loops over t.  Both add the tile's H values in subcarrier order.
-template <bool kItemH>
-__device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s, int n0, int nstep,
-                     int ns) {
-  const int M = d.M, N = d.N, K = d.K, L = d.L, tid = threadIdx.x, nth = blockDim.x;
+template <bool kItemH, class Team>
+__device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassConst& pc, Lds& s, int n0,
+                     int nstep, int ns) {
+  const int M = d.M, N = d.N, K = d.K, L = d.L, tid = tm.tid, nth = tm.nth;
   const Divs& dv = d.dv;
   const double sg = d.sigma;
 #define NOF(t) (n0 + (t) * nstep)
 
-  // 1. gains, slot state and per-RRH totals into LDS
-  for (int i = tid; i < ns * M * K; i += nth) {
-    const int t = dv.MK.div(i), r = i - t * M * K, m = dv.K.div(r), k = r - m * K;
-    s.g[i] = d.G[((size_t)m * N + NOF(t)) * K + k];
-  }
-  for (int i = tid; i < ns * M * L; i += nth) {
-    const int t = dv.ML.div(i), r = i - t * M * L, m = dv.L.div(r), q = r - m * L;
-    const size_t gi = ((size_t)m * N + NOF(t)) * L + q;
-    s.su[i] = d.sel[gi];
-    s.sp[i] = d.p[gi];
-    s.sal[i] = pc.reset ? 1.0 : d.al[gi];
-    s.sbe[i] = pc.reset ? 0.0 : d.be[gi];
-    s.chosen[i] = -1;
-  }
-  for (int i = tid; i < ns * M * L * L; i += nth) {
-    const int t = dv.MLL.div(i), r = i - t * M * L * L, m = dv.LL.div(r), ab = r - m * L * L;
-    s.szs[i] = d.zs[((size_t)m * N + NOF(t)) * L * L + ab];
-    s.szn[i] = 0.0;
-  }
-  for (int i = tid; i < ns * M; i += nth) {
-    const int t = dv.M.div(i), m = i - t * M;
-    s.churn[i] = pc.reset ? 0 : d.churn_sel[(size_t)m * N + NOF(t)];
-    double acc = 0.0;  // total power of RRH m on the subcarrier
-    for (int q = 0; q < L; ++q) {
-      const size_t gi = ((size_t)m * N + NOF(t)) * L + q;
-      if (d.sel[gi] >= 0) acc += d.p[gi];
+  // 1. gains, slot state and per-RRH totals into LDS.  Within a round every
+  //    global load is issued before the first LDS store (the round waits for
+  //    memory once); the totals come from unconditional loads.
+  {
+    constexpr int kG = 6;  // gains per thread per round
+    const int nG = ns * M * K, nS = ns * M * L, nZ = nS * L, nP = ns * M;
+    const int rounds = max((nG + kG * nth - 1) / (kG * nth), (max(nZ, nP) + nth - 1) / nth);
+    for (int r0 = 0; r0 < rounds; ++r0) {
+      float gv[kG];
+#pragma unroll
+      for (int j = 0; j < kG; ++j) {
+        const int i = tid + (r0 * kG + j) * nth;
+        if (i < nG) {
+          const int t = dv.MK.div(i), r = i - t * M * K, m = dv.K.div(r), k = r - m * K;
+          gv[j] = gl(d.G)[((size_t)m * N + NOF(t)) * K + k];
+        }
+      }
+      const int i = tid + r0 * nth;
+      int sel = -1;
+      double p = 0.0, al = 1.0, be = 0.0, z = 0.0, pq[kMaxL];
+      int sq[kMaxL], ch = 0;
+      if (i < nS) {
+        const int t = dv.ML.div(i), r = i - t * M * L, m = dv.L.div(r), q = r - m * L;
+        const size_t gi = ((size_t)m * N + NOF(t)) * L + q;
+        sel = gl(d.sel)[gi];
+        p = gl(d.p)[gi];
+        if (!pc.reset) {
+          al = gl(d.al)[gi];
+          be = gl(d.be)[gi];
+        }
+      }
+      if (i < nZ) {
+        const int t = dv.MLL.div(i), r = i - t * M * L * L, m = dv.LL.div(r), ab = r - m * L * L;
+        z = gl(d.zs)[((size_t)m * N + NOF(t)) * L * L + ab];
+      }
+      if (i < nP) {
+        const int t = dv.M.div(i), m = i - t * M;
+        const size_t gi = ((size_t)m * N + NOF(t)) * L;
+        if (!pc.reset) ch = gl(d.churn_sel)[(size_t)m * N + NOF(t)];
+#pragma unroll
+        for (int q = 0; q < kMaxL; ++q) {
+          sq[q] = q < L ? gl(d.sel)[gi + q] : -1;
+          pq[q] = q < L ? gl(d.p)[gi + q] : 0.0;
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < kG; ++j) {
+        const int ij = tid + (r0 * kG + j) * nth;
+        if (ij < nG) s.g[ij] = gv[j];
+      }
+      if (i < nS) {
+        s.su[i] = sel;
+        s.sp[i] = p;
+        s.sal[i] = al;
+        s.sbe[i] = be;
+        s.chosen[i] = -1;
+      }
+      if (i < nZ) {
+        s.szs[i] = z;
+        s.szn[i] = 0.0;
+      }
+      if (i < nP) {
+        s.churn[i] = ch;
+        double acc = 0.0;  // total power of RRH m on the subcarrier
+#pragma unroll
+        for (int q = 0; q < kMaxL; ++q)
+          if (sq[q] >= 0) acc += pq[q];
+        s.Ptot[i] = acc;
+      }
     }
-    s.Ptot[i] = acc;
   }
   for (int i = tid; i < ns * K; i += nth) {
     s.rk[i] = 0.0;
     s.rhk[i] = 0.0;
   }
-  __syncthreads();
+  tm.sync();
 
   // 2. inter-cell interference as exclusive prefix + suffix over RRHs (no
   //    subtraction), stored as u = (sigma + ICI)/Gamma
@@ -451,7 +562,7 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
       s.u[IX_MK(t, m, k)] = (sg + ici) / gm;
     }
   }
-  __syncthreads();
+  tm.sync();
 
   // 3. SIC decoding order of each RRH's users: normalised gain descending
   //    (u ascending), ties to the lower user; position by rank
@@ -476,7 +587,7 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
     for (int q = 0; q < L; ++q) cnt += s.su[i * L + q] >= 0;
     s.vcnt[i] = cnt;
   }
-  __syncthreads();
+  tm.sync();
 
   // 4. per selected user: SINR, rate, SCALE refit and surrogate, price c
   for (int i = tid; i < ns * M * L; i += nth) {
@@ -486,7 +597,7 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
     for (int a2 = 0; a2 < a; ++a2) pre += s.sp[IX_ML(t, m, s.vslot[IX_ML(t, m, a2)])];
     const int k = s.vuser[i], q = s.vslot[i];
     const double pq = s.sp[IX_ML(t, m, q)];
-    const double wmk = d.w ? d.w[(size_t)m * K + k] : 1.0;
+    const double wmk = d.w ? gl(d.w)[(size_t)m * K + k] : 1.0;
     const double uu = s.vu[i];
     const double gam = pq / (uu + pre);
     const double rr = log2_1p(gam);
@@ -507,11 +618,11 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
     s.rhk[IX_SK(t, k)] = wmk * rh;
     if (pc.write_out) {
       const size_t o = ((size_t)m * N + NOF(t)) * L + a;
-      d.out_sel[o] = k;
-      d.out_p[o] = pq;
+      gl(d.out_sel)[o] = k;
+      gl(d.out_p)[o] = pq;
     }
   }
-  __syncthreads();
+  tm.sync();
   for (int i = tid; i < ns * M; i += nth) {
     const int t = dv.M.div(i), m = i - t * M;
     const int cnt = s.vcnt[i];
@@ -531,17 +642,17 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
     if (pc.write_out) {
       for (int a = cnt; a < L; ++a) {
         const size_t o = ((size_t)m * N + NOF(t)) * L + a;
-        d.out_sel[o] = -1;
-        d.out_p[o] = 0.0;
+        gl(d.out_sel)[o] = -1;
+        gl(d.out_p)[o] = 0.0;
       }
       int pi = 0;
       for (int a = 0; a < L; ++a)
         for (int b = a + 1; b < L; ++b, ++pi)
-          d.out_zs[((size_t)m * N + NOF(t)) * d.NP + pi] =
+          gl(d.out_zs)[((size_t)m * N + NOF(t)) * d.NP + pi] =
               (b < cnt) ? s.szs[IX_MLL(t, m, s.vslot[IX_ML(t, m, a)], s.vslot[IX_ML(t, m, b)])] : 0.0;
     }
   }
-  __syncthreads();
+  tm.sync();
   // tile sums into the pass accumulators, in subcarrier order
   for (int k = tid; k < K; k += nth) {
     double r = 0.0, rh = 0.0;
@@ -553,14 +664,18 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
     s.rhacc[k] += rh;
   }
   for (int m = tid; m < M; m += nth) {
+    double ps = s.psacc[m], pe = s.peacc[m], Rm = s.Racc[m];
     for (int t = 0; t < ns; ++t) {
-      s.psacc[m] += s.tps[IX_SM(t, m)];
-      s.peacc[m] += s.tpe[IX_SM(t, m)];
-      s.Racc[m] += s.tR[IX_SM(t, m)];
+      ps += s.tps[IX_SM(t, m)];
+      pe += s.tpe[IX_SM(t, m)];
+      Rm += s.tR[IX_SM(t, m)];
     }
+    s.psacc[m] = ps;
+    s.peacc[m] = pe;
+    s.Racc[m] = Rm;
   }
   if (!pc.update) {
-    __syncthreads();
+    tm.sync();
     return;
   }
 
@@ -607,7 +722,7 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
     s.szn[IX_MLL(t, m, sa, sb)] = zn;
     s.szn[IX_MLL(t, m, sb, sa)] = zn;
   }
-  __syncthreads();
+  tm.sync();
   for (int i = tid; i < ns * M; i += nth) {
     const int t = dv.M.div(i), m = i - t * M;
     double inter = 0.0, sic = 0.0;
@@ -622,11 +737,11 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
     for (int a = cnt - 1; a >= 0; --a) s.vT[IX_ML1(t, m, a)] = s.vT[IX_ML1(t, m, a + 1)] + s.vcg[IX_ML(t, m, a)];
     s.frozen[i] = sc.churn > 0 && s.churn[i] >= sc.churn;
   }
-  __syncthreads();
+  tm.sync();
 
   // 6. per-triple Lagrangian maximum H
   auto h_item = [&](int t, int m, int k, double u) -> double {
-    const double wmu = (d.w ? d.w[(size_t)m * K + k] : 1.0) * s.mu[k];
+    const double wmu = (d.w ? gl(d.w)[(size_t)m * K + k] : 1.0) * s.mu[k];
     const int cnt = s.vcnt[IX_SM(t, m)];
     int q = -1, pos = 0;
     for (int a = 0; a < cnt; ++a) {
@@ -663,7 +778,7 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
       const int t = dv.MK.div(i), r = i - t * M * K, m = dv.K.div(r), k = r - m * K;
       s.u[i] = h_item(t, m, k, s.u[i]);
     }
-    __syncthreads();
+    tm.sync();
     for (int i = tid; i < M * K; i += nth) {
       double Hsum = 0.0;
       for (int t = 0; t < ns; ++t) Hsum += s.u[t * M * K + i];
@@ -677,7 +792,7 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
       s.Sacc[i] += Hsum;
     }
   }
-  __syncthreads();
+  tm.sync();
 
   // 7. selection: the l best of RRH m's users with H > 0 (H desc, user asc),
   //    by each candidate's rank within its group
@@ -695,7 +810,7 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
     }
     if (rank < L) s.chosen[IX_ML(t, m, rank)] = k;
   }
-  __syncthreads();
+  tm.sync();
   for (int i = tid; i < ns * M; i += nth) {
     const int t = dv.M.div(i), m = i - t * M;
     const int cnt = s.vcnt[i];
@@ -714,9 +829,9 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
       if (!same) s.churn[i]++;
     }
     s.np[i] = np;
-    d.churn_sel[(size_t)m * N + NOF(t)] = s.churn[i];
+    gl(d.churn_sel)[(size_t)m * N + NOF(t)] = s.churn[i];
   }
-  __syncthreads();
+  tm.sync();
   // closed-form powers of the new selection
   for (int i = tid; i < ns * M * L; i += nth) {
     const int t = dv.ML.div(i), r = i - t * M * L, m = dv.L.div(r), a = r - m * L;
@@ -734,7 +849,7 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
         alph = s.sal[IX_ML(t, m, old)];
         bet = s.sbe[IX_ML(t, m, old)];
       }
-      const double wmu = (d.w ? d.w[(size_t)m * K + k] : 1.0) * s.mu[k];
+      const double wmu = (d.w ? gl(d.w)[(size_t)m * K + k] : 1.0) * s.mu[k];
       const double ps = s.psic[IX_SM(t, m)];
       const double pplus = fmax(ps, 0.0), pminus = fmax(-ps, 0.0);
       const double cp = (s.el[k] ? pc.E * s.eta[m] : 0.0) + s.xi[m] + s.pic[IX_SK(t, k)] +
@@ -753,12 +868,12 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
     s.nold[i] = old;
     s.dmi[i] = dm;
     const size_t gi = ((size_t)m * N + NOF(t)) * L + a;
-    d.sel[gi] = k;
-    d.p[gi] = pn;
-    d.al[gi] = alph;
-    d.be[gi] = bet;
+    gl(d.sel)[gi] = k;
+    gl(d.p)[gi] = pn;
+    gl(d.al)[gi] = alph;
+    gl(d.be)[gi] = bet;
   }
-  __syncthreads();
+  tm.sync();
   // C14 multipliers follow their user pair into the new slots
   for (int i = tid; i < ns * M * L * L; i += nth) {
     const int t = dv.MLL.div(i), r = i - t * M * L * L, m = dv.LL.div(r), rl = dv.L.div(r), a = rl - dv.L.div(rl) * L,
@@ -767,7 +882,7 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
     double z = 0.0;
     if (a < np && b < np && a != b && s.nold[IX_ML(t, m, a)] >= 0 && s.nold[IX_ML(t, m, b)] >= 0)
       z = s.szn[IX_MLL(t, m, s.nold[IX_ML(t, m, a)], s.nold[IX_ML(t, m, b)])];
-    d.zs[(((size_t)m * N + NOF(t)) * L + a) * L + b] = z;
+    gl(d.zs)[(((size_t)m * N + NOF(t)) * L + a) * L + b] = z;
   }
   for (int m = tid; m < M; m += nth) {
     double dm = s.dmax[m];
@@ -775,21 +890,21 @@ __device__ void tile(const Drop& d, const Sched& sc, const PassConst& pc, Lds& s
       for (int a = 0; a < L; ++a) dm = fmax(dm, s.dmi[IX_ML(t, m, a)]);
     s.dmax[m] = dm;
   }
-  __syncthreads();
+  tm.sync();
 #undef NOF
 }
 
 // Per-workgroup partials after its subcarriers.
 __device__ void write_partials(const Drop& d, const Lds& s, int b) {
   const int M = d.M, K = d.K, tid = threadIdx.x, nth = blockDim.x;
-  for (int i = tid; i < M * K; i += nth) d.S_part[(size_t)b * M * K + i] = s.Sacc[i];
+  for (int i = tid; i < M * K; i += nth) gl(d.S_part)[(size_t)b * M * K + i] = s.Sacc[i];
   for (int k = tid; k < K; k += nth) {
-    d.r_part[(size_t)b * K + k] = s.racc[k];
-    d.rh_part[(size_t)b * K + k] = s.rhacc[k];
+    gl(d.r_part)[(size_t)b * K + k] = s.racc[k];
+    gl(d.rh_part)[(size_t)b * K + k] = s.rhacc[k];
   }
   for (int m = tid; m < M; m += nth) {
-    d.psum_part[(size_t)b * M + m] = s.psacc[m];
-    d.pel_part[(size_t)b * M + m] = s.peacc[m];
+    gl(d.psum_part)[(size_t)b * M + m] = s.psacc[m];
+    gl(d.pel_part)[(size_t)b * M + m] = s.peacc[m];
   }
   if (tid == 0) {
     double R = 0.0, dm = 0.0;
@@ -797,8 +912,8 @@ __device__ void write_partials(const Drop& d, const Lds& s, int b) {
       R += s.Racc[m];
       dm = fmax(dm, s.dmax[m]);
     }
-    d.R_part[b] = R;
-    d.d_part[b] = dm;
+    gl(d.R_part)[b] = R;
+    gl(d.d_part)[b] = dm;
   }
 }
 
@@ -848,7 +963,7 @@ __device__ void reduce_pass(const Drop& d, const Sched& sc, const Ctrl& c, Lds& 
     if (update) reduce_groups<false>(s, d.S_part + k, G, M, (size_t)M * K, K, s.tmp + 2);
     if (tid == 0) {
       const double r = s.tmp[0], rh = s.tmp[1];
-      d.user_rate[k] = r;
+      gl(d.user_rate)[k] = r;
       if (update) {
         double best = -INFINITY;
         int bm = 0;
@@ -857,24 +972,24 @@ __device__ void reduce_pass(const Drop& d, const Sched& sc, const Ctrl& c, Lds& 
             best = s.tmp[2 + m];
             bm = m;
           }
-        int ch_A = c.reset ? 0 : d.churn_A[k];
-        const int before = d.A[k];
+        int ch_A = c.reset ? 0 : gl(d.churn_A)[k];
+        const int before = gl(d.A)[k];
         if (!(sc.churn > 0 && ch_A >= sc.churn)) {
           int after = before;
           if (best > 0.0)
             after = bm;
-          else if (d.elastic[k])
+          else if (gl(d.elastic)[k])
             after = -1;
           if (after != before) {
-            d.A[k] = after;
+            gl(d.A)[k] = after;
             ++ch_A;
             ++changes;
           }
         }
-        d.churn_A[k] = ch_A;
-        if (!d.elastic[k]) {
-          const double viol = fmin(fmax((d.psi[k] - rh) / d.psi[k], -1.0), 1.0);
-          d.zeta[k] = fmax(d.zeta[k] + delta_v * viol, 0.0);
+        gl(d.churn_A)[k] = ch_A;
+        if (!gl(d.elastic)[k]) {
+          const double viol = fmin(fmax((gl(d.psi)[k] - rh) / gl(d.psi)[k], -1.0), 1.0);
+          gl(d.zeta)[k] = fmax(gl(d.zeta)[k] + delta_v * viol, 0.0);
         }
       }
     }
@@ -891,12 +1006,12 @@ __device__ void reduce_pass(const Drop& d, const Sched& sc, const Ctrl& c, Lds& 
     if (update)
       for (int m = tid; m < M; m += blockDim.x) {
         const double ps = s.psacc[m];
-        const double scale = (double)d.N * d.L / (kLn2 * d.pmax[m]);
-        d.xi[m] = fmax(d.xi[m] + delta_v * scale * (ps - d.pmax[m]) / d.pmax[m], 0.0);
+        const double scale = (double)d.N * d.L / (kLn2 * gl(d.pmax)[m]);
+        gl(d.xi)[m] = fmax(gl(d.xi)[m] + delta_v * scale * (ps - gl(d.pmax)[m]) / gl(d.pmax)[m], 0.0);
       }
     if (tid == 0) {
       double P = d.pstatic;
-      for (int m = 0; m < M; ++m) P += d.eta[m] * s.peacc[m];
+      for (int m = 0; m < M; ++m) P += gl(d.eta)[m] * s.peacc[m];
       store_shared(&d.red[0], s.tmp[0]);
       store_shared(&d.red[1], P);
       store_shared(&d.red[2], s.tmp[1]);
@@ -970,7 +1085,8 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(Drop d, Sched sc) {
     pc.write_out = !update;
     begin_pass(d, s);
     const int nb = (d.N - b + G - 1) / G;  // my subcarriers: b, b+G, ...
-    for (int j = 0; j < nb; j += sc.tile) tile<false>(d, sc, pc, s, b + j * G, G, min(sc.tile, nb - j));
+    for (int j = 0; j < nb; j += sc.tile) tile<false>(BlockTeam{(int)threadIdx.x, (int)blockDim.x}, d, sc, pc, s, b + j * G, G,
+                                                   min(sc.tile, nb - j));
     write_partials(d, s, b);
     grid.sync();
     reduce_pass(d, sc, c, s, b, G, update, pc.delta_v);
@@ -991,13 +1107,13 @@ __global__ void __launch_bounds__(kBlock) solve_kernel(Drop d, Sched sc) {
 // 0); zeta' = max(zeta0, 0) (else 1) for streaming users, 0 for elastic.
 __device__ void block_start(const Drop& d, Lds& s) {
   const int M = d.M, N = d.N, K = d.K, L = d.L, tid = threadIdx.x, nth = blockDim.x;
-  const double* p0 = d.p0;
+  GLB const double* p0 = gl(d.p0);
   for (int i = tid; i < M * K; i += nth) {
     const int m = i / K, k = i - m * K;
     double acc = 0.0, pacc = 0.0;
     for (int n = 0; n < N; ++n) {
       const size_t gi = ((size_t)m * N + n) * K + k;
-      acc += log2_1p((double)d.G[gi] * d.pmask[m] / d.sigma);
+      acc += log2_1p((double)gl(d.G)[gi] * gl(d.pmask)[m] / d.sigma);
       if (p0) pacc += p0[gi];
     }
     s.Sacc[i] = acc;
@@ -1022,11 +1138,11 @@ __device__ void block_start(const Drop& d, Lds& s) {
         }
       if (wb >= 0) best = wb;
     }
-    d.A[k] = best;
-    d.churn_A[k] = 0;
-    d.zeta[k] = d.elastic[k] ? 0.0 : (d.zeta0 ? fmax(d.zeta0[k], 0.0) : 1.0);
+    gl(d.A)[k] = best;
+    gl(d.churn_A)[k] = 0;
+    gl(d.zeta)[k] = gl(d.elastic)[k] ? 0.0 : (d.zeta0 ? fmax(gl(d.zeta0)[k], 0.0) : 1.0);
   }
-  for (int m = tid; m < M; m += nth) d.xi[m] = d.xi0 ? fmax(d.xi0[m], 0.0) : 0.0;
+  for (int m = tid; m < M; m += nth) gl(d.xi)[m] = d.xi0 ? fmax(gl(d.xi0)[m], 0.0) : 0.0;
   __syncthreads();
   for (int i = tid; i < M * N; i += nth) {
     const int m = i / N, n = i - m * N;
@@ -1034,14 +1150,14 @@ __device__ void block_start(const Drop& d, Lds& s) {
     double bv[kMaxL];
     int cnt = 0;
     for (int k = 0; k < K; ++k) {
-      if (d.A[k] != m) continue;
+      if (gl(d.A)[k] != m) continue;
       const size_t gi = ((size_t)m * N + n) * K + k;
       double v;
       if (p0) {
         v = p0[gi];
         if (!(v > 0.0)) continue;
       } else {
-        v = d.G[gi];
+        v = gl(d.G)[gi];
       }
       int t = cnt < L ? cnt : L;
       while (t > 0 && (bv[t - 1] < v || (bv[t - 1] == v && bk[t - 1] > k))) {
@@ -1059,13 +1175,13 @@ __device__ void block_start(const Drop& d, Lds& s) {
     }
     const size_t base = ((size_t)m * N + n) * L;
     for (int a = 0; a < L; ++a) {
-      d.sel[base + a] = a < cnt ? bk[a] : -1;
-      d.p[base + a] = a < cnt ? (p0 ? fmin(bv[a], d.pmask[m]) : d.pmax[m] / ((double)N * L)) : 0.0;
-      d.al[base + a] = 1.0;
-      d.be[base + a] = 0.0;
-      for (int b = 0; b < L; ++b) d.zs[(base + a) * L + b] = 0.0;
+      gl(d.sel)[base + a] = a < cnt ? bk[a] : -1;
+      gl(d.p)[base + a] = a < cnt ? (p0 ? fmin(bv[a], gl(d.pmask)[m]) : gl(d.pmax)[m] / ((double)N * L)) : 0.0;
+      gl(d.al)[base + a] = 1.0;
+      gl(d.be)[base + a] = 0.0;
+      for (int b = 0; b < L; ++b) gl(d.zs)[(base + a) * L + b] = 0.0;
     }
-    d.churn_sel[i] = 0;
+    gl(d.churn_sel)[i] = 0;
   }
   __syncthreads();
 }
@@ -1076,7 +1192,7 @@ __device__ void block_reduce(const Drop& d, const Sched& sc, const Ctrl& c, Lds&
                              double delta_v, int* changes) {
   const int M = d.M, K = d.K, tid = threadIdx.x, nth = blockDim.x;
   for (int k = tid; k < K; k += nth) {
-    d.user_rate[k] = s.racc[k];
+    gl(d.user_rate)[k] = s.racc[k];
     if (!update) continue;
     double best = -INFINITY;
     int bm = 0;
@@ -1085,31 +1201,31 @@ __device__ void block_reduce(const Drop& d, const Sched& sc, const Ctrl& c, Lds&
         best = s.Sacc[m * K + k];
         bm = m;
       }
-    int ch_A = c.reset ? 0 : d.churn_A[k];
-    const int before = d.A[k];
+    int ch_A = c.reset ? 0 : gl(d.churn_A)[k];
+    const int before = gl(d.A)[k];
     if (!(sc.churn > 0 && ch_A >= sc.churn)) {
       int after = before;
       if (best > 0.0)
         after = bm;
-      else if (d.elastic[k])
+      else if (gl(d.elastic)[k])
         after = -1;
       if (after != before) {
-        d.A[k] = after;
+        gl(d.A)[k] = after;
         ++ch_A;
         atomicAdd(changes, 1);
       }
     }
-    d.churn_A[k] = ch_A;
-    if (!d.elastic[k]) {
-      const double viol = fmin(fmax((d.psi[k] - s.rhacc[k]) / d.psi[k], -1.0), 1.0);
-      d.zeta[k] = fmax(d.zeta[k] + delta_v * viol, 0.0);
+    gl(d.churn_A)[k] = ch_A;
+    if (!gl(d.elastic)[k]) {
+      const double viol = fmin(fmax((gl(d.psi)[k] - s.rhacc[k]) / gl(d.psi)[k], -1.0), 1.0);
+      gl(d.zeta)[k] = fmax(gl(d.zeta)[k] + delta_v * viol, 0.0);
     }
   }
   if (update)
     for (int m = tid; m < M; m += nth) {
       const double ps = s.psacc[m];
-      const double scale = (double)d.N * d.L / (kLn2 * d.pmax[m]);
-      d.xi[m] = fmax(d.xi[m] + delta_v * scale * (ps - d.pmax[m]) / d.pmax[m], 0.0);
+      const double scale = (double)d.N * d.L / (kLn2 * gl(d.pmax)[m]);
+      gl(d.xi)[m] = fmax(gl(d.xi)[m] + delta_v * scale * (ps - gl(d.pmax)[m]) / gl(d.pmax)[m], 0.0);
     }
   __syncthreads();
 }
@@ -1170,8 +1286,62 @@ __device__ inline Ctrl initial_ctrl(const Drop& d) {
   return c0;
 }
 
+// Wave tiles: wave w of W runs subcarriers w, w + W, ... into its own
+// accumulators, which are then summed in wave order.
+__device__ __attribute__((always_inline)) void wave_pass(const Drop& d, const Sched& sd, const PassConst& pc, Lds& s, Lds* sw) {
+  const int M = d.M, K = d.K, W = blockDim.x >> 6;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const WaveTeam tm{(int)(threadIdx.x & 63)};
+  Lds& v = sw[w];
+  for (int i = tm.tid; i < M * K; i += tm.nth) v.Sacc[i] = 0.0;
+  for (int k = tm.tid; k < K; k += tm.nth) {
+    v.racc[k] = 0.0;
+    v.rhacc[k] = 0.0;
+  }
+  for (int m = tm.tid; m < M; m += tm.nth) {
+    v.psacc[m] = 0.0;
+    v.peacc[m] = 0.0;
+    v.Racc[m] = 0.0;
+    v.dmax[m] = 0.0;
+  }
+  tm.sync();
+  const int nb = (d.N - w + W - 1) / W;  // subcarriers of this wave
+  for (int j = 0; j < nb; j += d.wave) tile<true>(tm, d, sd, pc, v, w + j * W, W, min(d.wave, nb - j));
+  __syncthreads();
+  const int tid = threadIdx.x, nth = blockDim.x;
+  for (int i = tid; i < M * K; i += nth) {
+    double a = 0.0;
+    for (int u = 0; u < W; ++u) a += sw[u].Sacc[i];
+    s.Sacc[i] = a;
+  }
+  for (int k = tid; k < K; k += nth) {
+    double r = 0.0, rh = 0.0;
+    for (int u = 0; u < W; ++u) {
+      r += sw[u].racc[k];
+      rh += sw[u].rhacc[k];
+    }
+    s.racc[k] = r;
+    s.rhacc[k] = rh;
+  }
+  for (int m = tid; m < M; m += nth) {
+    double ps = 0.0, pe = 0.0, R = 0.0, dm = 0.0;
+    for (int u = 0; u < W; ++u) {
+      ps += sw[u].psacc[m];
+      pe += sw[u].peacc[m];
+      R += sw[u].Racc[m];
+      dm = fmax(dm, sw[u].dmax[m]);
+    }
+    s.psacc[m] = ps;
+    s.peacc[m] = pe;
+    s.Racc[m] = R;
+    s.dmax[m] = dm;
+  }
+  __syncthreads();
+}
+
 // A drop solved by one workgroup, every reduction inside it.
-__device__ void solve_single(const Drop& d, const Sched& sd, Lds& s, Ctrl& s_c, int& s_changes, Ctrl* out) {
+__device__ __attribute__((always_inline)) void solve_single(const Drop& d, const Sched& sd, Lds& s, Lds* sw, Ctrl& s_c, int& s_changes,
+                             Ctrl* out) {
   block_start(d, s);
   if (threadIdx.x == 0) s_c = initial_ctrl(d);
   __syncthreads();
@@ -1187,13 +1357,17 @@ __device__ void solve_single(const Drop& d, const Sched& sd, Lds& s, Ctrl& s_c, 
     pc.write_out = !update;
     if (threadIdx.x == 0) s_changes = 0;
     begin_pass(d, s);
-    for (int n0 = 0; n0 < d.N; n0 += sd.tile) tile<true>(d, sd, pc, s, n0, 1, min(sd.tile, d.N - n0));
+    if (d.wave > 0)
+      wave_pass(d, sd, pc, s, sw);
+    else
+      for (int n0 = 0; n0 < d.N; n0 += sd.tile)
+        tile<true>(BlockTeam{(int)threadIdx.x, (int)blockDim.x}, d, sd, pc, s, n0, 1, min(sd.tile, d.N - n0));
     block_reduce(d, sd, c, s, update, pc.delta_v, &s_changes);
     if (threadIdx.x == 0) {
       double R = 0.0, P = d.pstatic, dm = 0.0;
       for (int m = 0; m < d.M; ++m) {
         R += s.Racc[m];
-        P += d.eta[m] * s.peacc[m];
+        P += gl(d.eta)[m] * s.peacc[m];
         dm = fmax(dm, s.dmax[m]);
       }
       Ctrl cn = c;
@@ -1209,7 +1383,7 @@ __device__ void solve_single(const Drop& d, const Sched& sd, Lds& s, Ctrl& s_c, 
 // A drop solved by G workgroups together, this one of rank r: the grid
 // solver's pass (subcarriers r, r+G, ..., partials, fixed-order reductions)
 // with the group barrier in place of the grid barrier.
-__device__ void solve_group(const Drop& d, const Sched& sd, Lds& s, int r, int G, Ctrl* out) {
+__device__ __attribute__((always_inline)) void solve_group(const Drop& d, const Sched& sd, Lds& s, int r, int G, Ctrl* out) {
   if (r == 0) {
     if (threadIdx.x == 0) {
       store_shared(&d.chg_count[0], 0);
@@ -1230,7 +1404,8 @@ __device__ void solve_group(const Drop& d, const Sched& sd, Lds& s, int r, int G
     pc.write_out = !update;
     begin_pass(d, s);
     const int nb = (d.N - r + G - 1) / G;
-    for (int j = 0; j < nb; j += sd.tile) tile<false>(d, sd, pc, s, r + j * G, G, min(sd.tile, nb - j));
+    for (int j = 0; j < nb; j += sd.tile) tile<false>(BlockTeam{(int)threadIdx.x, (int)blockDim.x}, d, sd, pc, s, r + j * G, G,
+                                                   min(sd.tile, nb - j));
     write_partials(d, s, r);
     if (!(ok = group_sync(d.bar, G))) break;
     reduce_pass(d, sd, c, s, r, G, update, pc.delta_v);
@@ -1252,25 +1427,31 @@ __device__ void solve_group(const Drop& d, const Sched& sd, Lds& s, int r, int G
 // Slots go out in order and every workgroup is resident, so the earliest
 // unfinished drop always has all its ranks running: no group waits forever.
 __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4)))
-batch_kernel(const Drop* drops, const int2* slots, int S, Sched sc, int* queue, Ctrl* ctrls) {
+batch_kernel(const Drop* __restrict__ drops, const int2* __restrict__ slots, int S, Sched sc, int* queue, Ctrl* ctrls) {
   extern __shared__ __align__(16) char smem[];
   __shared__ int s_idx, s_changes;
   __shared__ Ctrl s_c;
   __shared__ Lds s_tab;
+  __shared__ Lds s_wtab[kBlock / 64];
   for (;;) {
     if (threadIdx.x == 0) s_idx = atomicAdd(queue, 1);
     __syncthreads();
-    const int idx = s_idx;
+    const int idx = __builtin_amdgcn_readfirstlane(s_idx);
     __syncthreads();
     if (idx >= S) break;
     const int2 sl = slots[idx];
     const Drop& d = drops[sl.x];
     Sched sd = sc;
     sd.tile = d.tile;
-    if (threadIdx.x == 0) carve_lds((LDS char*)smem, d.M, d.K, d.L, sd.tile, &s_tab);
+    if (threadIdx.x == 0) {
+      if (d.wave > 0)
+        carve_waves((LDS char*)smem, d.M, d.K, d.L, d.wave, blockDim.x >> 6, &s_tab, s_wtab);
+      else
+        carve_lds((LDS char*)smem, d.M, d.K, d.L, sd.tile, &s_tab);
+    }
     __syncthreads();
     if (d.group <= 1)
-      solve_single(d, sd, s_tab, s_c, s_changes, ctrls + sl.x);
+      solve_single(d, sd, s_tab, s_wtab, s_c, s_changes, ctrls + sl.x);
     else
       solve_group(d, sd, s_tab, sl.y, d.group, ctrls + sl.x);
   }
@@ -1286,7 +1467,7 @@ __global__ void cold_assoc_kernel(Drop d, double* snr) {
   const int m = i / d.K, k = i - m * d.K;
   double acc = 0.0;
   for (int n = 0; n < d.N; ++n)
-    acc += log2_1p((double)d.G[((size_t)m * d.N + n) * d.K + k] * d.pmask[m] / d.sigma);
+    acc += log2_1p((double)gl(d.G)[((size_t)m * d.N + n) * d.K + k] * gl(d.pmask)[m] / d.sigma);
   snr[i] = acc;
 }
 
@@ -1314,9 +1495,9 @@ __global__ void cold_pick_kernel(Drop d, const double* snr, const double* p0sum)
     }
     if (wb >= 0) best = wb;
   }
-  d.A[k] = best;
-  d.churn_A[k] = 0;
-  d.zeta[k] = d.elastic[k] ? 0.0 : 1.0;
+  gl(d.A)[k] = best;
+  gl(d.churn_A)[k] = 0;
+  gl(d.zeta)[k] = gl(d.elastic)[k] ? 0.0 : 1.0;
 }
 
 // Strongest l users of RRH m on n (by Gamma, or by initial power when warm).
@@ -1328,13 +1509,13 @@ __global__ void cold_select_kernel(Drop d, const double* p0) {
   double bv[kMaxL];
   int cnt = 0;
   for (int k = 0; k < d.K; ++k) {
-    if (d.A[k] != m) continue;
+    if (gl(d.A)[k] != m) continue;
     double v;
     if (p0) {
       v = p0[((size_t)m * d.N + n) * d.K + k];
       if (!(v > 0.0)) continue;
     } else {
-      v = d.G[((size_t)m * d.N + n) * d.K + k];
+      v = gl(d.G)[((size_t)m * d.N + n) * d.K + k];
     }
     int t = cnt < L ? cnt : L;
     while (t > 0 && (bv[t - 1] < v || (bv[t - 1] == v && bk[t - 1] > k))) {
@@ -1352,15 +1533,15 @@ __global__ void cold_select_kernel(Drop d, const double* p0) {
   }
   const size_t base = ((size_t)m * d.N + n) * L;
   for (int a = 0; a < L; ++a) {
-    d.sel[base + a] = a < cnt ? bk[a] : -1;
+    gl(d.sel)[base + a] = a < cnt ? bk[a] : -1;
     double pa = 0.0;
-    if (a < cnt) pa = p0 ? fmin(bv[a], d.pmask[m]) : d.pmax[m] / ((double)d.N * L);
-    d.p[base + a] = pa;
-    d.al[base + a] = 1.0;
-    d.be[base + a] = 0.0;
-    for (int b = 0; b < L; ++b) d.zs[(base + a) * L + b] = 0.0;
+    if (a < cnt) pa = p0 ? fmin(bv[a], gl(d.pmask)[m]) : gl(d.pmax)[m] / ((double)d.N * L);
+    gl(d.p)[base + a] = pa;
+    gl(d.al)[base + a] = 1.0;
+    gl(d.be)[base + a] = 0.0;
+    for (int b = 0; b < L; ++b) gl(d.zs)[(base + a) * L + b] = 0.0;
   }
-  d.churn_sel[i] = 0;
+  gl(d.churn_sel)[i] = 0;
 }
 
 __global__ void p0_sum_kernel(Drop d, const double* p0, double* out) {
@@ -1376,8 +1557,8 @@ __global__ void p0_sum_kernel(Drop d, const double* p0, double* out) {
 // for streaming users (1 without zeta0), 0 for elastic users.
 __global__ void init_mult_kernel(Drop d, const double* xi0, const double* zeta0) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < d.M) d.xi[i] = xi0 ? fmax(xi0[i], 0.0) : 0.0;
-  if (i < d.K) d.zeta[i] = d.elastic[i] ? 0.0 : (zeta0 ? fmax(zeta0[i], 0.0) : 1.0);
+  if (i < d.M) gl(d.xi)[i] = xi0 ? fmax(xi0[i], 0.0) : 0.0;
+  if (i < d.K) gl(d.zeta)[i] = gl(d.elastic)[i] ? 0.0 : (zeta0 ? fmax(zeta0[i], 0.0) : 1.0);
 }
 
 // Dense [M][N][K] powers from the decoding-order slots.
@@ -1393,8 +1574,8 @@ __global__ void scatter_kernel(Drop d, float* out) {
   if (i >= d.M * d.N) return;
   const int m = i / d.N, n = i - m * d.N;
   for (int a = 0; a < d.L; ++a) {
-    const int k = d.out_sel[(size_t)i * d.L + a];
-    if (k >= 0) out[((size_t)m * d.N + n) * d.K + k] = (float)d.out_p[(size_t)i * d.L + a];
+    const int k = gl(d.out_sel)[(size_t)i * d.L + a];
+    if (k >= 0) out[((size_t)m * d.N + n) * d.K + k] = (float)gl(d.out_p)[(size_t)i * d.L + a];
   }
 }
 
@@ -1420,7 +1601,8 @@ int validate(const alloc_problem* pb, const alloc_params* prm) {
   if (!std::isfinite(pb->noise_w)) return ALLOC_EINVAL;
   if (pb->M > kMaxM || pb->l > kMaxL || pb->K > kMaxK || pb->M * pb->K > kMaxMK) return ALLOC_ETOOBIG;
   if (prm->sweeps_per_dinkelbach < 1 || prm->max_dinkelbach < 1 || prm->max_groups < 0 || prm->tile < 0 ||
-      prm->lds_kb < 0 || !(prm->block == 0 || prm->block == 256 || prm->block == 512))
+      prm->lds_kb < 0 || !(prm->block == 0 || prm->block == 256 || prm->block == 512) || prm->wave < 0 ||
+      prm->wave > 16)
     return ALLOC_EINVAL;
   for (int m = 0; m < pb->M; ++m) {
     if (!(pb->pmax_w[m] > 0) || !std::isfinite(pb->pmax_w[m])) return ALLOC_EINVAL;
@@ -1471,6 +1653,7 @@ void alloc_params_default(alloc_params* p) {
   p->tile = 0;
   p->lds_kb = 0;
   p->block = 0;
+  p->wave = 0;
 }
 
 int alloc_ctx_set_timing(alloc_ctx* ctx, int enable) {
@@ -1820,20 +2003,35 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
     }
   }
   if (hipSetDevice(ctx->device) != hipSuccess) return ALLOC_EDEVICE;
-  // LDS per workgroup: the whole CU (the kernel's static LDS stays below
-  // 1 KB), or the requested share, raised to what the largest drop needs
-  const size_t full = ctx->lds_max - 1024;
-  size_t need = 0;
-  for (int b = 0; b < B; ++b) need = std::max(need, carve_lds(nullptr, probs[b].M, probs[b].K, probs[b].l, 1, nullptr));
+  // LDS per workgroup (dynamic part; the kernel's static LDS on top): the
+  // whole CU, or the requested share, raised to what the largest drop needs;
+  // with wave tiles and no request, what the largest wave-tiled drop needs
+  hipFuncAttributes fa;
+  if (hipFuncGetAttributes(&fa, (const void*)batch_kernel) != hipSuccess) return ALLOC_EDEVICE;
+  const size_t stat = fa.sharedSizeBytes;
+  const size_t full = ctx->lds_max - stat;
+  const int nthreads = prm->block > 0 ? prm->block : kBlock;
+  const int nwaves = nthreads / 64;
+  size_t need = 0, need_wave = 0;
+  for (int b = 0; b < B; ++b) {
+    const alloc_problem& pb = probs[b];
+    need = std::max(need, carve_lds(nullptr, pb.M, pb.K, pb.l, 1, nullptr));
+    if (prm->wave > 0) {
+      const size_t w = carve_waves(nullptr, pb.M, pb.K, pb.l, prm->wave, nwaves, nullptr, nullptr);
+      if (w <= full) need_wave = std::max(need_wave, w);
+    }
+  }
   if (need > full) return ALLOC_ETOOBIG;
   size_t budget = full;
-  if (prm->lds_kb > 0) budget = std::max(need, std::min(full, (size_t)prm->lds_kb * 1024 - std::min<size_t>(1024, (size_t)prm->lds_kb * 1024)));
+  if (prm->lds_kb > 0)
+    budget = std::max(need, std::min(full, (size_t)prm->lds_kb * 1024 - std::min<size_t>(stat, (size_t)prm->lds_kb * 1024)));
+  else if (need_wave > 0)
+    budget = std::max(need, need_wave);
 
-  const int nthreads = prm->block > 0 ? prm->block : kBlock;
   P.threads = nthreads;
   int per_cu = 0;
   if (hipFuncSetAttribute((const void*)batch_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                          (int)(ctx->lds_max - 1024)) != hipSuccess ||
+                          (int)full) != hipSuccess ||
       hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)batch_kernel, nthreads, budget) !=
           hipSuccess)
     return ALLOC_EDEVICE;
@@ -2017,6 +2215,10 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
     int T = prm->tile > 0 ? std::min(prm->tile, nb) : nb;
     while (T > 1 && carve_lds(nullptr, M, K, L, T, nullptr) > budget) --T;
     d.tile = T;
+    d.wave = (g == 1 && prm->wave > 0 &&
+              carve_waves(nullptr, M, K, L, prm->wave, nwaves, nullptr, nullptr) <= budget)
+                 ? prm->wave
+                 : 0;
   }
   // slots, largest work per slot first; a drop's slots are consecutive
   std::vector<int> order(B);

@@ -3,7 +3,9 @@
 The choices are the LDS share of a workgroup (``lds_kb``: a whole compute
 unit, or a half, a third or a quarter so that several workgroups share one),
 the cap on subcarriers per LDS tile (``tile``) and the threads per workgroup
-(``block``: 512, or 256 for more, smaller workgroups per compute unit).  They change only the order of
+(``block``: 512, or 256 for more, smaller workgroups per compute unit) and
+whether each wave runs its own subcarriers (``wave``: subcarriers per wave
+tile, 0 = tiles of the whole workgroup).  They change only the order of
 floating-point sums inside a drop, not the method.  Candidates are timed on
 the GPU (the batched kernel's HIP-event duration) on the whole batch, so the
 load per workgroup (and which drops are split over several workgroups) is the
@@ -23,15 +25,19 @@ import numpy as np
 from . import Params
 
 CANDIDATES = (
-    {"lds_kb": 0, "tile": 0, "block": 512},
-    {"lds_kb": 79, "tile": 0, "block": 512},
-    {"lds_kb": 52, "tile": 0, "block": 512},
-    {"lds_kb": 0, "tile": 8, "block": 512},
-    {"lds_kb": 79, "tile": 8, "block": 512},
-    {"lds_kb": 79, "tile": 0, "block": 256},
-    {"lds_kb": 52, "tile": 0, "block": 256},
-    {"lds_kb": 39, "tile": 0, "block": 256},
-    {"lds_kb": 0, "tile": 8, "block": 256},
+    {"lds_kb": 0, "tile": 0, "block": 512, "wave": 0},
+    {"lds_kb": 79, "tile": 0, "block": 512, "wave": 0},
+    {"lds_kb": 52, "tile": 0, "block": 512, "wave": 0},
+    {"lds_kb": 0, "tile": 8, "block": 512, "wave": 0},
+    {"lds_kb": 79, "tile": 8, "block": 512, "wave": 0},
+    {"lds_kb": 79, "tile": 0, "block": 256, "wave": 0},
+    {"lds_kb": 52, "tile": 0, "block": 256, "wave": 0},
+    {"lds_kb": 39, "tile": 0, "block": 256, "wave": 0},
+    {"lds_kb": 0, "tile": 8, "block": 256, "wave": 0},
+    {"lds_kb": 0, "tile": 0, "block": 512, "wave": 1},
+    {"lds_kb": 0, "tile": 0, "block": 256, "wave": 1},
+    {"lds_kb": 0, "tile": 0, "block": 512, "wave": 2},
+    {"lds_kb": 0, "tile": 0, "block": 256, "wave": 2},
 )
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 
@@ -75,7 +81,7 @@ def tuned(drops, params: Params, cache: dict | None = None) -> Params:
     if not e:
         return params
     return dataclasses.replace(params, lds_kb=int(e["lds_kb"]), tile=int(e["tile"]),
-                               block=int(e.get("block", 0)))
+                               block=int(e.get("block", 0)), wave=int(e.get("wave", 0)))
 
 
 def tune(ctx, drops, params: Params, gains=None, sweeps: int = 12,
@@ -98,7 +104,7 @@ def tune(ctx, drops, params: Params, gains=None, sweeps: int = 12,
     fastest = min(t for t, _ in times)
     best = next(c for t, c in times if t <= 1.02 * fastest)
     if cache is not None:
-        cache[batch_key(drops)] = dict(best, ms={f"{c['lds_kb']}/{c['tile']}/{c['block']}": round(t, 3)
+        cache[batch_key(drops)] = dict(best, ms={"/".join(str(c[f]) for f in ("lds_kb", "tile", "block", "wave")): round(t, 3)
                                                  for t, c in times},
                                       drops=len(drops), sweeps=sweeps)
     return best, times

@@ -224,6 +224,61 @@ def test_lds_cap_shares_compute_units(ctx):
         assert np.array_equal(a.sel, b.sel)
 
 
+def test_wave_tiles_match_oracle(ctx):
+    """Each wave running its own subcarriers (no workgroup barrier inside a
+    pass) on ragged drops, including drops with fewer subcarriers than waves:
+    parity with the oracle per drop."""
+    import torch
+
+    import paper_1803_07772_amd as pa
+    drops = _mixed_batch()
+    op = oracle.Params(fixed_count=0, sweeps_per_dinkelbach=120)
+    # three workgroups in all: no drop is split over several
+    p = pa.Params(fixed_count=0, sweeps_per_dinkelbach=120, max_groups=3)
+    gains = [torch.from_numpy(d.gain).cuda() for d in drops]
+    for wave, blk in ((1, 0), (2, 256)):
+        print(f"[gpu case] wave tiles: wave={wave} block={blk}, {len(drops)} mixed drops", flush=True)
+        res = ctx.solve_batch(drops, dataclasses.replace(p, wave=wave, block=blk), gains=gains)
+        chaotic = 0
+        for d, r in zip(drops, res):
+            o = oracle.solve(d, op)
+
+            def rerun(scale, d=d):
+                return oracle.solve(dataclasses.replace(d, noise_w=d.noise_w * scale), op)
+
+            info = parity.compare(d, r, o, label=f"wave={wave} drop {d.index} {d.M}x{d.N}x{d.K} l={d.l}",
+                                  rerun=rerun)
+            print(info, flush=True)
+            chaotic += bool(info.get("skipped"))
+        assert chaotic <= 3
+
+
+def test_wave_tiles_agree_with_workgroup_tiles(ctx):
+    """Wave tiles only change the order of the sums over subcarriers: the
+    same allocations as workgroup tiles; replays of a captured wave-tiled
+    batch equal the eager solve."""
+    import paper_1803_07772_amd as pa
+    drops = [synth.make_drop(synth.CFG2, 70 + i, i) for i in range(6)]
+    p = pa.Params(fixed_count=0, sweeps_per_dinkelbach=60, max_groups=6)
+    print("[gpu case] wave tiles vs workgroup tiles, 6 drops", flush=True)
+    ref = ctx.solve_batch(drops, p)
+    for wave, blk in ((1, 0), (2, 0), (1, 256), (4, 256)):
+        q = dataclasses.replace(p, wave=wave, block=blk)
+        for a, b in zip(ctx.solve_batch(drops, q), ref):
+            assert abs(a.ee - b.ee) <= 1e-9 * abs(b.ee), (wave, blk)
+            assert np.array_equal(a.sel, b.sel) and np.array_equal(a.rrh_of_user, b.rrh_of_user)
+    with pytest.raises(pa.AllocError, match="-22"):
+        ctx.solve_batch(drops[:1], dataclasses.replace(p, wave=17))
+    q = dataclasses.replace(p, wave=1)
+    eager = ctx.solve_batch(drops, q)
+    bt = pa.Batch(ctx, drops, q)
+    for rep in range(2):
+        bt.run()
+        for a, b in zip(bt.results(), eager):
+            _same(a, b)
+    bt.close()
+
+
 def test_autotuner_picks_a_candidate(ctx):
     import paper_1803_07772_amd as pa
     from paper_1803_07772_amd import tune
@@ -235,7 +290,7 @@ def test_autotuner_picks_a_candidate(ctx):
     assert best in tune.CANDIDATES and len(times) == len(tune.CANDIDATES)
     assert all(t > 0 for t, _ in times)
     key = tune.batch_key(drops)
-    assert cache[key]["lds_kb"] == best["lds_kb"] and cache[key]["tile"] == best["tile"]
+    assert all(cache[key][f] == best[f] for f in ("lds_kb", "tile", "block", "wave"))
     q = tune.tuned(drops, p, cache)
     ref = ctx.solve_batch(drops[:4], p)
     for a, b in zip(ctx.solve_batch(drops[:4], q), ref):

@@ -26,6 +26,8 @@ def test_tuned_params_from_cache(tmp_path):
     p = tune.tuned(drops, Params(fixed_count=0), cache)
     assert p == dataclasses.replace(Params(fixed_count=0), lds_kb=79, tile=8)
     assert tune.tuned(drops, Params(), {}) == Params()
+    full = {"M8-N64-K32-l2": {"lds_kb": 0, "tile": 0, "block": 256, "wave": 2}}
+    assert tune.tuned(drops, Params(), full) == dataclasses.replace(Params(), block=256, wave=2)
     path = tmp_path / "c.json"
     tune.save_cache(cache, str(path))
     assert tune.load_cache(str(path)) == cache
