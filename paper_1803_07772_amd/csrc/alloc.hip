@@ -339,6 +339,23 @@ __host__ __device__ inline size_t carve_waves(LDS char* base, int M, int K, int 
 
 __device__ inline double log2_1p(double x) { return log1p(x) / kLn2; }
 
+// init + at(0) + at(1) + ... + at(n-1), added in that order; the loads of
+// each group of eight are issued together (at() is called on clamped
+// indices only).
+template <class F>
+__device__ __forceinline__ double seq_sum(int n, double init, F&& at) {
+  double acc = init;
+  for (int t0 = 0; t0 < n; t0 += 8) {
+    double v[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) v[j] = at(min(t0 + j, n - 1));
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (t0 + j < n) acc += v[j];
+  }
+  return acc;
+}
+
 // Loop-control inputs cross workgroups (and XCDs): stored and loaded with
 // device-scope atomics so every workgroup reads the same value after a grid
 // barrier.
@@ -655,24 +672,13 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
   tm.sync();
   // tile sums into the pass accumulators, in subcarrier order
   for (int k = tid; k < K; k += nth) {
-    double r = 0.0, rh = 0.0;
-    for (int t = 0; t < ns; ++t) {
-      r += s.rk[IX_SK(t, k)];
-      rh += s.rhk[IX_SK(t, k)];
-    }
-    s.racc[k] += r;
-    s.rhacc[k] += rh;
+    s.racc[k] += seq_sum(ns, 0.0, [&](int t) { return s.rk[IX_SK(t, k)]; });
+    s.rhacc[k] += seq_sum(ns, 0.0, [&](int t) { return s.rhk[IX_SK(t, k)]; });
   }
   for (int m = tid; m < M; m += nth) {
-    double ps = s.psacc[m], pe = s.peacc[m], Rm = s.Racc[m];
-    for (int t = 0; t < ns; ++t) {
-      ps += s.tps[IX_SM(t, m)];
-      pe += s.tpe[IX_SM(t, m)];
-      Rm += s.tR[IX_SM(t, m)];
-    }
-    s.psacc[m] = ps;
-    s.peacc[m] = pe;
-    s.Racc[m] = Rm;
+    s.psacc[m] = seq_sum(ns, s.psacc[m], [&](int t) { return s.tps[IX_SM(t, m)]; });
+    s.peacc[m] = seq_sum(ns, s.peacc[m], [&](int t) { return s.tpe[IX_SM(t, m)]; });
+    s.Racc[m] = seq_sum(ns, s.Racc[m], [&](int t) { return s.tR[IX_SM(t, m)]; });
   }
   if (!pc.update) {
     tm.sync();
@@ -779,11 +785,8 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
       s.u[i] = h_item(t, m, k, s.u[i]);
     }
     tm.sync();
-    for (int i = tid; i < M * K; i += nth) {
-      double Hsum = 0.0;
-      for (int t = 0; t < ns; ++t) Hsum += s.u[t * M * K + i];
-      s.Sacc[i] += Hsum;
-    }
+    for (int i = tid; i < M * K; i += nth)
+      s.Sacc[i] += seq_sum(ns, 0.0, [&](int t) { return s.u[t * M * K + i]; });
   } else {
     for (int i = tid; i < M * K; i += nth) {
       const int m = dv.K.div(i), k = i - m * K;
