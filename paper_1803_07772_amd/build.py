@@ -1,4 +1,5 @@
-"""Builds _liballoc.so for gfx950 with hipcc (in place, always recompiles)."""
+"""Builds _liballoc.so (and the tests' logarithm harness) for gfx950 with hipcc
+(in place, always recompiles)."""
 from __future__ import annotations
 
 import os
@@ -21,6 +22,19 @@ def build(verbose: bool = False) -> str:
     out = os.path.join(_HERE, "_liballoc.so")
     tmp = out + ".tmp"
     cmd = [HIPCC, *FLAGS, "-I", os.path.join(ROOT, "include"), "-o", tmp, *srcs]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, out)
+    return out
+
+
+def build_logs_probe(verbose: bool = False) -> str:
+    """tests/_liblogs_probe.so: the test harness of csrc/logs.h."""
+    src = os.path.join(ROOT, "tests", "logs_probe.hip")
+    out = os.path.join(ROOT, "tests", "_liblogs_probe.so")
+    tmp = out + ".tmp"
+    cmd = [HIPCC, *FLAGS, "-I", os.path.join(_HERE, "csrc"), "-o", tmp, src]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

@@ -27,6 +27,7 @@
 
 #include "alloc.h"
 #include "ctx.h"
+#include "logs.h"
 
 namespace cg = cooperative_groups;
 
@@ -337,7 +338,8 @@ __host__ __device__ inline size_t carve_waves(LDS char* base, int M, int K, int 
   return o;
 }
 
-__device__ inline double log2_1p(double x) { return log1p(x) / kLn2; }
+__device__ inline double log2_1p(double x) { return alloc_logs::log2_1p_d(x); }
+__device__ inline double log2_(double x) { return alloc_logs::log2_d(x); }
 
 // init + at(0) + at(1) + ... + at(n-1), added in that order; the loads of
 // each group of eight are issued together (at() is called on clamped
@@ -621,11 +623,11 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
     double al = s.sal[IX_ML(t, m, q)], be = s.sbe[IX_ML(t, m, q)];
     if (pc.refit && pq > 0.0) {
       al = gam / (1.0 + gam);
-      be = rr - al * log2(gam);
+      be = rr - al * log2_(gam);
       s.sal[IX_ML(t, m, q)] = al;
       s.sbe[IX_ML(t, m, q)] = be;
     }
-    const double rh = (pq > 0.0) ? be + al * log2(gam) : 0.0;
+    const double rh = (pq > 0.0) ? be + al * log2_(gam) : 0.0;
     const double cg = wmk * s.mu[k] * al / (kLn2 * (uu + pre));
     s.vpre[IX_ML1(t, m, a)] = pre;
     s.vcg[i] = cg;
