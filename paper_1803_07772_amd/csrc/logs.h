@@ -10,8 +10,9 @@
 //
 // with |s| < 0.1716, so the odd series through s^23 leaves a truncation
 // below 2^-60 of the result.  m - 1 is exact, s carries about one rounding
-// of (m + 1) and one of the division, and ln 2 is split into a 32-bit head
-// (e ln2_hi exact) and a tail: the result is within about 2 ulp.
+// of (m + 1) and one of the quotient (a reciprocal estimate refined by a
+// Newton step and a residual correction), and ln 2 is split into a 32-bit
+// head (e ln2_hi exact) and a tail: the result is within about 2 ulp.
 // log1p(x) adds to log(1 + x) the first-order correction for the rounding
 // of 1 + x, (x - ((1 + x) - 1)) / (1 + x), which keeps small arguments
 // accurate.
@@ -34,7 +35,14 @@ __device__ __forceinline__ double log_d(double x) {
   const bool low = m < kSqrtHalf;
   m = low ? 2.0 * m : m;
   e = low ? e - 1 : e;
-  const double s = (m - 1.0) / (m + 1.0);
+  // s = (m - 1)/(m + 1) with the divisor in [1.7, 2.5): reciprocal estimate,
+  // one Newton step, then the quotient's residual correction (no scaling
+  // is needed in this range)
+  const double a = m - 1.0, b = m + 1.0;
+  double rb = __builtin_amdgcn_rcp(b);
+  rb = fma(fma(-b, rb, 1.0), rb, rb);
+  double s = a * rb;
+  s = fma(fma(-b, s, a), rb, s);
   const double z = s * s;
   double p = 1.0 / 23.0;
   p = fma(p, z, 1.0 / 21.0);
@@ -58,7 +66,7 @@ __device__ __forceinline__ double log_d(double x) {
 // log(1 + x) for x >= 0; +inf and NaN are returned unchanged.
 __device__ __forceinline__ double log1p_d(double x) {
   const double u = 1.0 + x;
-  const double c = (x - (u - 1.0)) / u;
+  const double c = (x - (u - 1.0)) * __builtin_amdgcn_rcp(u);  // a correction of relative size <= 2^-53
   const double r = log_d(u) + c;
   return x < INFINITY ? r : x;
 }
