@@ -245,8 +245,34 @@ __host__ __device__ inline size_t carve_lds(LDS char* base, int M, int K, int L,
   };
   const size_t TM = (size_t)T * M, TML = TM * L, TK = (size_t)T * K;
   part = kTile;
-  s.g = (LDS float*)take(sizeof(float) * TM * K);
+  // Arrays whose live ranges within a tile do not overlap share storage: H
+  // and the intra-cell price of each user on its own RRH (steps 6-7) take
+  // the gains' place (steps 1-5); the inter-cell and C14 price terms (step
+  // 5) the per-user rates' (steps 1-4); the selection, the slots' previous
+  // positions and their power changes (steps 6-7) the prices c and c Gamma
+  // (steps 4-5).
+  {
+    LDS char* r = take(std::max(sizeof(float) * TM * K, sizeof(double) * 2 * TK));
+    s.g = (LDS float*)r;
+    s.Hc = (LDS double*)r;
+    s.pic = r ? s.Hc + TK : nullptr;
+  }
   s.u = (LDS double*)take(sizeof(double) * TM * K);
+  {
+    LDS char* r = take(std::max(sizeof(double) * 2 * TK, sizeof(double) * 2 * TM * M));
+    s.rk = (LDS double*)r;
+    s.rhk = r ? s.rk + TK : nullptr;
+    s.pij = (LDS double*)r;
+    s.contrib = r ? s.pij + TM * M : nullptr;
+  }
+  {
+    LDS char* r = take(sizeof(double) * 2 * TML);
+    s.vc = (LDS double*)r;
+    s.vcg = r ? s.vc + TML : nullptr;
+    s.chosen = (LDS int*)r;
+    s.nold = r ? s.chosen + TML : nullptr;
+    s.dmi = r ? (LDS double*)(s.nold + TML) : nullptr;
+  }
   part = kAccum;
   s.Sacc = (LDS double*)take(sizeof(double) * M * K);
   s.racc = (LDS double*)take(sizeof(double) * K);
@@ -270,10 +296,6 @@ __host__ __device__ inline size_t carve_lds(LDS char* base, int M, int K, int L,
   s.red = (LDS double*)take(sizeof(double) * kBlock);
   s.tmp = (LDS double*)take(sizeof(double) * (M + 2));
   part = kTile;
-  s.Hc = (LDS double*)take(sizeof(double) * TK);
-  s.pic = (LDS double*)take(sizeof(double) * TK);
-  s.rk = (LDS double*)take(sizeof(double) * TK);
-  s.rhk = (LDS double*)take(sizeof(double) * TK);
   s.su = (LDS int*)take(sizeof(int) * TML);
   s.sp = (LDS double*)take(sizeof(double) * TML);
   s.sal = (LDS double*)take(sizeof(double) * TML);
@@ -285,8 +307,6 @@ __host__ __device__ inline size_t carve_lds(LDS char* base, int M, int K, int L,
   s.vuser = (LDS int*)take(sizeof(int) * TML);
   s.vu = (LDS double*)take(sizeof(double) * TML);
   s.vpre = (LDS double*)take(sizeof(double) * TM * (L + 1));
-  s.vc = (LDS double*)take(sizeof(double) * TML);
-  s.vcg = (LDS double*)take(sizeof(double) * TML);
   s.vr = (LDS double*)take(sizeof(double) * TML);
   s.vT = (LDS double*)take(sizeof(double) * TM * (L + 1));
   s.Ptot = (LDS double*)take(sizeof(double) * TM);
@@ -298,11 +318,6 @@ __host__ __device__ inline size_t carve_lds(LDS char* base, int M, int K, int L,
   s.frozen = (LDS int*)take(sizeof(int) * TM);
   s.churn = (LDS int*)take(sizeof(int) * TM);
   s.np = (LDS int*)take(sizeof(int) * TM);
-  s.pij = (LDS double*)take(sizeof(double) * TM * M);
-  s.contrib = (LDS double*)take(sizeof(double) * TM * M);
-  s.chosen = (LDS int*)take(sizeof(int) * TML);
-  s.nold = (LDS int*)take(sizeof(int) * TML);
-  s.dmi = (LDS double*)take(sizeof(double) * TML);
   if (out) *out = s;
   return o;
 }
@@ -542,7 +557,6 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
         s.sp[i] = p;
         s.sal[i] = al;
         s.sbe[i] = be;
-        s.chosen[i] = -1;
       }
       if (i < nZ) {
         s.szs[i] = z;
@@ -682,10 +696,10 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
     s.peacc[m] = seq_sum(ns, s.peacc[m], [&](int t) { return s.tpe[IX_SM(t, m)]; });
     s.Racc[m] = seq_sum(ns, s.Racc[m], [&](int t) { return s.tR[IX_SM(t, m)]; });
   }
-  if (!pc.update) {
-    tm.sync();
-    return;
-  }
+  // (the barrier also ends the reads of the rates, whose storage step 5
+  // reuses)
+  tm.sync();
+  if (!pc.update) return;
 
   // 5. inter-cell price and C14 terms per (RRH m, other RRH j)
   for (int i = tid; i < ns * M * M; i += nth) {
@@ -747,7 +761,9 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
   }
   tm.sync();
 
-  // 6. per-triple Lagrangian maximum H
+  // 6. per-triple Lagrangian maximum H (the selection starts empty: its
+  //    storage held the prices read in step 5)
+  for (int i = tid; i < ns * M * L; i += nth) s.chosen[i] = -1;
   auto h_item = [&](int t, int m, int k, double u) -> double {
     const double wmu = (d.w ? gl(d.w)[(size_t)m * K + k] : 1.0) * s.mu[k];
     const int cnt = s.vcnt[IX_SM(t, m)];
