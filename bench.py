@@ -60,6 +60,15 @@ def parse():
     return ap.parse_args()
 
 
+def solver_source_sha() -> str:
+    """sha256 over the solver kernel's sources (alloc.hip and the headers it
+    includes), in a fixed order."""
+    h = hashlib.sha256()
+    for f in ("alloc.hip", "ctx.h", "logs.h"):
+        h.update(open(os.path.join(ROOT, "paper_1803_07772_amd", "csrc", f), "rb").read())
+    return h.hexdigest()
+
+
 def traffic_for(kernel: str, drops: int | None):
     """HBM bytes per launch from the committed counter summary, if it was
     taken on the current kernel source and the same batch size (else None)."""
@@ -68,9 +77,8 @@ def traffic_for(kernel: str, drops: int | None):
         return None
     try:
         t = json.load(open(path))
-        src = open(os.path.join(ROOT, "paper_1803_07772_amd", "csrc", "alloc.hip"), "rb").read()
         e = t[kernel]
-        if e["src_sha256"] != hashlib.sha256(src).hexdigest() or e["drops_per_step"] != drops:
+        if e["src_sha256"] != solver_source_sha() or e["drops_per_step"] != drops:
             return None
         return e["hbm_bytes_per_launch"]
     except (KeyError, ValueError, OSError):
@@ -87,8 +95,8 @@ def roofline(kernel, bytes_per_launch, ms_per_launch, drops=None):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported: drops shard across "
-              "GPUs with no exchange, and this build runs and reports one GPU only.", flush=True)
+        print(f"bench.py measures one GPU; --gpus {a.gpus} is not supported: drops would shard "
+              "across GPUs with no exchange, and only the one-GPU path is run and reported.", flush=True)
         sys.exit(2)
     import numpy as np
     import torch
