@@ -206,12 +206,9 @@ struct Lds {
   LDS double* tR;     // [T][M]
   LDS int* frozen;    // [T][M]
   LDS int* churn;     // [T][M]
-  LDS int* np;        // [T][M]
   LDS double* pij;    // [T][M][M]
   LDS double* contrib; // [T][M][M]
   LDS int* chosen;    // [T][M][L]
-  LDS int* nold;      // [T][M][L]
-  LDS double* dmi;    // [T][M][L]
   LDS double* xi;     // [M]
   LDS double* eta;    // [M]
   LDS double* pmask;  // [M]
@@ -248,9 +245,8 @@ __host__ __device__ inline size_t carve_lds(LDS char* base, int M, int K, int L,
   // Arrays whose live ranges within a tile do not overlap share storage: H
   // and the intra-cell price of each user on its own RRH (steps 6-7) take
   // the gains' place (steps 1-5); the inter-cell and C14 price terms (step
-  // 5) the per-user rates' (steps 1-4); the selection, the slots' previous
-  // positions and their power changes (steps 6-7) the prices c and c Gamma
-  // (steps 4-5).
+  // 5) the per-user rates' (steps 1-4); the selection (steps 6-7) the prices
+  // c and c Gamma (steps 4-5).
   {
     LDS char* r = take(std::max(sizeof(float) * TM * K, sizeof(double) * 2 * TK));
     s.g = (LDS float*)r;
@@ -270,8 +266,6 @@ __host__ __device__ inline size_t carve_lds(LDS char* base, int M, int K, int L,
     s.vc = (LDS double*)r;
     s.vcg = r ? s.vc + TML : nullptr;
     s.chosen = (LDS int*)r;
-    s.nold = r ? s.chosen + TML : nullptr;
-    s.dmi = r ? (LDS double*)(s.nold + TML) : nullptr;
   }
   part = kAccum;
   s.Sacc = (LDS double*)take(sizeof(double) * M * K);
@@ -317,7 +311,6 @@ __host__ __device__ inline size_t carve_lds(LDS char* base, int M, int K, int L,
   s.tR = (LDS double*)take(sizeof(double) * TM);
   s.frozen = (LDS int*)take(sizeof(int) * TM);
   s.churn = (LDS int*)take(sizeof(int) * TM);
-  s.np = (LDS int*)take(sizeof(int) * TM);
   if (out) *out = s;
   return o;
 }
@@ -803,6 +796,7 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
       s.u[i] = h_item(t, m, k, s.u[i]);
     }
     tm.sync();
+    // (the selection below runs in the same barrier interval)
     for (int i = tid; i < M * K; i += nth)
       s.Sacc[i] += seq_sum(ns, 0.0, [&](int t) { return s.u[t * M * K + i]; });
   } else {
@@ -812,8 +806,8 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
       for (int t = 0; t < ns; ++t) Hsum += h_item(t, m, k, s.u[IX_MK(t, m, k)]);
       s.Sacc[i] += Hsum;
     }
+    tm.sync();
   }
-  tm.sync();
 
   // 7. selection: the l best of RRH m's users with H > 0 (H desc, user asc),
   //    by each candidate's rank within its group
@@ -832,84 +826,105 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
     if (rank < L) s.chosen[IX_ML(t, m, rank)] = k;
   }
   tm.sync();
-  for (int i = tid; i < ns * M; i += nth) {
-    const int t = dv.M.div(i), m = i - t * M;
-    const int cnt = s.vcnt[i];
-    int np = 0;
-    if (s.frozen[i]) {  // churn cap reached: keep the incumbents still associated with m
-      for (int a = 0; a < cnt; ++a)
-        if (s.Al[s.vuser[IX_ML(t, m, a)]] == m) s.chosen[IX_ML(t, m, np++)] = s.vuser[IX_ML(t, m, a)];
-    } else {
-      while (np < L && s.chosen[IX_ML(t, m, np)] >= 0) ++np;
-      bool same = (np == cnt);
-      for (int a = 0; a < np && same; ++a) {
-        bool f = false;
-        for (int b = 0; b < cnt; ++b) f = f || (s.vuser[IX_ML(t, m, b)] == s.chosen[IX_ML(t, m, a)]);
-        same = f;
-      }
-      if (!same) s.churn[i]++;
-    }
-    s.np[i] = np;
-    gl(d.churn_sel)[(size_t)m * N + NOF(t)] = s.churn[i];
-  }
-  tm.sync();
-  // closed-form powers of the new selection
+  // The new selection of each (subcarrier, RRH), its closed-form powers and
+  // the C14 multipliers' move into the new slots, one item per slot: each
+  // item settles its (subcarrier, RRH)'s selection itself from the ranks
+  // above (at most l entries), so the three need no barrier between them.
   for (int i = tid; i < ns * M * L; i += nth) {
     const int t = dv.ML.div(i), r = i - t * M * L, m = dv.L.div(r), a = r - m * L;
-    const int cnt = s.vcnt[IX_SM(t, m)], np = s.np[IX_SM(t, m)];
+    const int sm = IX_SM(t, m);
+    const int cnt = s.vcnt[sm];
+    const bool fr = s.frozen[sm];
+    int vk[kMaxL], vq[kMaxL], ch[kMaxL];
+#pragma unroll
+    for (int b = 0; b < kMaxL; ++b) {
+      vk[b] = b < cnt ? s.vuser[IX_ML(t, m, b)] : -1;
+      vq[b] = b < cnt ? s.vslot[IX_ML(t, m, b)] : -1;
+      ch[b] = -1;
+    }
+    int np = 0;
+    if (fr) {  // churn cap reached: keep the incumbents still associated with m
+#pragma unroll
+      for (int b = 0; b < kMaxL; ++b)
+        if (b < cnt && s.Al[vk[b]] == m) ch[np++] = vk[b];
+    } else {  // the ranks' leading entries
+#pragma unroll
+      for (int b = 0; b < kMaxL; ++b)
+        if (b < L && np == b) {
+          const int c = s.chosen[IX_ML(t, m, b)];
+          if (c >= 0) ch[np++] = c;
+        }
+    }
+    if (a == 0) {  // the selection's churn counter
+      int churn = s.churn[sm];
+      if (!fr) {
+        bool same = np == cnt;
+#pragma unroll
+        for (int b = 0; b < kMaxL; ++b)
+          if (b < np) {
+            bool f = false;
+#pragma unroll
+            for (int b2 = 0; b2 < kMaxL; ++b2) f = f || (b2 < cnt && vk[b2] == ch[b]);
+            same = same && f;
+          }
+        if (!same) ++churn;
+      }
+      gl(d.churn_sel)[(size_t)m * N + NOF(t)] = churn;
+    }
+    int old[kMaxL];  // each new entry's slot before this sweep (-1 if new)
+#pragma unroll
+    for (int b = 0; b < kMaxL; ++b) {
+      old[b] = -1;
+#pragma unroll
+      for (int b2 = 0; b2 < kMaxL; ++b2)
+        if (b < np && b2 < cnt && vk[b2] == ch[b]) old[b] = vq[b2];
+    }
     double dm = 0.0;
-    int k = -1, old = -1;
+    int k = -1;
     double pn = 0.0, alph = 1.0, bet = 0.0;
     if (a < np) {
-      k = s.chosen[i];
+      k = ch[a];
       double p_old = 0.0;
-      for (int b = 0; b < cnt; ++b)
-        if (s.vuser[IX_ML(t, m, b)] == k) old = s.vslot[IX_ML(t, m, b)];
-      if (old >= 0) {
-        p_old = s.sp[IX_ML(t, m, old)];
-        alph = s.sal[IX_ML(t, m, old)];
-        bet = s.sbe[IX_ML(t, m, old)];
+      if (old[a] >= 0) {
+        p_old = s.sp[IX_ML(t, m, old[a])];
+        alph = s.sal[IX_ML(t, m, old[a])];
+        bet = s.sbe[IX_ML(t, m, old[a])];
       }
       const double wmu = (d.w ? gl(d.w)[(size_t)m * K + k] : 1.0) * s.mu[k];
-      const double ps = s.psic[IX_SM(t, m)];
+      const double ps = s.psic[sm];
       const double pplus = fmax(ps, 0.0), pminus = fmax(-ps, 0.0);
-      const double cp = (s.el[k] ? pc.E * s.eta[m] : 0.0) + s.xi[m] + s.pic[IX_SK(t, k)] +
-                        s.pinter[IX_SM(t, m)] + pplus;
+      const double cp = (s.el[k] ? pc.E * s.eta[m] : 0.0) + s.xi[m] + s.pic[IX_SK(t, k)] + s.pinter[sm] + pplus;
       const double num = wmu * alph / kLn2 + p_old * pminus;
       pn = (cp > 0.0) ? fmin(fmax(num / cp, 0.0), s.pmask[m]) : s.pmask[m];
       if (pn < kPowerFloorRel * s.pmask[m]) pn = 0.0;
       dm = fabs(pn - p_old) / s.pmask[m];
     }
     if (a < cnt) {  // an incumbent that leaves the selection
-      const int kt = s.vuser[IX_ML(t, m, a)];
+      const int kt = vk[a];
       bool kept = false;
-      for (int b = 0; b < np; ++b) kept = kept || (s.chosen[IX_ML(t, m, b)] == kt);
-      if (!kept) dm = fmax(dm, s.sp[IX_ML(t, m, s.vslot[IX_ML(t, m, a)])] / s.pmask[m]);
+#pragma unroll
+      for (int b = 0; b < kMaxL; ++b) kept = kept || (b < np && ch[b] == kt);
+      if (!kept) dm = fmax(dm, s.sp[IX_ML(t, m, vq[a])] / s.pmask[m]);
     }
-    s.nold[i] = old;
-    s.dmi[i] = dm;
+    // largest power change of RRH m: dm >= 0, so the bit patterns order as
+    // the values and an integer maximum is exact and order-free (NaN is
+    // skipped, as the maximum over the values would skip it)
+    if (dm == dm)
+      __hip_atomic_fetch_max((LDS unsigned long long*)(s.dmax + m), (unsigned long long)__double_as_longlong(dm),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     const size_t gi = ((size_t)m * N + NOF(t)) * L + a;
     gl(d.sel)[gi] = k;
     gl(d.p)[gi] = pn;
     gl(d.al)[gi] = alph;
     gl(d.be)[gi] = bet;
-  }
-  tm.sync();
-  // C14 multipliers follow their user pair into the new slots
-  for (int i = tid; i < ns * M * L * L; i += nth) {
-    const int t = dv.MLL.div(i), r = i - t * M * L * L, m = dv.LL.div(r), rl = dv.L.div(r), a = rl - dv.L.div(rl) * L,
-              b = r - rl * L;
-    const int np = s.np[IX_SM(t, m)];
-    double z = 0.0;
-    if (a < np && b < np && a != b && s.nold[IX_ML(t, m, a)] >= 0 && s.nold[IX_ML(t, m, b)] >= 0)
-      z = s.szn[IX_MLL(t, m, s.nold[IX_ML(t, m, a)], s.nold[IX_ML(t, m, b)])];
-    gl(d.zs)[(((size_t)m * N + NOF(t)) * L + a) * L + b] = z;
-  }
-  for (int m = tid; m < M; m += nth) {
-    double dm = s.dmax[m];
-    for (int t = 0; t < ns; ++t)
-      for (int a = 0; a < L; ++a) dm = fmax(dm, s.dmi[IX_ML(t, m, a)]);
-    s.dmax[m] = dm;
+    // the C14 multipliers of this new slot's pairs, from the pairs' old slots
+#pragma unroll
+    for (int b = 0; b < kMaxL; ++b)
+      if (b < L) {
+        double z = 0.0;
+        if (a < np && b < np && a != b && old[a] >= 0 && old[b] >= 0) z = s.szn[IX_MLL(t, m, old[a], old[b])];
+        gl(d.zs)[(gi * L) + b] = z;
+      }
   }
   tm.sync();
 #undef NOF
