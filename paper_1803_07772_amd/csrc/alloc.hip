@@ -678,21 +678,29 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
               (b < cnt) ? s.szs[IX_MLL(t, m, s.vslot[IX_ML(t, m, a)], s.vslot[IX_ML(t, m, b)])] : 0.0;
     }
   }
-  tm.sync();
-  // tile sums into the pass accumulators, in subcarrier order
+  // tile sums of the per-user rates into the pass accumulators, in
+  // subcarrier order (the rates are complete since the barrier above)
   for (int k = tid; k < K; k += nth) {
     s.racc[k] += seq_sum(ns, 0.0, [&](int t) { return s.rk[IX_SK(t, k)]; });
     s.rhacc[k] += seq_sum(ns, 0.0, [&](int t) { return s.rhk[IX_SK(t, k)]; });
   }
-  for (int m = tid; m < M; m += nth) {
-    s.psacc[m] = seq_sum(ns, s.psacc[m], [&](int t) { return s.tps[IX_SM(t, m)]; });
-    s.peacc[m] = seq_sum(ns, s.peacc[m], [&](int t) { return s.tpe[IX_SM(t, m)]; });
-    s.Racc[m] = seq_sum(ns, s.Racc[m], [&](int t) { return s.tR[IX_SM(t, m)]; });
-  }
   // (the barrier also ends the reads of the rates, whose storage step 5
   // reuses)
   tm.sync();
-  if (!pc.update) return;
+  // tile sums of the per-RRH powers and elastic rates of the loop above; on
+  // a sweep they run in step 5's barrier interval, which does not touch them
+  auto rrh_sums = [&]() {
+    for (int m = tid; m < M; m += nth) {
+      s.psacc[m] = seq_sum(ns, s.psacc[m], [&](int t) { return s.tps[IX_SM(t, m)]; });
+      s.peacc[m] = seq_sum(ns, s.peacc[m], [&](int t) { return s.tpe[IX_SM(t, m)]; });
+      s.Racc[m] = seq_sum(ns, s.Racc[m], [&](int t) { return s.tR[IX_SM(t, m)]; });
+    }
+  };
+  if (!pc.update) {
+    rrh_sums();
+    tm.sync();
+    return;
+  }
 
   // 5. inter-cell price and C14 terms per (RRH m, other RRH j)
   for (int i = tid; i < ns * M * M; i += nth) {
@@ -737,6 +745,7 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
     s.szn[IX_MLL(t, m, sa, sb)] = zn;
     s.szn[IX_MLL(t, m, sb, sa)] = zn;
   }
+  rrh_sums();
   tm.sync();
   for (int i = tid; i < ns * M; i += nth) {
     const int t = dv.M.div(i), m = i - t * M;
