@@ -69,27 +69,52 @@ def solver_source_sha() -> str:
     return h.hexdigest()
 
 
-def traffic_for(kernel: str, drops: int | None):
-    """HBM bytes per launch from the committed counter summary, if it was
-    taken on the current kernel source and the same batch size (else None)."""
+def counter_record(kernel: str, drops: int | None):
+    """The committed counter summary of a kernel (profiles/traffic.json), if
+    it was taken on the current kernel sources and the same batch size."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path) or drops is None:
         return None
     try:
-        t = json.load(open(path))
-        e = t[kernel]
+        e = json.load(open(path))[kernel]
         if e["src_sha256"] != solver_source_sha() or e["drops_per_step"] != drops:
             return None
-        return e["hbm_bytes_per_launch"]
+        return e
     except (KeyError, ValueError, OSError):
         return None
 
 
+def traffic_for(kernel: str, drops: int | None):
+    """HBM bytes per launch from the committed counter summary (else None)."""
+    e = counter_record(kernel, drops)
+    return e["hbm_bytes_per_launch"] if e else None
+
+
+# Vector issue capacity: every wave64 VALU instruction holds its SIMD for at
+# least 4 cycles; 256 CUs x 4 SIMDs at 2.4 GHz.
+VALU_WAVE_INSTS_PEAK = 256 * 4 * 2.4e9 / 4
+
+
+def valu_issue(kernel: str, drops: int | None, ms_per_launch: float):
+    """VALU wave instructions per launch (rocprof SQ_INSTS_VALU, committed
+    summary) against the vector issue capacity, or None."""
+    e = counter_record(kernel, drops)
+    if not e or "valu_wave_insts_per_launch" not in e:
+        return None
+    rate = e["valu_wave_insts_per_launch"] / (ms_per_launch * 1e-3)
+    return {"wave_instructions_per_launch": e["valu_wave_insts_per_launch"], "achieved_per_s": rate,
+            "peak_per_s": VALU_WAVE_INSTS_PEAK, "frac": rate / VALU_WAVE_INSTS_PEAK}
+
+
 def roofline(kernel, bytes_per_launch, ms_per_launch, drops=None):
     ach = bytes_per_launch / (ms_per_launch * 1e-3) / 1e9
-    return {"bound": "hbm", "achieved": round(ach, 4), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": ach / HBM_PEAK_GBS, "traffic": traffic_for(kernel, drops), "kernel": kernel,
-            "algorithmic_bytes_per_launch": bytes_per_launch, "ms_per_launch": ms_per_launch}
+    r = {"bound": "hbm", "achieved": round(ach, 4), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+         "frac": ach / HBM_PEAK_GBS, "traffic": traffic_for(kernel, drops), "kernel": kernel,
+         "algorithmic_bytes_per_launch": bytes_per_launch, "ms_per_launch": ms_per_launch}
+    v = valu_issue(kernel, drops, ms_per_launch)
+    if v:
+        r["valu_issue"] = v
+    return r
 
 
 def main():
