@@ -3,23 +3,27 @@
 // The sweep evaluates log2(1 + x) once per (RRH, subcarrier, user) triple
 // and once or twice more per selected user; the general-purpose library
 // versions carry extra-precision arithmetic that makes them several times
-// longer than needed here.  These follow the classical reduction
+// longer than needed here.  These are table-driven, after P. T. P. Tang,
+// "Table-driven implementation of the logarithm function in IEEE
+// floating-point arithmetic", ACM TOMS 16(4), 1990:
 //
-//   x = 2^e m,  sqrt(1/2) <= m < sqrt(2),   log x = e ln 2 + log m,
-//   log m = 2 atanh(s) = 2 (s + s^3/3 + s^5/5 + ...),  s = (m - 1)/(m + 1),
+//   x = 2^e m,  sqrt(1/2) <= m < sqrt(2),   c = j/128 the nearest multiple,
+//   log x = e ln 2 - log(1/c) + log(1 + r),  r = m (1/c) - 1,  |r| < 0.0056,
 //
-// with |s| < 0.1716, so the odd series through s^23 leaves a truncation
-// below 2^-60 of the result.  m - 1 is exact, s carries about one rounding
-// of (m + 1) and one of the quotient (a reciprocal estimate refined by a
-// Newton step and a residual correction), and ln 2 is split into a 32-bit
-// head (e ln2_hi exact) and a tail: the result is within about 2 ulp.
-// log1p(x) adds to log(1 + x) the first-order correction for the rounding
-// of 1 + x, (x - ((1 + x) - 1)) / (1 + x), which keeps small arguments
-// accurate.
+// where 1/c is the double in the table (logtab.h) and -log(1/c) of that very
+// double is tabulated as a head and a tail, so r = fma(m, 1/c, -1) carries a
+// single rounding; log(1 + r) is its series through r^8 (truncation below
+// 2^-70 of the result).  ln 2 is split into a 32-bit head (e ln2_hi exact)
+// and a tail, and the heads are added in one rounding: within about 1 ulp,
+// and exact where c = 1 and e = 0 (x near 1).  log1p(x) adds to log(1 + x)
+// the first-order correction for the rounding of 1 + x,
+// (x - ((1 + x) - 1)) / (1 + x), which keeps small arguments accurate.
 #pragma once
 
 #include <hip/hip_runtime.h>
 #include <math.h>
+
+#include "logtab.h"
 
 namespace alloc_logs {
 
@@ -33,34 +37,26 @@ __device__ __forceinline__ double log_d(double x) {
   int e;
   double m = frexp(x, &e);  // [1/2, 1)
   const bool low = m < kSqrtHalf;
-  m = low ? 2.0 * m : m;
+  m = low ? 2.0 * m : m;  // [sqrt(1/2), sqrt(2))
   e = low ? e - 1 : e;
-  // s = (m - 1)/(m + 1) with the divisor in [1.7, 2.5): reciprocal estimate,
-  // one Newton step, then the quotient's residual correction (no scaling
-  // is needed in this range)
-  const double a = m - 1.0, b = m + 1.0;
-  double rb = __builtin_amdgcn_rcp(b);
-  rb = fma(fma(-b, rb, 1.0), rb, rb);
-  double s = a * rb;
-  s = fma(fma(-b, s, a), rb, s);
-  const double z = s * s;
-  double p = 1.0 / 23.0;
-  p = fma(p, z, 1.0 / 21.0);
-  p = fma(p, z, 1.0 / 19.0);
-  p = fma(p, z, 1.0 / 17.0);
-  p = fma(p, z, 1.0 / 15.0);
-  p = fma(p, z, 1.0 / 13.0);
-  p = fma(p, z, 1.0 / 11.0);
-  p = fma(p, z, 1.0 / 9.0);
-  p = fma(p, z, 1.0 / 7.0);
-  p = fma(p, z, 1.0 / 5.0);
-  p = fma(p, z, 1.0 / 3.0);
-  const double s2 = 2.0 * s;
-  const double lm = fma(s2 * z, p, s2);  // 2s + 2s z p(z)
+  // nearest c = j/128 (91 <= j <= 181; the clamp only matters for 0, inf, NaN)
+  const int j = min(max((int)(m * 128.0 + 0.5), kLogTabJ0), kLogTabJ0 + 90);
+  const double* tb = kLogTab[j - kLogTabJ0];
+  const double r = fma(m, tb[0], -1.0);
+  double p = -1.0 / 8.0;
+  p = fma(p, r, 1.0 / 7.0);
+  p = fma(p, r, -1.0 / 6.0);
+  p = fma(p, r, 1.0 / 5.0);
+  p = fma(p, r, -1.0 / 4.0);
+  p = fma(p, r, 1.0 / 3.0);
+  p = fma(p, r, -0.5);
+  const double lr = fma(r * r, p, r);  // log(1 + r)
   const double fe = (double)e;
-  const double r = fma(fe, kLn2Hi, fma(fe, kLn2Lo, lm));
+  const double hi = fma(fe, kLn2Hi, tb[1]);
+  const double lo = fma(fe, kLn2Lo, tb[2]) + lr;
+  const double res = hi + lo;
   if (x == 0.0) return -INFINITY;
-  return x < INFINITY ? r : x;
+  return x < INFINITY ? res : x;
 }
 
 // log(1 + x) for x >= 0; +inf and NaN are returned unchanged.

@@ -1,6 +1,6 @@
 """The solver's double-precision logarithms (csrc/logs.h) against the host C
 library over arguments spread across the double range: log and log1p within
-3 ulp of it, log2 and log2(1 + x) within 5 ulp of references that are
+2 ulp of it, log2 and log2(1 + x) within 3 ulp of references that are
 themselves rounded twice (log(x)/log(2)); exact at the special points.  The
 harness (tests/logs_probe.hip, built with the package) evaluates them on the
 GPU."""
@@ -44,7 +44,7 @@ def _ulps(y, ref):
 def test_log_and_log2_accuracy():
     print("[gpu case] logs: log, log2 on 820k arguments", flush=True)
     x = _args()
-    for which, ref_f, bound in ((0, np.log, 3.0), (2, np.log2, 5.0)):
+    for which, ref_f, bound in ((0, np.log, 2.0), (2, np.log2, 3.0)):
         y, ref = _eval(x, which), ref_f(x)
         ok = ref != 0.0
         err = _ulps(y[ok], ref[ok])
@@ -56,7 +56,7 @@ def test_log_and_log2_accuracy():
 def test_log1p_and_log2_1p_accuracy():
     print("[gpu case] logs: log1p, log2(1+x) on 820k arguments", flush=True)
     x = np.concatenate([_args(), 10.0 ** np.random.default_rng(8).uniform(-320, -16, 20_000)])
-    for which, ref_f, bound in ((1, np.log1p, 3.0), (3, lambda v: np.log1p(v) / np.log(2.0), 5.0)):
+    for which, ref_f, bound in ((1, np.log1p, 2.0), (3, lambda v: np.log1p(v) / np.log(2.0), 3.0)):
         y, ref = _eval(x, which), ref_f(x)
         ok = ref != 0.0
         err = _ulps(y[ok], ref[ok])
