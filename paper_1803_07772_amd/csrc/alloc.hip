@@ -449,6 +449,9 @@ __device__ void begin_pass(const Drop& d, Lds& s) {
   __syncthreads();
 }
 
+__device__ __forceinline__ int mul24(int a, int b) { return (int)__umul24(a, b); }
+__device__ __forceinline__ int mad24(int a, int b, int c) { return mul24(a, b) + c; }
+
 struct PassConst {
   double E, delta_v;
   int refit, reset, update, write_out;
@@ -473,13 +476,15 @@ struct WaveTeam {
 
 // One subcarrier of a sweep (update) or of an evaluation pass (no update).
 // Indexing of the per-tile LDS arrays (s = subcarrier within the tile).
-#define IX_MK(s, m, k) ((((s) * M) + (m)) * K + (k))
-#define IX_ML(s, m, q) ((((s) * M) + (m)) * L + (q))
-#define IX_ML1(s, m, t) ((((s) * M) + (m)) * (L + 1) + (t))
-#define IX_MLL(s, m, a, b) (((((s) * M) + (m)) * L + (a)) * L + (b))
-#define IX_SM(s, m) ((s) * M + (m))
-#define IX_SMM(s, m, j) ((((s) * M) + (m)) * M + (j))
-#define IX_SK(s, k) ((s) * K + (k))
+// (LDS indices stay below 2^24: 24-bit multiply-adds, full rate, instead of
+// 32-bit multiplies)
+#define IX_MK(s, m, k) mad24(mad24((s), M, (m)), K, (k))
+#define IX_ML(s, m, q) mad24(mad24((s), M, (m)), L, (q))
+#define IX_ML1(s, m, t) mad24(mad24((s), M, (m)), L + 1, (t))
+#define IX_MLL(s, m, a, b) mad24(mad24(mad24((s), M, (m)), L, (a)), L, (b))
+#define IX_SM(s, m) mad24((s), M, (m))
+#define IX_SMM(s, m, j) mad24(mad24((s), M, (m)), M, (j))
+#define IX_SK(s, k) mad24((s), K, (k))
 
 // One tile of ns subcarriers n = n0, n0 + nstep, ... of a sweep (update) or
 // of an evaluation pass (no update).  Everything here is defined per
@@ -508,7 +513,7 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
       for (int j = 0; j < kG; ++j) {
         const int i = tid + (r0 * kG + j) * nth;
         if (i < nG) {
-          const int t = dv.MK.div(i), r = i - t * M * K, m = dv.K.div(r), k = r - m * K;
+          const int t = dv.MK.div(i), r = i - mul24(t, M * K), m = dv.K.div(r), k = r - mul24(m, K);
           gv[j] = gl(d.G)[((size_t)m * N + NOF(t)) * K + k];
         }
       }
@@ -517,7 +522,7 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
       double p = 0.0, al = 1.0, be = 0.0, z = 0.0, pq[kMaxL];
       int sq[kMaxL], ch = 0;
       if (i < nS) {
-        const int t = dv.ML.div(i), r = i - t * M * L, m = dv.L.div(r), q = r - m * L;
+        const int t = dv.ML.div(i), r = i - mul24(t, M * L), m = dv.L.div(r), q = r - mul24(m, L);
         const size_t gi = ((size_t)m * N + NOF(t)) * L + q;
         sel = gl(d.sel)[gi];
         p = gl(d.p)[gi];
@@ -527,11 +532,11 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
         }
       }
       if (i < nZ) {
-        const int t = dv.MLL.div(i), r = i - t * M * L * L, m = dv.LL.div(r), ab = r - m * L * L;
+        const int t = dv.MLL.div(i), r = i - mul24(t, M * L * L), m = dv.LL.div(r), ab = r - mul24(m, L * L);
         z = gl(d.zs)[((size_t)m * N + NOF(t)) * L * L + ab];
       }
       if (i < nP) {
-        const int t = dv.M.div(i), m = i - t * M;
+        const int t = dv.M.div(i), m = i - mul24(t, M);
         const size_t gi = ((size_t)m * N + NOF(t)) * L;
         if (!pc.reset) ch = gl(d.churn_sel)[(size_t)m * N + NOF(t)];
 #pragma unroll
@@ -574,7 +579,7 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
   // 2. inter-cell interference as exclusive prefix + suffix over RRHs (no
   //    subtraction), stored as u = (sigma + ICI)/Gamma
   for (int i = tid; i < ns * K; i += nth) {
-    const int t = dv.K.div(i), k = i - t * K;
+    const int t = dv.K.div(i), k = i - mul24(t, K);
     double suf = 0.0;
     for (int m = M - 1; m >= 0; --m) {
       s.u[IX_MK(t, m, k)] = suf;
@@ -593,7 +598,7 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
   // 3. SIC decoding order of each RRH's users: normalised gain descending
   //    (u ascending), ties to the lower user; position by rank
   for (int i = tid; i < ns * M * L; i += nth) {
-    const int t = dv.ML.div(i), r = i - t * M * L, m = dv.L.div(r), q = r - m * L;
+    const int t = dv.ML.div(i), r = i - mul24(t, M * L), m = dv.L.div(r), q = r - mul24(m, L);
     const int k = s.su[i];
     if (k < 0) continue;
     const double uq = s.u[IX_MK(t, m, k)];
@@ -617,7 +622,7 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
 
   // 4. per selected user: SINR, rate, SCALE refit and surrogate, price c
   for (int i = tid; i < ns * M * L; i += nth) {
-    const int t = dv.ML.div(i), r = i - t * M * L, m = dv.L.div(r), a = r - m * L;
+    const int t = dv.ML.div(i), r = i - mul24(t, M * L), m = dv.L.div(r), a = r - mul24(m, L);
     if (a >= s.vcnt[IX_SM(t, m)]) continue;
     double pre = 0.0;
     for (int a2 = 0; a2 < a; ++a2) pre += s.sp[IX_ML(t, m, s.vslot[IX_ML(t, m, a2)])];
@@ -650,7 +655,7 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
   }
   tm.sync();
   for (int i = tid; i < ns * M; i += nth) {
-    const int t = dv.M.div(i), m = i - t * M;
+    const int t = dv.M.div(i), m = i - mul24(t, M);
     const int cnt = s.vcnt[i];
     double ps = 0.0, pe = 0.0, Rm = 0.0;
     for (int a = 0; a < cnt; ++a) {
@@ -704,7 +709,7 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
 
   // 5. inter-cell price and C14 terms per (RRH m, other RRH j)
   for (int i = tid; i < ns * M * M; i += nth) {
-    const int t = dv.MM.div(i), r = i - t * M * M, m = dv.M.div(r), j = r - m * M;
+    const int t = dv.MM.div(i), r = i - mul24(t, M * M), m = dv.M.div(r), j = r - mul24(m, M);
     double inter = 0.0, sic = 0.0;
     if (j != m) {
       const int cj = s.vcnt[IX_SM(t, j)];
@@ -731,8 +736,8 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
   }
   // subgradient step of each pair's C14 multiplier on the margin Omega/nu
   for (int i = tid; i < ns * M * L * L; i += nth) {
-    const int t = dv.MLL.div(i), r = i - t * M * L * L, m = dv.LL.div(r), rl = dv.L.div(r), a = rl - dv.L.div(rl) * L,
-              b = r - rl * L;
+    const int t = dv.MLL.div(i), r = i - mul24(t, M * L * L), m = dv.LL.div(r), rl = dv.L.div(r), a = rl - mul24(dv.L.div(rl), L),
+              b = r - mul24(rl, L);
     if (!(a < b && b < s.vcnt[IX_SM(t, m)])) continue;
     const int ka = s.vuser[IX_ML(t, m, a)], kb = s.vuser[IX_ML(t, m, b)];
     const double ga = s.g[IX_MK(t, m, ka)], gb = s.g[IX_MK(t, m, kb)];
@@ -748,7 +753,7 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
   rrh_sums();
   tm.sync();
   for (int i = tid; i < ns * M; i += nth) {
-    const int t = dv.M.div(i), m = i - t * M;
+    const int t = dv.M.div(i), m = i - mul24(t, M);
     double inter = 0.0, sic = 0.0;
     for (int j = 0; j < M; ++j) {
       inter += s.pij[IX_SMM(t, m, j)];
@@ -801,7 +806,7 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
   if (kItemH) {
     // H replaces the triple's own u (nothing later in the pass reads u)
     for (int i = tid; i < ns * M * K; i += nth) {
-      const int t = dv.MK.div(i), r = i - t * M * K, m = dv.K.div(r), k = r - m * K;
+      const int t = dv.MK.div(i), r = i - mul24(t, M * K), m = dv.K.div(r), k = r - mul24(m, K);
       s.u[i] = h_item(t, m, k, s.u[i]);
     }
     tm.sync();
@@ -810,7 +815,7 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
       s.Sacc[i] += seq_sum(ns, 0.0, [&](int t) { return s.u[t * M * K + i]; });
   } else {
     for (int i = tid; i < M * K; i += nth) {
-      const int m = dv.K.div(i), k = i - m * K;
+      const int m = dv.K.div(i), k = i - mul24(m, K);
       double Hsum = 0.0;
       for (int t = 0; t < ns; ++t) Hsum += h_item(t, m, k, s.u[IX_MK(t, m, k)]);
       s.Sacc[i] += Hsum;
@@ -821,7 +826,7 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
   // 7. selection: the l best of RRH m's users with H > 0 (H desc, user asc),
   //    by each candidate's rank within its group
   for (int i = tid; i < ns * K; i += nth) {
-    const int t = dv.K.div(i), k = i - t * K;
+    const int t = dv.K.div(i), k = i - mul24(t, K);
     const int m = s.Al[k];
     if (m < 0 || s.frozen[IX_SM(t, m)]) continue;
     const double h = s.Hc[i];
@@ -840,7 +845,7 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
   // item settles its (subcarrier, RRH)'s selection itself from the ranks
   // above (at most l entries), so the three need no barrier between them.
   for (int i = tid; i < ns * M * L; i += nth) {
-    const int t = dv.ML.div(i), r = i - t * M * L, m = dv.L.div(r), a = r - m * L;
+    const int t = dv.ML.div(i), r = i - mul24(t, M * L), m = dv.L.div(r), a = r - mul24(m, L);
     const int sm = IX_SM(t, m);
     const int cnt = s.vcnt[sm];
     const bool fr = s.frozen[sm];
