@@ -87,6 +87,7 @@ __host__ __device__ inline Div make_div(uint32_t d) {
 // Divisors of the per-subcarrier item loops of one drop.
 struct Divs {
   Div K, M, L, MK, ML, MLL, LL, MM;
+  Div K4, MK4;  // K/4 and M*K/4 (when K is a multiple of 4)
 };
 
 inline Divs make_divs(int M, int K, int L) {
@@ -99,6 +100,8 @@ inline Divs make_divs(int M, int K, int L) {
   v.MLL = make_div(M * L * L);
   v.LL = make_div(L * L);
   v.MM = make_div(M * M);
+  v.K4 = make_div(K % 4 == 0 ? K / 4 : 1);
+  v.MK4 = make_div(K % 4 == 0 ? M * K / 4 : 1);
   return v;
 }
 
@@ -141,6 +144,7 @@ struct Drop {
   double* out_zs;          // [M][N][NP]
   Ctrl* ctrl;              // final control state for the host
   int tile;                // subcarriers per LDS tile (batched solver)
+  int gvec4;               // K % 4 == 0 and G 16-byte aligned: gains load four at a time
   int wave;                // batched solver, one-workgroup drops: subcarriers per wave tile
                            // (each wave runs its own subcarriers), 0 = workgroup tiles
   const double* p0;        // batched solver, warm start (device, may be null):
@@ -156,6 +160,7 @@ struct Drop {
 // Device memory reached through the drop descriptor: global (not generic)
 // accesses, so loads complete in order and are waited for one by one.
 #define GLB __attribute__((address_space(1)))
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 template <class T>
 __device__ __forceinline__ GLB T* gl(T* p) {
   return (GLB T*)p;
@@ -248,6 +253,7 @@ __host__ __device__ inline size_t carve_lds(LDS char* base, int M, int K, int L,
   // 5) the per-user rates' (steps 1-4); the selection (steps 6-7) the prices
   // c and c Gamma (steps 4-5).
   {
+    if (parts & kTile) o = (o + 15) & ~size_t(15);  // the gains take 16-byte stores
     LDS char* r = take(std::max(sizeof(float) * TM * K, sizeof(double) * 2 * TK));
     s.g = (LDS float*)r;
     s.Hc = (LDS double*)r;
@@ -325,6 +331,7 @@ __host__ __device__ inline size_t carve_waves(LDS char* base, int M, int K, int 
   size_t o = carve_lds(base, M, K, L, 0, &c, kShared | kAccum);
   for (int w = 0; w < W; ++w) {
     Lds v;
+    o = (o + 15) & ~size_t(15);
     o += carve_lds(base ? base + o : nullptr, M, K, L, T, &v, kTile | kAccum);
     v.mu = c.mu;
     v.Al = c.Al;
@@ -504,17 +511,36 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
   //    global load is issued before the first LDS store (the round waits for
   //    memory once); the totals come from unconditional loads.
   {
-    constexpr int kG = 6;  // gains per thread per round
-    const int nG = ns * M * K, nS = ns * M * L, nZ = nS * L, nP = ns * M;
-    const int rounds = max((nG + kG * nth - 1) / (kG * nth), (max(nZ, nP) + nth - 1) / nth);
+    constexpr int kG = 6;  // gains per thread per round (four-wide: kQ)
+    constexpr int kQ = 2;
+    const bool vec4 = d.gvec4;
+    const int K4 = K >> 2;
+    const int nG = ns * M * K, nG4 = ns * M * K4, nS = ns * M * L, nZ = nS * L, nP = ns * M;
+    const int rounds = max(vec4 ? (nG4 + kQ * nth - 1) / (kQ * nth) : (nG + kG * nth - 1) / (kG * nth),
+                           (max(nZ, nP) + nth - 1) / nth);
     for (int r0 = 0; r0 < rounds; ++r0) {
       float gv[kG];
+      f32x4 gq[kQ];
+      int gqi[kQ];
+      if (vec4) {
 #pragma unroll
-      for (int j = 0; j < kG; ++j) {
-        const int i = tid + (r0 * kG + j) * nth;
-        if (i < nG) {
-          const int t = dv.MK.div(i), r = i - mul24(t, M * K), m = dv.K.div(r), k = r - mul24(m, K);
-          gv[j] = gl(d.G)[((size_t)m * N + NOF(t)) * K + k];
+        for (int j = 0; j < kQ; ++j) {
+          const int i = tid + (r0 * kQ + j) * nth;
+          gqi[j] = -1;
+          if (i < nG4) {
+            const int t = dv.MK4.div(i), r = i - mul24(t, M * K4), m = dv.K4.div(r), c = r - mul24(m, K4);
+            gq[j] = *(GLB const f32x4*)(gl(d.G) + ((size_t)m * N + NOF(t)) * K + 4 * c);
+            gqi[j] = IX_MK(t, m, 4 * c);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < kG; ++j) {
+          const int i = tid + (r0 * kG + j) * nth;
+          if (i < nG) {
+            const int t = dv.MK.div(i), r = i - mul24(t, M * K), m = dv.K.div(r), k = r - mul24(m, K);
+            gv[j] = gl(d.G)[((size_t)m * N + NOF(t)) * K + k];
+          }
         }
       }
       const int i = tid + r0 * nth;
@@ -545,10 +571,16 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
           pq[q] = q < L ? gl(d.p)[gi + q] : 0.0;
         }
       }
+      if (vec4) {
 #pragma unroll
-      for (int j = 0; j < kG; ++j) {
-        const int ij = tid + (r0 * kG + j) * nth;
-        if (ij < nG) s.g[ij] = gv[j];
+        for (int j = 0; j < kQ; ++j)
+          if (gqi[j] >= 0) *(LDS f32x4*)(s.g + gqi[j]) = gq[j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < kG; ++j) {
+          const int ij = tid + (r0 * kG + j) * nth;
+          if (ij < nG) s.g[ij] = gv[j];
+        }
       }
       if (i < nS) {
         s.su[i] = sel;
@@ -1886,6 +1918,7 @@ int solve_one(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, 
   d.M = M; d.N = N; d.K = K; d.L = L; d.NP = NP;
   d.dv = make_divs(M, K, L);
   d.G = gain_dev ? pb->gain : (const float*)(ws + oG);
+  d.gvec4 = K % 4 == 0 && ((uintptr_t)d.G & 15) == 0;
   d.psi = (const double*)(ws + oPsi);
   d.elastic = (const uint8_t*)(ws + oEl);
   d.pmax = (const double*)(ws + oPmax);
@@ -2225,6 +2258,7 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
     d.M = M; d.N = N; d.K = K; d.L = L; d.NP = L * (L - 1) / 2;
     d.dv = make_divs(M, K, L);
     d.G = gain_dev ? pb.gain : (const float*)(ws + o.G);
+    d.gvec4 = K % 4 == 0 && ((uintptr_t)d.G & 15) == 0;
     d.psi = (const double*)(ws + o.psi);
     d.elastic = (const uint8_t*)(ws + o.el);
     d.pmax = (const double*)(ws + o.pmax);
