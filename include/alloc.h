@@ -105,8 +105,10 @@ typedef struct {
   uint32_t flags;                /* ALLOC_GAIN_ON_DEVICE | ALLOC_OUT_ON_DEVICE */
   int32_t max_groups;            /* 0: cap on the workgroups of the solve grid
                                     (0 = one per compute unit, <= N) */
-  int32_t tile;                  /* 0: subcarriers a workgroup processes together
-                                    (0 = as many as its LDS holds) */
+  int32_t tile;                  /* 0: cap on the subcarriers a workgroup processes
+                                    together (0 = as many as its LDS holds); its
+                                    subcarriers are split into the fewest tiles
+                                    within the cap, of equal size */
   int32_t lds_kb;                /* 0: batched solver only: requested LDS per workgroup
                                     in KiB (0 = a whole compute unit's); smaller shares
                                     let several workgroups share a compute unit.  Raised

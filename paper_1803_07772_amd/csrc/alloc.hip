@@ -1705,6 +1705,19 @@ int validate(const alloc_problem* pb, const alloc_params* prm) {
   return ALLOC_OK;
 }
 
+// Subcarriers per tile for a workgroup that owns nb of them: the fewest
+// tiles that fit (at most cap subcarriers each when cap > 0), of equal size
+// but the last.  A phase takes as long as its fullest tile's items need
+// rounds of the workgroup's threads: four tiles of 16 subcarriers run faster
+// than tiles of 18, 18, 18 and 10.
+template <class Fits>
+int balanced_tile(int nb, int cap, Fits fits) {
+  int T = cap > 0 ? std::min(cap, nb) : nb;
+  while (T > 1 && !fits(T)) --T;
+  const int tiles = (nb + T - 1) / T;
+  return (nb + tiles - 1) / tiles;
+}
+
 struct Layout {
   size_t off[48];
   int n = 0;
@@ -1820,8 +1833,7 @@ int solve_one(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, 
   int G = std::min(N, ctx->cus);
   if (prm->max_groups > 0) G = std::min(G, prm->max_groups);
   const int nb = (N + G - 1) / G;
-  int T = prm->tile > 0 ? std::min(prm->tile, nb) : nb;
-  while (T > 1 && carve_lds(nullptr, M, K, L, T, nullptr) > budget) --T;
+  const int T = balanced_tile(nb, prm->tile, [&](int t) { return carve_lds(nullptr, M, K, L, t, nullptr) <= budget; });
   const size_t lds = carve_lds(nullptr, M, K, L, T, nullptr);
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)solve_kernel, kBlock, lds) !=
@@ -2296,8 +2308,7 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
       d.bar = (unsigned*)(ws + o.bar);
     }
     const int nb = (N + g - 1) / g;  // subcarriers of one rank
-    int T = prm->tile > 0 ? std::min(prm->tile, nb) : nb;
-    while (T > 1 && carve_lds(nullptr, M, K, L, T, nullptr) > budget) --T;
+    const int T = balanced_tile(nb, prm->tile, [&](int t) { return carve_lds(nullptr, M, K, L, t, nullptr) <= budget; });
     d.tile = T;
     d.wave = (g == 1 && prm->wave > 0 &&
               carve_waves(nullptr, M, K, L, prm->wave, nwaves, nullptr, nullptr) <= budget)
