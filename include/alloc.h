@@ -115,7 +115,7 @@ typedef struct {
                                     to what the batch's largest drop needs for a
                                     one-subcarrier tile. */
   int32_t block;                 /* 0: batched solver only: threads per workgroup,
-                                    256 or 512 (0 = 512) */
+                                    256, 512 or 1024 (0 = 512) */
   int32_t wave;                  /* 0: batched solver only, drops solved by one
                                     workgroup: 1..16 = each 64-lane wave runs its own
                                     subcarriers, this many at a time, with no

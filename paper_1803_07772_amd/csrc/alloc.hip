@@ -38,7 +38,8 @@ constexpr int kMaxL = 4;
 constexpr int kMaxM = 32;
 constexpr int kMaxK = 1024;
 constexpr int kMaxMK = 4608;
-constexpr int kBlock = 512;
+constexpr int kBlock = 1024;     // largest workgroup of the batched solver
+constexpr int kGridBlock = 512;  // workgroup of the grid solver
 // Closed-form powers below this fraction of the mask become exactly zero, so
 // decaying powers never reach the subnormal range.
 constexpr double kPowerFloorRel = 1e-20;
@@ -182,7 +183,7 @@ struct Lds {
   LDS int* grp;       // [K] users grouped by RRH
   LDS int* grpk;      // [K] rank of a user within its RRH group
   LDS int* grp_off;   // [M+1]
-  LDS int* wcnt;      // [kBlock/64][M] per-wave group counts
+  LDS int* wcnt;      // [waves][M] per-wave group counts
   LDS int* gcur;      // [M]
   LDS double* Hc;     // [T][K] H of user k on its own RRH
   LDS double* pic;    // [T][K] intra-cell price of user k on its own RRH
@@ -221,7 +222,7 @@ struct Lds {
   LDS double* peacc;  // [M]
   LDS double* Racc;   // [M]
   LDS double* dmax;   // [M]
-  LDS double* red;    // [kBlock] scratch for reductions
+  LDS double* red;    // [threads] scratch for reductions
   LDS double* tmp;    // [M+2] reduction results
 };
 
@@ -234,7 +235,7 @@ enum LdsPart : int { kShared = 1, kAccum = 2, kTile = 4, kAllParts = 7 };
 // Lays the arrays of `parts` out from `base`; returns the bytes used (the
 // other pointers are left null).  With base == nullptr it only measures
 // (host side).
-__host__ __device__ inline size_t carve_lds(LDS char* base, int M, int K, int L, int T, Lds* out,
+__host__ __device__ inline size_t carve_lds(LDS char* base, int M, int K, int L, int T, int nth, Lds* out,
                                             int parts = kAllParts) {
   Lds s;
   size_t o = 0;
@@ -288,12 +289,12 @@ __host__ __device__ inline size_t carve_lds(LDS char* base, int M, int K, int L,
   s.grp = (LDS int*)take(sizeof(int) * K);
   s.grpk = (LDS int*)take(sizeof(int) * K);
   s.grp_off = (LDS int*)take(sizeof(int) * (M + 1));
-  s.wcnt = (LDS int*)take(sizeof(int) * (kBlock / 64) * M);
+  s.wcnt = (LDS int*)take(sizeof(int) * (nth / 64) * M);
   s.gcur = (LDS int*)take(sizeof(int) * M);
   s.xi = (LDS double*)take(sizeof(double) * M);
   s.eta = (LDS double*)take(sizeof(double) * M);
   s.pmask = (LDS double*)take(sizeof(double) * M);
-  s.red = (LDS double*)take(sizeof(double) * kBlock);
+  s.red = (LDS double*)take(sizeof(double) * nth);
   s.tmp = (LDS double*)take(sizeof(double) * (M + 2));
   part = kTile;
   s.su = (LDS int*)take(sizeof(int) * TML);
@@ -328,11 +329,11 @@ __host__ __device__ inline size_t carve_lds(LDS char* base, int M, int K, int L,
 __host__ __device__ inline size_t carve_waves(LDS char* base, int M, int K, int L, int T, int W, Lds* common,
                                               Lds* waves) {
   Lds c;
-  size_t o = carve_lds(base, M, K, L, 0, &c, kShared | kAccum);
+  size_t o = carve_lds(base, M, K, L, 0, 64 * W, &c, kShared | kAccum);
   for (int w = 0; w < W; ++w) {
     Lds v;
     o = (o + 15) & ~size_t(15);
-    o += carve_lds(base ? base + o : nullptr, M, K, L, T, &v, kTile | kAccum);
+    o += carve_lds(base ? base + o : nullptr, M, K, L, T, 64 * W, &v, kTile | kAccum);
     v.mu = c.mu;
     v.Al = c.Al;
     v.el = c.el;
@@ -1147,10 +1148,10 @@ __device__ void control(const Drop& d, const Sched& sc, Ctrl& c) {
   advance(sc, c, R, P, dm, changes);
 }
 
-__global__ void __launch_bounds__(kBlock) solve_kernel(Drop d, Sched sc) {
+__global__ void __launch_bounds__(kGridBlock) solve_kernel(Drop d, Sched sc) {
   extern __shared__ __align__(16) char smem[];
   __shared__ Lds s_tab;
-  if (threadIdx.x == 0) carve_lds((LDS char*)smem, d.M, d.K, d.L, sc.tile, &s_tab);
+  if (threadIdx.x == 0) carve_lds((LDS char*)smem, d.M, d.K, d.L, sc.tile, blockDim.x, &s_tab);
   __syncthreads();
   Lds& s = s_tab;
   cg::grid_group grid = cg::this_grid();
@@ -1529,7 +1530,7 @@ batch_kernel(const Drop* __restrict__ drops, const int2* __restrict__ slots, int
       if (d.wave > 0)
         carve_waves((LDS char*)smem, d.M, d.K, d.L, d.wave, blockDim.x >> 6, &s_tab, s_wtab);
       else
-        carve_lds((LDS char*)smem, d.M, d.K, d.L, sd.tile, &s_tab);
+        carve_lds((LDS char*)smem, d.M, d.K, d.L, sd.tile, blockDim.x, &s_tab);
     }
     __syncthreads();
     if (d.group <= 1)
@@ -1683,7 +1684,7 @@ int validate(const alloc_problem* pb, const alloc_params* prm) {
   if (!std::isfinite(pb->noise_w)) return ALLOC_EINVAL;
   if (pb->M > kMaxM || pb->l > kMaxL || pb->K > kMaxK || pb->M * pb->K > kMaxMK) return ALLOC_ETOOBIG;
   if (prm->sweeps_per_dinkelbach < 1 || prm->max_dinkelbach < 1 || prm->max_groups < 0 || prm->tile < 0 ||
-      prm->lds_kb < 0 || !(prm->block == 0 || prm->block == 256 || prm->block == 512) || prm->wave < 0 ||
+      prm->lds_kb < 0 || !(prm->block == 0 || prm->block == 256 || prm->block == 512 || prm->block == 1024) || prm->wave < 0 ||
       prm->wave > 16)
     return ALLOC_EINVAL;
   for (int m = 0; m < pb->M; ++m) {
@@ -1818,7 +1819,7 @@ int solve_one(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, 
   if (rc != ALLOC_OK) return rc;
   const int M = pb->M, N = pb->N, K = pb->K, L = pb->l, NP = L * (L - 1) / 2;
   const size_t budget = ctx->lds_max - 1024;  // the kernel's static LDS stays below 1 KB
-  if (carve_lds(nullptr, M, K, L, 1, nullptr) > budget) return ALLOC_ETOOBIG;
+  if (carve_lds(nullptr, M, K, L, 1, kGridBlock, nullptr) > budget) return ALLOC_ETOOBIG;
   if (hipSetDevice(ctx->device) != hipSuccess) return ALLOC_EDEVICE;
   const bool gain_dev = prm->flags & ALLOC_GAIN_ON_DEVICE;
   const bool out_dev = prm->flags & ALLOC_OUT_ON_DEVICE;
@@ -1833,10 +1834,11 @@ int solve_one(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, 
   int G = std::min(N, ctx->cus);
   if (prm->max_groups > 0) G = std::min(G, prm->max_groups);
   const int nb = (N + G - 1) / G;
-  const int T = balanced_tile(nb, prm->tile, [&](int t) { return carve_lds(nullptr, M, K, L, t, nullptr) <= budget; });
-  const size_t lds = carve_lds(nullptr, M, K, L, T, nullptr);
+  const int T = balanced_tile(nb, prm->tile,
+                              [&](int t) { return carve_lds(nullptr, M, K, L, t, kGridBlock, nullptr) <= budget; });
+  const size_t lds = carve_lds(nullptr, M, K, L, T, kGridBlock, nullptr);
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)solve_kernel, kBlock, lds) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)solve_kernel, kGridBlock, lds) !=
       hipSuccess)
     return ALLOC_EDEVICE;
   if (per_cu < 1) return ALLOC_ETOOBIG;
@@ -1992,7 +1994,7 @@ int solve_one(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, 
   sc.tile = T;
   void* args[] = {(void*)&d, (void*)&sc};
   if (ctx->timing && hipEventRecord(ctx->ev0, st) != hipSuccess) return ALLOC_EDEVICE;
-  if (hipLaunchCooperativeKernel((const void*)solve_kernel, dim3(G), dim3(kBlock), args, lds, st) !=
+  if (hipLaunchCooperativeKernel((const void*)solve_kernel, dim3(G), dim3(kGridBlock), args, lds, st) !=
       hipSuccess)
     return ALLOC_EDEVICE;
   if (ctx->timing && hipEventRecord(ctx->ev1, st) != hipSuccess) return ALLOC_EDEVICE;
@@ -2072,7 +2074,7 @@ struct BatchPlan {
   std::vector<int> Ms, Ns, Ks, Ls;
   Sched sc;
   int grid = 0;
-  int threads = kBlock;
+  int threads = kGridBlock;
   size_t lds = 0;
 };
 
@@ -2105,12 +2107,12 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
   if (hipFuncGetAttributes(&fa, (const void*)batch_kernel) != hipSuccess) return ALLOC_EDEVICE;
   const size_t stat = fa.sharedSizeBytes;
   const size_t full = ctx->lds_max - stat;
-  const int nthreads = prm->block > 0 ? prm->block : kBlock;
+  const int nthreads = prm->block > 0 ? prm->block : 512;
   const int nwaves = nthreads / 64;
   size_t need = 0, need_wave = 0;
   for (int b = 0; b < B; ++b) {
     const alloc_problem& pb = probs[b];
-    need = std::max(need, carve_lds(nullptr, pb.M, pb.K, pb.l, 1, nullptr));
+    need = std::max(need, carve_lds(nullptr, pb.M, pb.K, pb.l, 1, nthreads, nullptr));
     if (prm->wave > 0) {
       const size_t w = carve_waves(nullptr, pb.M, pb.K, pb.l, prm->wave, nwaves, nullptr, nullptr);
       if (w <= full) need_wave = std::max(need_wave, w);
@@ -2308,7 +2310,8 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
       d.bar = (unsigned*)(ws + o.bar);
     }
     const int nb = (N + g - 1) / g;  // subcarriers of one rank
-    const int T = balanced_tile(nb, prm->tile, [&](int t) { return carve_lds(nullptr, M, K, L, t, nullptr) <= budget; });
+    const int T = balanced_tile(nb, prm->tile,
+                                [&](int t) { return carve_lds(nullptr, M, K, L, t, nthreads, nullptr) <= budget; });
     d.tile = T;
     d.wave = (g == 1 && prm->wave > 0 &&
               carve_waves(nullptr, M, K, L, prm->wave, nwaves, nullptr, nullptr) <= budget)

@@ -3,7 +3,8 @@
 The choices are the LDS share of a workgroup (``lds_kb``: a whole compute
 unit, or a half, a third or a quarter so that several workgroups share one),
 the cap on subcarriers per LDS tile (``tile``) and the threads per workgroup
-(``block``: 512, or 256 for more, smaller workgroups per compute unit) and
+(``block``: 512, 256 for more and smaller workgroups per compute unit, or
+1024 for one workgroup per compute unit with all of its LDS) and
 whether each wave runs its own subcarriers (``wave``: subcarriers per wave
 tile, 0 = tiles of the whole workgroup).  They change only the order of
 floating-point sums inside a drop, not the method.  Candidates are timed on
@@ -38,6 +39,8 @@ CANDIDATES = (
     {"lds_kb": 0, "tile": 0, "block": 256, "wave": 1},
     {"lds_kb": 0, "tile": 0, "block": 512, "wave": 2},
     {"lds_kb": 0, "tile": 0, "block": 256, "wave": 2},
+    {"lds_kb": 0, "tile": 0, "block": 1024, "wave": 0},
+    {"lds_kb": 0, "tile": 8, "block": 1024, "wave": 0},
 )
 DEFAULT_CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tune_cache.json")
 

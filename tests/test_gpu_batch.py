@@ -210,9 +210,10 @@ def test_lds_cap_shares_compute_units(ctx):
     for a, b in zip(capped, full):
         assert abs(a.ee - b.ee) <= 1e-9 * abs(b.ee)
         assert np.array_equal(a.sel, b.sel) and np.array_equal(a.rrh_of_user, b.rrh_of_user)
-    # 256-thread workgroups (more, smaller workgroups per compute unit)
-    for blk in (256,):
-        for a, b in zip(ctx.solve_batch(drops, dataclasses.replace(p, block=blk, lds_kb=39)), full):
+    # 256-thread workgroups (more, smaller workgroups per compute unit) and
+    # 1024-thread ones (one per compute unit, all of its LDS)
+    for blk, kb in ((256, 39), (1024, 0)):
+        for a, b in zip(ctx.solve_batch(drops, dataclasses.replace(p, block=blk, lds_kb=kb)), full):
             assert abs(a.ee - b.ee) <= 1e-9 * abs(b.ee)
             assert np.array_equal(a.sel, b.sel) and np.array_equal(a.rrh_of_user, b.rrh_of_user)
     with pytest.raises(pa.AllocError, match="-22"):
@@ -328,7 +329,9 @@ def test_group_scheduled_large_drop_matches_oracle(ctx):
     alone = ctx.solve_batch([big], p)[0]
     capped = ctx.solve_batch(drops, dataclasses.replace(p, max_groups=3))[1]
     plain = ctx.solve(big, p)
-    for x in (alone, capped, plain):
+    # 1024-thread workgroups with a whole compute unit's LDS each
+    wide = ctx.solve_batch(drops, dataclasses.replace(p, block=1024))[1]
+    for x in (alone, capped, plain, wide):
         assert abs(x.ee - res[1].ee) <= 1e-9 * abs(res[1].ee)
         assert np.array_equal(x.sel, res[1].sel) and np.array_equal(x.rrh_of_user, res[1].rrh_of_user)
 
