@@ -104,7 +104,9 @@ typedef struct {
   double step0;                  /* 0.1: subgradient step step0/sqrt(1+v) */
   uint32_t flags;                /* ALLOC_GAIN_ON_DEVICE | ALLOC_OUT_ON_DEVICE */
   int32_t max_groups;            /* 0: cap on the workgroups of the solve grid
-                                    (0 = one per compute unit, <= N) */
+                                    (0 = one per compute unit, <= N, and one per
+                                    two subcarriers when two subcarriers' triples
+                                    fit one round of a workgroup's threads) */
   int32_t tile;                  /* 0: cap on the subcarriers a workgroup processes
                                     together (0 = as many as its LDS holds); its
                                     subcarriers are split into the fewest tiles
