@@ -66,6 +66,17 @@ class _Result(ctypes.Structure):
                 ("sweeps", ctypes.c_int32), ("status_flags", ctypes.c_uint32)]
 
 
+# NumPy mirrors of the C structs (same field order, offsets and size), so
+# whole struct arrays are filled column by column.
+_PROBLEM_DTYPE = np.dtype({"names": [f for f, _ in _Problem._fields_],
+                           "formats": ["<i4"] * 4 + ["<u8"] * 8 + ["<f8"] * 7,
+                           "offsets": [getattr(_Problem, f).offset for f, _ in _Problem._fields_],
+                           "itemsize": ctypes.sizeof(_Problem)})
+_RESULT_DTYPE = np.dtype({"names": [f for f, _ in _Result._fields_],
+                          "formats": ["<u8"] * 8 + ["<f8"] * 3 + ["<i4", "<i4", "<u4"],
+                          "offsets": [getattr(_Result, f).offset for f, _ in _Result._fields_],
+                          "itemsize": ctypes.sizeof(_Result)})
+
 EXPORTS = ("alloc_ctx_create", "alloc_ctx_destroy", "alloc_params_default", "alloc_solve",
            "alloc_solve_batch", "alloc_strerror", "alloc_ctx_set_timing", "alloc_ctx_last_kernel_ms",
            "alloc_mlp_create", "alloc_mlp_destroy", "alloc_mlp_set_params", "alloc_mlp_get_params",
@@ -281,27 +292,113 @@ class Context:
                 w = w or {}
                 cwarms[b] = _Warm(*(_hp(keep, w[k], np.float64) if w.get(k) is not None else None
                                     for k in ("p0", "xi0", "zeta0")))
-        probs, results, outs = self._batch_structs(drops, keep, gains, dense_power)
+        probs, results, meta = self._batch_structs(drops, keep, gains, dense_power)
         pc = params._c(flags)
         _check(load().alloc_solve_batch(self._h, B, probs, ctypes.byref(pc), cwarms, results))
-        return [to_result(results[b], *outs[b]) for b in range(B)]
+        return self._batch_results(results, meta)
 
     @staticmethod
     def _batch_structs(drops, keep, gains, dense_power):
+        """Problem and result structs of a batch.  The per-user and per-RRH
+        inputs and every output field live in one host buffer per field,
+        drops back to back, and the struct arrays are filled column by
+        column (a handful of allocations instead of a dozen per drop); each
+        drop's arrays are views into the buffers."""
         B = len(drops)
-        probs = (_Problem * B)()
-        results = (_Result * B)()
-        outs = []
         if gains is not None and len(gains) != B:
             raise ValueError("one gain tensor per drop")
+        M = np.fromiter((d.M for d in drops), np.int64, B)
+        N = np.fromiter((d.N for d in drops), np.int64, B)
+        K = np.fromiter((d.K for d in drops), np.int64, B)
+        L = np.fromiter((d.l for d in drops), np.int64, B)
+        NP = L * (L - 1) // 2
+
+        def offsets(n):
+            o = np.zeros(B + 1, np.int64)
+            np.cumsum(n, out=o[1:])
+            return o
+
+        oK, oM, oS, oP = offsets(K), offsets(M), offsets(M * N * L), offsets(M * N * NP)
+
+        def gather(attr, dtype, o):
+            buf = np.concatenate([getattr(d, attr) for d in drops], axis=None).astype(dtype, copy=False)
+            if buf.size != o[-1]:
+                raise ValueError(f"{attr}: sizes do not match the drops")
+            buf = np.ascontiguousarray(buf)
+            keep.append(buf)
+            return buf.ctypes.data
+
+        # gain pointers (device tensors checked as in problem_struct)
+        gptr = np.empty(B, np.uint64)
         for b, drop in enumerate(drops):
+            shape = (int(M[b]), int(N[b]), int(K[b]))
             g = None if gains is None else gains[b]
-            if g is not None and not hasattr(g, "data_ptr"):
-                raise ValueError(f"gain {b} must be a GPU tensor")
-            probs[b], _ = problem_struct(drop, keep, g)
-            results[b], out, dense = result_struct(drop, dense_power)
-            outs.append((out, dense))
-        return probs, results, outs
+            if g is not None:
+                if not hasattr(g, "data_ptr"):
+                    raise ValueError(f"gain {b} must be a GPU tensor")
+                if not g.is_cuda or not g.is_contiguous() or g.dtype.itemsize != 4:
+                    raise ValueError("gain tensor must be contiguous float32 on the GPU")
+                if tuple(g.shape) != shape:
+                    raise ValueError(f"gain shape {tuple(g.shape)} != {shape}")
+                gptr[b] = g.data_ptr()
+            else:
+                if np.shape(drop.gain) != shape:
+                    raise ValueError("gain shape mismatch")
+                gptr[b] = _hp(keep, drop.gain, np.float32)
+        pr = np.zeros(B, _PROBLEM_DTYPE)
+        pr["M"], pr["N"], pr["K"], pr["l"] = M, N, K, L
+        pr["gain"] = gptr
+        pr["user_type"] = gather("user_type", np.uint8, oK) + oK[:-1]
+        pr["arrival_bps"] = gather("arrival_bps", np.float64, oK) + 8 * oK[:-1]
+        pr["delay_s"] = gather("delay_s", np.float64, oK) + 8 * oK[:-1]
+        pr["pmax_w"] = gather("pmax_w", np.float64, oM) + 8 * oM[:-1]
+        pr["eta"] = gather("eta", np.float64, oM) + 8 * oM[:-1]
+        for f in ("noise_w", "bw_hz", "packet_bits", "p_fiber_hpn", "p_fiber_lpn", "p_circuit_hpn",
+                  "p_circuit_lpn"):
+            pr[f] = np.fromiter((getattr(d, f) for d in drops), np.float64, B)
+        keep.append(pr)
+        probs = (_Problem * B).from_buffer(pr)
+
+        out_buf = dict(sel=np.empty(int(oS[-1]), np.int32), slot_power=np.empty(int(oS[-1])),
+                       rrh_of_user=np.empty(int(oK[-1]), np.int32), xi=np.empty(int(oM[-1])),
+                       zeta=np.empty(int(oK[-1])), zeta_sic=np.empty(max(1, int(oP[-1]))),
+                       user_rate=np.empty(int(oK[-1])))
+        rs = np.zeros(B, _RESULT_DTYPE)
+        for f, o, size in (("sel", oS, 4), ("slot_power", oS, 8), ("rrh_of_user", oK, 4), ("xi", oM, 8),
+                           ("zeta", oK, 8), ("zeta_sic", oP, 8), ("user_rate", oK, 8)):
+            rs[f] = out_buf[f].ctypes.data + size * o[:-1]
+        rs["zeta_sic"][NP == 0] = 0
+        dense = [None] * B
+        if dense_power:
+            oD = offsets(M * N * K)
+            dense_buf = np.empty(int(oD[-1]), np.float32)
+            rs["power"] = dense_buf.ctypes.data + 4 * oD[:-1]
+            dense = [dense_buf[int(oD[b]):int(oD[b + 1])].reshape(int(M[b]), int(N[b]), int(K[b]))
+                     for b in range(B)]
+        keep.append(rs)
+        results = (_Result * B).from_buffer(rs)
+        return probs, results, (out_buf, M, N, K, L, NP, oK, oM, oS, oP, list(enumerate(dense)))
+
+    @staticmethod
+    def _batch_results(results, meta):
+        """Result objects of a batch from _batch_structs' buffers (views)."""
+        out_buf, M, N, K, L, NP, oK, oM, oS, oP, outs = meta
+        sel, sp, rrh, xi = out_buf["sel"], out_buf["slot_power"], out_buf["rrh_of_user"], out_buf["xi"]
+        zeta, zs, ur = out_buf["zeta"], out_buf["zeta_sic"], out_buf["user_rate"]
+        M, N, L, NP = M.tolist(), N.tolist(), L.tolist(), NP.tolist()
+        oK, oM, oS, oP = oK.tolist(), oM.tolist(), oS.tolist(), oP.tolist()
+        rs = []
+        for b, dense in outs:
+            k0, k1, m0, m1, s0, s1 = oK[b], oK[b + 1], oM[b], oM[b + 1], oS[b], oS[b + 1]
+            shape = (M[b], N[b], L[b])
+            r = results[b]
+            rs.append(Result(sel=sel[s0:s1].reshape(shape), slot_power=sp[s0:s1].reshape(shape),
+                             rrh_of_user=rrh[k0:k1], xi=xi[m0:m1], zeta=zeta[k0:k1],
+                             zeta_sic=zs[oP[b]:oP[b + 1]].reshape(M[b], N[b], NP[b]),
+                             user_rate=ur[k0:k1], ee=r.ee, rate_sum=r.rate_sum,
+                             power_sum=r.power_sum, dinkelbach_iters=r.dinkelbach_iters,
+                             sweeps=r.sweeps, status_flags=r.status_flags, power=dense))
+        return rs
 
     def solve(self, drop, params: Params | None = None, gain=None, warm=None, pmask=None,
               weight=None, dense_power: bool = False) -> Result:
@@ -336,8 +433,8 @@ class Batch:
         self.drops = list(drops)
         self._gains = gains  # device gains must outlive the batch
         flags = ALLOC_GAIN_ON_DEVICE if gains is not None else 0
-        probs, results, outs = Context._batch_structs(self.drops, self._keep, gains, dense_power)
-        self._results, self._outs = results, outs
+        probs, results, meta = Context._batch_structs(self.drops, self._keep, gains, dense_power)
+        self._results, self._meta = results, meta
         pc = (params or Params())._c(flags)
         h = ctypes.c_void_p()
         _check(load().alloc_batch_create(ctx._h, len(self.drops), probs, ctypes.byref(pc), ctypes.byref(h)))
@@ -350,14 +447,12 @@ class Batch:
         return load().alloc_batch_last_ms(self._h)
 
     def results(self) -> list:
+        """Results of the last run (copies: later runs reuse the buffers)."""
         _check(load().alloc_batch_results(self._h, self._results))
-        out = []
-        for b in range(len(self.drops)):
-            o, dense = self._outs[b]
-            r = to_result(self._results[b], {k: v.copy() for k, v in o.items()},
-                          None if dense is None else dense.copy())
-            out.append(r)
-        return out
+        out_buf, *rest, outs = self._meta
+        copied = {k: v.copy() for k, v in out_buf.items()}
+        outs = [(b, None if dense is None else dense.copy()) for b, dense in outs]
+        return Context._batch_results(self._results, (copied, *rest, outs))
 
     def close(self):
         if getattr(self, "_h", None):

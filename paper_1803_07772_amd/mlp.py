@@ -219,10 +219,10 @@ class MLP:
     def solve_batch(self, drops, params: Params | None = None, gains=None, dense_power=False):
         keep = []
         flags = 1 if gains is not None else 0
-        probs, results, outs = Context._batch_structs(drops, keep, gains, dense_power)
+        probs, results, meta = Context._batch_structs(drops, keep, gains, dense_power)
         pc = (params or Params())._c(flags)
         _check(_lib().alloc_solve_batch_mlp(self._h, len(drops), probs, ctypes.byref(pc), results))
-        return [to_result(results[b], *outs[b]) for b in range(len(drops))]
+        return Context._batch_results(results, meta)
 
     def last_ms(self) -> float:
         return _lib().alloc_mlp_last_ms(self._h)
