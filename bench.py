@@ -9,6 +9,9 @@ launch shape the autotuner chose for the bucket.  Beside it, on the same GPU:
 * cfg4_ragged: the first drops of the ragged 4096-drop batch (one graph
   replay; large drops split over several workgroups);
 * plain: the same drops through alloc_solve, one after another;
+* architectures: the paper's architecture comparison (H-CRAN with PD-NOMA,
+  the same with one user per subcarrier, 1-tier C-RAN, 2-tier HCN, 1-tier
+  HPN) on the same users under the paper's channel, one batch each;
 * large_drop: the 17-RRH, 1024-subcarrier, 256-user drop (l=3, exactly 200
   sweeps per Dinkelbach step) through alloc_solve;
 * nn_warm: a warm-start network trained on the GPU (solved drops of the same
@@ -50,6 +53,8 @@ def parse():
     ap.add_argument("--no-large", action="store_true")
     ap.add_argument("--no-nn", action="store_true")
     ap.add_argument("--no-cfg4", action="store_true")
+    ap.add_argument("--no-arch", action="store_true")
+    ap.add_argument("--arch-drops", type=int, default=1024, help="drops per architecture")
     ap.add_argument("--cfg4-drops", type=int, default=1024,
                     help="drops of the ragged 4096-drop batch timed in the cfg4 leg")
     ap.add_argument("--save-tune", metavar="PATH", default=None,
@@ -243,6 +248,39 @@ def main():
         modes["plain"] = {"allocations_per_s": len(sub) / dtp, "drops": len(sub),
                           "roofline": roofline("solve_kernel", b, float(np.mean([k for _, _, k in rs])))}
         print(f"[bench] plain: {len(sub) / dtp:.1f} allocations/s", flush=True)
+
+    if not a.no_arch:
+        # the architecture comparison of the paper's simulation section: the
+        # same users and fading under the paper's channel, solved as one
+        # batch per architecture
+        arch = {}
+        for kind in synth.ARCHITECTURES:
+            da = [synth.architecture_drop(kind, 0, i) for i in range(a.arch_drops)]
+            ga = [torch.from_numpy(d.gain).to(dev) for d in da]
+            ba = pa.Batch(ctx, da, tune.tuned(da, params, cache), gains=ga)
+            ba.run()
+            ba.run()
+            msa = ba.last_ms()
+            ra = ba.results()
+            ba.close()
+            ee = np.array([r.ee for r in ra])
+            arch[kind] = {"allocations_per_s": len(da) / (msa * 1e-3), "kernel_ms": msa,
+                          "M": da[0].M, "l": da[0].l, "ee_mean": float(ee.mean()),
+                          "ee_median": float(np.median(ee)),
+                          "rate_sum_mean": float(np.mean([r.rate_sum for r in ra])),
+                          "power_sum_mean": float(np.mean([r.power_sum for r in ra])),
+                          "sweeps_mean": float(np.mean([r.sweeps for r in ra])),
+                          "qos_infeasible": int(sum(bool(r.status_flags & pa.QOS_INFEASIBLE) for r in ra))}
+            del ga
+        base = arch["hcran"]["ee_mean"]
+        for kind in arch:
+            arch[kind]["ee_over_hcran"] = arch[kind]["ee_mean"] / base
+        modes["architectures"] = {
+            "workload": f"{a.arch_drops} drops per architecture of the paper's channel "
+                        "(chi d^-3, 42/23 dBm, N=32, K=12 of which 6 streaming at 125 packets/s), "
+                        "one graph replay each", **arch}
+        print("[bench] architectures: " + ", ".join(f"{k} EE {v['ee_mean']:.1f}" for k, v in arch.items()),
+              flush=True)
 
     if not a.no_large:
         d3 = synth.make_drop(synth.CFG3, 0, 0)

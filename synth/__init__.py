@@ -195,6 +195,58 @@ PAPER = Recipe(cfg_id=10, M=3, N=32, K=12, K_s=6, l=2, path_loss_model=1,
 
 PRESETS = {"cfg1": CFG1, "cfg2": CFG2, "cfg3": CFG3, "paper": PAPER}
 
+# Network architectures compared in the paper's simulation section (Sec. VIII,
+# the architecture comparison): the same users and fading, different radio
+# access networks on the same sites.  Under the paper's channel
+# (chi * d^-psi) a gain does not depend on the tier of the transmitter, so a
+# variant changes only which sites transmit, their power budgets and
+# efficiencies, and the static power; the solver charges RRH 0 the "hpn"
+# static terms and every other RRH the "lpn" ones.
+#
+# * hcran  the H-CRAN itself: an HPN and M-1 LPN RRHs, PD-NOMA (l users per
+#          subcarrier)
+# * oma    the same network with one user per subcarrier (l = 1)
+# * cran   1-tier C-RAN: LPN RRHs only (an LPN at the HPN's site too)
+# * hcn    2-tier HCN: base stations instead of RRHs (no fronthaul), a macro BS
+#          at the HPN's site (10 W static) and pico BSs at the LPNs' (6.8 W
+#          each), efficiency 4 for all
+# * hpn    1-tier HPN: two macro BSs, at the HPN's site and the first LPN's,
+#          both with the HPN's power budget, 10 W static and efficiency 4
+ARCHITECTURES = ("hcran", "oma", "cran", "hcn", "hpn")
+MACRO_STATIC_W = 10.0
+PICO_STATIC_W = 6.8
+BS_ETA = 4.0
+
+
+def architecture_drop(arch: str, seed: int = 0, index: int = 0, recipe: Recipe = None) -> Drop:
+    """Drop ``index`` of ``seed`` in one of the compared architectures.  All of
+    them are cut from the same H-CRAN drop, so they serve the same users over
+    the same fading."""
+    rc = PAPER if recipe is None else recipe
+    if rc.path_loss_model != 1:
+        raise ValueError("architectures are defined under the tier-independent channel (chi * d^-psi)")
+    if arch not in ARCHITECTURES:
+        raise ValueError(f"unknown architecture {arch!r}")
+    if arch == "hpn" and rc.M < 2:
+        raise ValueError("1-tier HPN needs two sites")
+    d = make_drop(rc, seed, index)
+    if arch == "oma":
+        return dataclasses.replace(d, l=1)
+    if arch == "cran":
+        return dataclasses.replace(d, pmax_w=np.full(d.M, d.pmax_w[-1]), eta=np.full(d.M, rc.eta_lpn),
+                                   p_fiber_hpn=d.p_fiber_lpn, p_circuit_hpn=d.p_circuit_lpn)
+    if arch == "hcn":
+        return dataclasses.replace(d, eta=np.full(d.M, BS_ETA), p_fiber_hpn=0.0, p_fiber_lpn=0.0,
+                                   p_circuit_hpn=MACRO_STATIC_W, p_circuit_lpn=PICO_STATIC_W)
+    if arch == "hpn":
+        two = slice(0, 2)
+        return dataclasses.replace(d, M=2, gain=np.ascontiguousarray(d.gain[two]),
+                                   pmax_w=np.full(2, d.pmax_w[0]), eta=np.full(2, BS_ETA),
+                                   rrh_xy=d.rrh_xy[two].copy(), p_fiber_hpn=0.0, p_fiber_lpn=0.0,
+                                   p_circuit_hpn=MACRO_STATIC_W, p_circuit_lpn=MACRO_STATIC_W)
+    return d
+
+
 CFG4_N_CHOICES = (64, 128, 256, 512, 1024)
 
 
