@@ -12,6 +12,8 @@ launch shape the autotuner chose for the bucket.  Beside it, on the same GPU:
 * architectures: the paper's architecture comparison (H-CRAN with PD-NOMA,
   the same with one user per subcarrier, 1-tier C-RAN, 2-tier HCN, 1-tier
   HPN) on the same users under the paper's channel, one batch each;
+* paper_sweeps (with --sweeps): the trend studies of the paper's simulation
+  section (users, streaming users, arrival rate, PD-NOMA/OMA, LPN count);
 * large_drop: the 17-RRH, 1024-subcarrier, 256-user drop (l=3, exactly 200
   sweeps per Dinkelbach step) through alloc_solve;
 * nn_warm: a warm-start network trained on the GPU (solved drops of the same
@@ -55,6 +57,9 @@ def parse():
     ap.add_argument("--no-cfg4", action="store_true")
     ap.add_argument("--no-arch", action="store_true")
     ap.add_argument("--arch-drops", type=int, default=1024, help="drops per architecture")
+    ap.add_argument("--sweeps", action="store_true",
+                    help="also run the trend studies of the paper's simulation section")
+    ap.add_argument("--sweep-drops", type=int, default=256, help="drops per point of --sweeps")
     ap.add_argument("--cfg4-drops", type=int, default=1024,
                     help="drops of the ragged 4096-drop batch timed in the cfg4 leg")
     ap.add_argument("--save-tune", metavar="PATH", default=None,
@@ -120,6 +125,48 @@ def roofline(kernel, bytes_per_launch, ms_per_launch, drops=None):
     if v:
         r["valu_issue"] = v
     return r
+
+
+def paper_sweeps(ctx, params, drops_per_point: int):
+    """The trend studies of the paper's simulation section on its channel:
+    EE of the elastic users against the number of users for several counts of
+    streaming users, for several packet arrival rates, and with PD-NOMA
+    against OMA; and against the number of LPN RRHs (12 users, half
+    streaming).  One batched solve of drops_per_point drops per point."""
+    import dataclasses as dc
+
+    import numpy as np
+
+    import synth
+    base = synth.PAPER
+    pts = []
+    for ks in (2, 4, 6):
+        for k in (8, 12, 16, 20, 24, 28):
+            pts.append(("streaming_users", dict(K_s=ks), k, dc.replace(base, K=k, K_s=ks)))
+    for lam in (62.5, 125.0, 250.0):
+        for k in (12, 16, 20, 24, 28):
+            rate = lam * base.packet_bits
+            pts.append(("arrival_rate", dict(packets_per_s=lam), k,
+                        dc.replace(base, K=k, K_s=6, rate_bps_lo=rate, rate_bps_hi=rate)))
+    for l in (2, 1):
+        for k in (12, 16, 20, 24, 28):
+            pts.append(("noma_vs_oma", dict(l=l), k, dc.replace(base, K=k, K_s=6, l=l)))
+        for mf in (1, 2, 3, 4, 5, 6):
+            pts.append(("lpn_count", dict(l=l), mf, dc.replace(base, M=1 + mf, K=12, K_s=6, l=l)))
+    out, solved, t_solve = {}, 0, 0.0
+    for study, series, x, rc in pts:
+        drops = [synth.make_drop(rc, 0, i) for i in range(drops_per_point)]
+        t0 = time.perf_counter()
+        rs = ctx.solve_batch(drops, params)
+        t_solve += time.perf_counter() - t0
+        solved += len(drops)
+        key = ",".join(f"{a}={b}" for a, b in series.items())
+        out.setdefault(study, {}).setdefault(key, []).append(
+            {"x": x, "ee_mean": float(np.mean([r.ee for r in rs])),
+             "qos_infeasible": int(sum(bool(r.status_flags & 2) for r in rs))})
+    out["drops_per_point"] = drops_per_point
+    out["allocations_per_s"] = solved / t_solve
+    return out
 
 
 def main():
@@ -281,6 +328,10 @@ def main():
                         "one graph replay each", **arch}
         print("[bench] architectures: " + ", ".join(f"{k} EE {v['ee_mean']:.1f}" for k, v in arch.items()),
               flush=True)
+
+    if a.sweeps:
+        modes["paper_sweeps"] = paper_sweeps(ctx, params, a.sweep_drops)
+        print("[bench] paper sweeps done", flush=True)
 
     if not a.no_large:
         d3 = synth.make_drop(synth.CFG3, 0, 0)

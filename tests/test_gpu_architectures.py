@@ -62,3 +62,19 @@ def test_architectures_plain(ctx, arch):
     print(f"[gpu case] plain {arch}", flush=True)
     r = ctx.solve(d, pa.Params(fixed_count=0))
     _check([d], [r], oracle.Params(fixed_count=0))
+
+
+def test_trend_study_points(ctx):
+    """Corner points of the trend studies run by bench.py --sweeps: most users
+    and LPNs, the highest arrival rate, OMA."""
+    import paper_1803_07772_amd as pa
+    base = synth.PAPER
+    rcs = [dataclasses.replace(base, K=28, K_s=2), dataclasses.replace(base, K=28, K_s=6,
+                                                                       rate_bps_lo=256e3, rate_bps_hi=256e3),
+           dataclasses.replace(base, M=7, K=12, K_s=6), dataclasses.replace(base, M=7, K=12, K_s=6, l=1),
+           dataclasses.replace(base, K=28, K_s=6, l=1)]
+    drops = [synth.make_drop(rc, 0, i) for rc in rcs for i in range(4)]
+    print(f"[gpu case] trend-study batch of {len(drops)} drops", flush=True)
+    res = ctx.solve_batch(drops, pa.Params(fixed_count=0))
+    ties, chaotic = _check(drops, res, oracle.Params(fixed_count=0))
+    assert chaotic <= 2 and ties + chaotic <= len(drops) // 2
