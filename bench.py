@@ -391,11 +391,26 @@ def main():
             oracle.solve(drops[n % len(drops)], op)
             n += 1
         dtc = time.perf_counter() - t0
-        cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        cores = oracle.set_threads(1)
+        t1 = time.perf_counter()
+        n1 = 0
+        while time.perf_counter() - t1 < 5.0:
+            oracle.solve(drops[n1 % len(drops)], op)
+            n1 += 1
+        dt1 = time.perf_counter() - t1
+        oracle.set_threads(cores)
+        model = ""
+        try:
+            with open("/proc/cpuinfo") as f:
+                model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), "")
+        except OSError:
+            pass
         line["cpu_baseline"] = {"value": n / dtc, "unit": "allocations/s", "cores": cores,
                                 "kind": "oracle",
                                 "sample": f"{n} solves of the first drops of the benchmark batch in "
-                                          f"{dtc:.1f} s (FP64 C oracle, OpenMP over subcarriers)"}
+                                          f"{dtc:.1f} s (FP64 C oracle, OpenMP over subcarriers)",
+                                "single_thread": {"value": n1 / dt1, "solves": n1, "seconds": dt1},
+                                "cpu_model": model}
     ctx.close()
     print(json.dumps(line), flush=True)
 

@@ -96,6 +96,8 @@ def _load():
         lib.orc_min_rate.restype = ctypes.c_double
         lib.orc_scale_coeffs.argtypes = [ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p]
         lib.orc_sic_margin.argtypes = [ctypes.c_double] * 5
+        lib.orc_set_threads.argtypes = [ctypes.c_int]
+        lib.orc_set_threads.restype = ctypes.c_int
         lib.orc_sic_margin.restype = ctypes.c_double
         _lib = lib
     return _lib
@@ -305,6 +307,12 @@ def scale_coeffs(z0: float):
     b = ctypes.c_double()
     _load().orc_scale_coeffs(z0, ctypes.byref(a), ctypes.byref(b))
     return a.value, b.value
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's loops over subcarriers (n < 1: unchanged);
+    returns the previous setting."""
+    return _load().orc_set_threads(n)
 
 
 def sic_margin(g_s, g_w, ici_s, ici_w, sigma) -> float:

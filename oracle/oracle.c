@@ -39,6 +39,7 @@
 
 #include <float.h>
 #include <math.h>
+#include <omp.h>
 #include <stdlib.h>
 #include <string.h>
 
@@ -77,6 +78,14 @@ ORC_API void orc_scale_coeffs(double z0, double* alpha, double* beta) {
  * weaker w, Omega = Gamma_w sigma - Gamma_s sigma + Gamma_w ICI_s - Gamma_s ICI_w,
  * and C8/C14 ask Omega <= 0.  Returned divided by the positive scale
  * nu = Gamma_w (sigma + ICI_s) + Gamma_s (sigma + ICI_w). */
+/* Threads of the OpenMP loops over subcarriers; returns the previous
+ * setting.  n < 1 leaves it unchanged. */
+ORC_API int orc_set_threads(int n) {
+  const int prev = omp_get_max_threads();
+  if (n > 0) omp_set_num_threads(n);
+  return prev;
+}
+
 ORC_API double orc_sic_margin(double g_s, double g_w, double ici_s, double ici_w,
                               double sigma) {
   const double omega = g_w * sigma - g_s * sigma + g_w * ici_s - g_s * ici_w;

@@ -129,6 +129,9 @@ double orc_min_rate(double arrival_bps, double delay_s, double packet_bits, doub
 void orc_scale_coeffs(double z0, double* alpha, double* beta);
 /* Relative SIC margin of a co-scheduled pair (strong s by raw gain, weak w). */
 double orc_sic_margin(double g_s, double g_w, double ici_s, double ici_w, double sigma);
+/* OpenMP threads of the loops over subcarriers (n < 1: unchanged); returns
+ * the previous setting. */
+int orc_set_threads(int n);
 
 #ifdef __cplusplus
 }

@@ -605,3 +605,19 @@ def test_brute_force_tiny_instances():
     print("EE / brute-force optimum:", np.round(ratios, 3))
     assert len(ratios) >= 4
     assert np.median(ratios) >= 0.75
+
+
+def test_oracle_result_independent_of_thread_count():
+    """The oracle's sums run in a fixed order: one thread or many give the
+    same bits (the benchmark times it both ways)."""
+    d = synth.make_drop(synth.CFG2, 3, 0)
+    op = oracle.Params(fixed_count=0)
+    prev = oracle.set_threads(1)
+    try:
+        r1 = oracle.solve(d, op)
+    finally:
+        oracle.set_threads(prev)
+    rn = oracle.solve(d, op)
+    assert r1.ee == rn.ee and r1.sweeps == rn.sweeps
+    np.testing.assert_array_equal(r1.sel, rn.sel)
+    np.testing.assert_array_equal(r1.slot_power, rn.slot_power)
