@@ -152,7 +152,10 @@ typedef struct {
   int32_t* sel;        /* [M][N][l] users of (m,n) in SIC decoding order, -1 = empty */
   double* slot_power;  /* [M][N][l] power of those users (W) */
   float* power;        /* [M][N][K] dense powers (W) */
-  int32_t* rrh_of_user; /* [K] serving RRH, -1 = unserved */
+  int32_t* rrh_of_user; /* [K] association A_k from the last sweep (the RRH the user may be
+                           served by in the next one), -1 = unserved.  When the dual loop
+                           ends at its sweep cap, a user whose A_k that sweep moved is still
+                           served by its previous RRH in sel / slot_power. */
   double* xi;          /* [M] */
   double* zeta;        /* [K] (0 for elastic users) */
   double* zeta_sic;    /* [M][N][l(l-1)/2] C14 multiplier of decoding positions (a<b) */

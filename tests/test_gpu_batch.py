@@ -350,3 +350,61 @@ def test_group_scheduled_graph_replays(ctx):
         for a, b in zip(bt.results(), eager):
             _same(a, b)
     bt.close()
+
+
+def _check_structure(d, r):
+    """What holds for any correct allocation of the drop: distinct users per
+    subcarrier, each user served by one RRH at most (C5/C6), powers within
+    the mask and zero on empty slots, EE = rate / power.  (rrh_of_user is
+    the association the last sweep computed for the next one, so a served
+    user may already show another RRH there.)"""
+    sel, sp = r.sel, r.slot_power
+    assert sel.shape == (d.M, d.N, d.l)
+    assert ((sel >= -1) & (sel < d.K)).all()
+    assert ((r.rrh_of_user >= -1) & (r.rrh_of_user < d.M)).all()
+    mask = d.pmax_w / d.N
+    assert (sp >= 0).all() and (sp <= mask[:, None, None] * (1 + 1e-12)).all()
+    assert (sp[sel < 0] == 0).all()
+    served_by = np.full(d.K, -1)
+    for m in range(d.M):
+        for n in range(d.N):
+            users = sel[m, n][sel[m, n] >= 0]
+            assert len(set(users.tolist())) == len(users)
+            assert ((served_by[users] == -1) | (served_by[users] == m)).all()
+            served_by[users] = m
+    assert np.isfinite(r.ee) and r.ee == pytest.approx(r.rate_sum / r.power_sum, rel=1e-12)
+
+
+def test_benchmark_batch_full_size(ctx):
+    """The benchmark's workload at full size and in its launch shape: 4096
+    drops of 5 RRHs x 64 subcarriers x 32 users, one graph replay in the
+    tuned shape.  A seeded sample of 16 drops against the oracle; every drop
+    against the properties any allocation has."""
+    import torch
+
+    import paper_1803_07772_amd as pa
+    from paper_1803_07772_amd import tune
+    drops = [synth.make_drop(synth.CFG2, s, 0) for s in range(4096)]
+    gains = [torch.from_numpy(d.gain).cuda() for d in drops]
+    p = tune.tuned(drops, pa.Params(fixed_count=0))
+    print(f"[gpu case] 4096-drop batch, lds_kb={p.lds_kb} block={p.block} wave={p.wave}", flush=True)
+    bt = pa.Batch(ctx, drops, p, gains=gains)
+    bt.run()
+    res = bt.results()
+    bt.close()
+    for d, r in zip(drops, res):
+        _check_structure(d, r)
+    op = oracle.Params(fixed_count=0)
+    sample = np.random.default_rng(20240).choice(len(drops), 16, replace=False)
+    skipped = 0
+    for b in sample:
+        d, r = drops[b], res[b]
+        o = oracle.solve(d, op)
+
+        def rerun(scale, d=d):
+            return oracle.solve(dataclasses.replace(d, noise_w=d.noise_w * scale), op)
+
+        info = parity.compare(d, r, o, label=f"benchmark drop {b}", rerun=rerun)
+        print(info, flush=True)
+        skipped += bool(info.get("skipped"))
+    assert skipped <= 4
