@@ -129,6 +129,22 @@ class MLP:
         _check(_lib().alloc_mlp_get_params(self._h, a.ctypes.data, N_PARAMS))
         return a
 
+    def save(self, path: str):
+        """Writes the FP32 master weights (the order alloc_mlp_get_params
+        returns) to a safetensors file; the optimizer's moments are not saved."""
+        from safetensors.numpy import save_file
+        save_file({"params": self.get_params()}, path,
+                  metadata={"n_params": str(N_PARAMS), "layers": "4-256-256-256-3"})
+
+    @classmethod
+    def load(cls, ctx: Context, path: str) -> "MLP":
+        """A network on ``ctx`` with the weights save() wrote."""
+        from safetensors.numpy import load_file
+        t = load_file(path)
+        if set(t) != {"params"} or t["params"].dtype != np.float32 or t["params"].size != N_PARAMS:
+            raise ValueError(f"{path}: not a saved warm-start network")
+        return cls(ctx, t["params"])
+
     def features(self, drop, gain=None, pmask=None):
         import torch
         keep = []

@@ -90,6 +90,23 @@ def test_get_set_params_roundtrip(ctx):
     assert np.array_equal(net.get_params(), flat)
 
 
+def test_save_load_roundtrip(ctx, tmp_path):
+    from paper_1803_07772_amd.mlp import MLP
+    flat, _ = _weights(2)
+    net = _net(ctx, flat)
+    path = str(tmp_path / "net.safetensors")
+    net.save(path)
+    back = MLP.load(ctx, path)
+    assert np.array_equal(back.get_params(), flat)
+    X = _cuda(_feat(np.random.default_rng(9), 300))
+    assert np.array_equal(back.forward(X).cpu().numpy(), net.forward(X).cpu().numpy())
+    from safetensors.numpy import save_file
+    bad = str(tmp_path / "bad.safetensors")
+    save_file({"params": flat[:10]}, bad)
+    with pytest.raises(ValueError):
+        MLP.load(ctx, bad)
+
+
 def test_features_match_reference(ctx):
     d = synth.make_drop(synth.CFG2, 3, 0)
     print("[gpu case] mlp features cfg2", flush=True)
