@@ -304,7 +304,13 @@ def main():
         for kind in synth.ARCHITECTURES:
             da = [synth.architecture_drop(kind, 0, i) for i in range(a.arch_drops)]
             ga = [torch.from_numpy(d.gain).to(dev) for d in da]
-            ba = pa.Batch(ctx, da, tune.tuned(da, params, cache), gains=ga)
+            ka = tune.batch_key(da)
+            if ka in cache and not a.save_tune:
+                pk, tk = tune.tuned(da, params, cache), "cache"
+            else:
+                best_a, _ = tune.tune(ctx, da, params, gains=ga, cache=cache)
+                pk, tk = dataclasses.replace(params, **best_a), "measured"
+            ba = pa.Batch(ctx, da, pk, gains=ga)
             ba.run()
             ba.run()
             msa = ba.last_ms()
@@ -317,7 +323,9 @@ def main():
                           "rate_sum_mean": float(np.mean([r.rate_sum for r in ra])),
                           "power_sum_mean": float(np.mean([r.power_sum for r in ra])),
                           "sweeps_mean": float(np.mean([r.sweeps for r in ra])),
-                          "qos_infeasible": int(sum(bool(r.status_flags & pa.QOS_INFEASIBLE) for r in ra))}
+                          "qos_infeasible": int(sum(bool(r.status_flags & pa.QOS_INFEASIBLE) for r in ra)),
+                          "launch": {"lds_kb": pk.lds_kb, "tile": pk.tile, "block": pk.block or 512,
+                                     "wave": pk.wave, "tuned_from": tk, "bucket": ka}}
             del ga
         base = arch["hcran"]["ee_mean"]
         for kind in arch:
@@ -328,6 +336,9 @@ def main():
                         "one graph replay each", **arch}
         print("[bench] architectures: " + ", ".join(f"{k} EE {v['ee_mean']:.1f}" for k, v in arch.items()),
               flush=True)
+
+    if a.save_tune and not a.no_arch:
+        tune.save_cache(cache, a.save_tune)
 
     if a.sweeps:
         modes["paper_sweeps"] = paper_sweeps(ctx, params, a.sweep_drops)
