@@ -305,11 +305,13 @@ def main():
             da = [synth.architecture_drop(kind, 0, i) for i in range(a.arch_drops)]
             ga = [torch.from_numpy(d.gain).to(dev) for d in da]
             ka = tune.batch_key(da)
-            if ka in cache and not a.save_tune:
-                pk, tk = tune.tuned(da, params, cache), "cache"
-            else:
+            if a.save_tune:
                 best_a, _ = tune.tune(ctx, da, params, gains=ga, cache=cache)
                 pk, tk = dataclasses.replace(params, **best_a), "measured"
+            elif ka in cache:
+                pk, tk = tune.tuned(da, params, cache), "cache"
+            else:  # untuned bucket: the default launch shape
+                pk, tk = params, "default"
             ba = pa.Batch(ctx, da, pk, gains=ga)
             ba.run()
             ba.run()
