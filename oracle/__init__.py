@@ -21,6 +21,8 @@ NOT_CONVERGED = 1
 QOS_INFEASIBLE = 2
 NEAR_TIE = 4
 NONFINITE = 8
+SIC_INFEASIBLE = 16
+BUDGET_INFEASIBLE = 64
 
 
 def build() -> str:
@@ -48,7 +50,7 @@ class _Params(ctypes.Structure):
                 ("refit_period", ctypes.c_int32), ("fixed_count", ctypes.c_int32),
                 ("tol_dinkelbach", ctypes.c_double), ("tol_dual", ctypes.c_double),
                 ("step0", ctypes.c_double), ("tie_rel", ctypes.c_double),
-                ("churn_limit", ctypes.c_int32)]
+                ("stall_sweeps", ctypes.c_int32), ("qos_down", ctypes.c_double)]
 
 
 class _Warm(ctypes.Structure):
@@ -59,9 +61,11 @@ class _Result(ctypes.Structure):
     _fields_ = [("sel", ctypes.c_void_p), ("slot_power", ctypes.c_void_p),
                 ("rrh_of_user", ctypes.c_void_p), ("xi", ctypes.c_void_p),
                 ("zeta", ctypes.c_void_p), ("zeta_sic", ctypes.c_void_p),
-                ("user_rate", ctypes.c_void_p), ("ee", ctypes.c_double),
+                ("user_rate", ctypes.c_void_p), ("tie_mn", ctypes.c_void_p),
+                ("tie_user", ctypes.c_void_p), ("ee", ctypes.c_double),
                 ("rate_sum", ctypes.c_double), ("power_sum", ctypes.c_double),
-                ("dinkelbach_iters", ctypes.c_int32), ("sweeps", ctypes.c_int32),
+                ("viol_qos", ctypes.c_double), ("viol_budget", ctypes.c_double),
+                ("viol_sic", ctypes.c_double), ("dinkelbach_iters", ctypes.c_int32), ("sweeps", ctypes.c_int32),
                 ("status_flags", ctypes.c_uint32), ("near_ties", ctypes.c_int64),
                 ("min_margin", ctypes.c_double), ("first_tie_sweep", ctypes.c_int32),
                 ("trace_E", ctypes.c_void_p), ("trace_F", ctypes.c_void_p),
@@ -83,7 +87,6 @@ def _load():
         lib.orc_state_destroy.argtypes = [ctypes.c_void_p]
         lib.orc_state_set_E.argtypes = [ctypes.c_void_p, ctypes.c_double]
         lib.orc_state_reset_scale.argtypes = [ctypes.c_void_p]
-        lib.orc_state_reset_churn.argtypes = [ctypes.c_void_p]
         lib.orc_state_sweep.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]
         lib.orc_state_sweep.restype = ctypes.c_double
         lib.orc_state_eval.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 4
@@ -113,12 +116,13 @@ class Params:
     tol_dual: float = 1e-7
     step0: float = 0.1
     tie_rel: float = 1e-9
-    churn_limit: int = 8
+    stall_sweeps: int = 30
+    qos_down: float = 0.2
 
     def _c(self) -> _Params:
         return _Params(self.max_dinkelbach, self.sweeps_per_dinkelbach, self.refit_period,
                        self.fixed_count, self.tol_dinkelbach, self.tol_dual, self.step0,
-                       self.tie_rel, self.churn_limit)
+                       self.tie_rel, self.stall_sweeps, self.qos_down)
 
 
 @dataclasses.dataclass
@@ -130,9 +134,14 @@ class Result:
     zeta: np.ndarray
     zeta_sic: np.ndarray
     user_rate: np.ndarray
+    tie_mn: np.ndarray
+    tie_user: np.ndarray
     ee: float
     rate_sum: float
     power_sum: float
+    viol_qos: float
+    viol_budget: float
+    viol_sic: float
     dinkelbach_iters: int
     sweeps: int
     status_flags: int
@@ -187,13 +196,15 @@ def solve(drop, params: Params | None = None, warm=None, pmask=None, weight=None
     NP = L * (L - 1) // 2
     out = dict(sel=np.empty((M, N, L), np.int32), slot_power=np.empty((M, N, L)),
                rrh_of_user=np.empty(K, np.int32), xi=np.empty(M), zeta=np.empty(K),
-               zeta_sic=np.empty((M, N, NP)), user_rate=np.empty(K))
+               zeta_sic=np.empty((M, N, NP)), user_rate=np.empty(K),
+               tie_mn=np.zeros((M, N), np.int32), tie_user=np.zeros(K, np.int32))
     T = max(params.max_dinkelbach, 1)
     tr = dict(trace_E=np.zeros(T), trace_F=np.zeros(T), trace_R=np.zeros(T),
               trace_P=np.zeros(T), trace_sweeps=np.zeros(T, np.int32))
     res = _Result(*(out[k].ctypes.data for k in ("sel", "slot_power", "rrh_of_user", "xi",
-                                                  "zeta", "zeta_sic", "user_rate")),
-                  0.0, 0.0, 0.0, 0, 0, 0, 0, 0.0, -1,
+                                                  "zeta", "zeta_sic", "user_rate", "tie_mn",
+                                                  "tie_user")),
+                  0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0, 0, 0.0, -1,
                   *(tr[k].ctypes.data for k in ("trace_E", "trace_F", "trace_R", "trace_P",
                                                  "trace_sweeps")))
     pb = _problem(drop, keep, pmask, weight, gain)
@@ -204,6 +215,7 @@ def solve(drop, params: Params | None = None, warm=None, pmask=None, weight=None
         raise ValueError(f"orc_solve rejected the problem ({rc})")
     n = res.dinkelbach_iters
     return Result(ee=res.ee, rate_sum=res.rate_sum, power_sum=res.power_sum,
+                  viol_qos=res.viol_qos, viol_budget=res.viol_budget, viol_sic=res.viol_sic,
                   dinkelbach_iters=n, sweeps=res.sweeps, status_flags=res.status_flags,
                   near_ties=res.near_ties, min_margin=res.min_margin,
                   first_tie_sweep=res.first_tie_sweep,
@@ -240,9 +252,6 @@ class State:
 
     def reset_scale(self):
         self._lib.orc_state_reset_scale(self._h)
-
-    def reset_churn(self):
-        self._lib.orc_state_reset_churn(self._h)
 
     def sweep(self, v: int, refit: bool) -> float:
         return self._lib.orc_state_sweep(self._h, v, int(refit))
@@ -292,8 +301,9 @@ class State:
                    rrh_of_user=np.empty(d.K, np.int32), xi=np.empty(d.M), zeta=np.empty(d.K),
                    zeta_sic=np.empty((d.M, d.N, NP)))
         res = _Result(*(out[k].ctypes.data for k in ("sel", "slot_power", "rrh_of_user", "xi",
-                                                      "zeta", "zeta_sic")), None,
-                      0.0, 0.0, 0.0, 0, 0, 0, 0, 0.0, -1, None, None, None, None, None)
+                                                      "zeta", "zeta_sic")), None, None, None,
+                      0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0, 0, 0.0, -1,
+                      None, None, None, None, None)
         self._lib.orc_state_export(self._h, ctypes.byref(res))
         return out
 

@@ -22,18 +22,28 @@
  *    weighted by mu = 1 (elastic) or zeta'_k (streaming);
  *  - C14 is used as the scale-free margin Omega/nu with
  *    nu = Gamma_w(sigma+ICI_s) + Gamma_s(sigma+ICI_w) taken at the state;
- *  - the binary constraints are met by selection: per (m,n) the l users of
- *    RRH m with the largest positive per-triple Lagrangian maximum H; per user
- *    the RRH with the largest sum of H over subcarriers, applied from the next
- *    sweep;
+ *  - the binary constraints are met by selection: per (m,n) the users of
+ *    RRH m with positive per-triple Lagrangian maximum H are taken in order
+ *    of H, each only if every pair it forms with those taken before it meets
+ *    C14 at the state's interference, up to l users; per user the RRH with
+ *    the largest sum of H over subcarriers, applied from the next sweep;
  *  - subgradient step step0/sqrt(1+v); xi' scaled by N*l/(ln2*pmax_m);
- *    the relative C13 violation clipped to [-1, 1];
+ *    the relative C13 violation clipped to [-qos_down, 1] (a streaming
+ *    user's rate jumps between zero and several times its minimum as it
+ *    gains or loses a subcarrier, so zeta' falls more slowly than it rises);
  *  - closed-form powers below 1e-20 of the mask are set to zero;
- *  - churn cap: within one Dinkelbach step the selected set of an (m,n) and
- *    the RRH of a user may change at most churn_limit times, after which
- *    they are frozen (simultaneous discrete updates can cycle); all
- *    sweeps are Jacobi (every quantity of a sweep is read from the state the
- *    sweep starts from).
+ *  - the dual sweeps are not a descent method, so each Dinkelbach step
+ *    returns the best state it visited: feasible for C12-C14 before
+ *    infeasible, less C12/C13 violation first, then less C14 violation, then
+ *    the larger R - E P (a replacement needs a relative gain of 1e-6); the
+ *    dual loop also ends after stall_sweeps sweeps without a better state
+ *    once the best is feasible; the multipliers xi' and zeta' continue from
+ *    the last sweep;
+ *  - a warm start's allocation is Dinkelbach's p^0 only when it is feasible
+ *    (then E^1 = R(p^0)/P(p^0)); otherwise E^1 = 0 and it is the first
+ *    step's starting state;
+ *  - all sweeps are Jacobi: every quantity of a sweep is read from the state
+ *    the sweep starts from.
  */
 #include "oracle.h"
 
@@ -50,6 +60,11 @@
  * closed-form powers would otherwise reach the subnormal range, where the
  * SINR underflows and the SCALE refit produces 0 * log2(0). */
 #define POWER_FLOOR_REL 1e-20
+/* Feasibility tolerances of an iterate: C13 r >= Psi (1 - QOS_TOL), C12
+ * sum p <= pmax (1 + BUDGET_TOL), C14 margin <= SIC_TOL. */
+#define QOS_TOL 1e-6
+#define BUDGET_TOL 1e-6
+#define SIC_TOL 1e-9
 
 /* ------------------------------------------------------------------ basics */
 
@@ -121,8 +136,15 @@ struct orc_state {
   int first_tie;
   int sweeps_done;
   int assoc_changed; /* users whose RRH changed in the last sweep */
-  int* churn_sel;    /* [M][N] selection changes in this Dinkelbach step */
-  int* churn_A;      /* [K] association changes in this Dinkelbach step */
+  int32_t* tie_mn;   /* [M][N] near-tie decisions of (m,n) over the solve */
+  int32_t* tie_user; /* [K] near-tie association decisions of each user */
+  double* part_sicv; /* [N] C14 violation at the state read by the sweep */
+  int* part_moved;   /* [N] the sweep changed a selected set on the subcarrier */
+  double* part_dres; /* [N] largest C14 multiplier step / delta_v on the subcarrier */
+  int moved;         /* the last sweep changed a selected set or an association */
+  /* evaluation of a state (the one the last sweep read, or orc_state_eval's):
+   * rate R, power P, violations of C13 (Vq), C12 (Vp), C14 (Vs) */
+  double ev_R, ev_P, ev_Vq, ev_Vp, ev_Vs;
 };
 
 #define IDX3(st, m, n, k) (((size_t)(m) * (st)->N + (n)) * (st)->K + (k))
@@ -134,6 +156,15 @@ static double mu_of(const orc_state* st, int k) { return st->elastic[k] ? 1.0 : 
 static void note_margin(double margin, double tie_rel, int64_t* ties, double* minm) {
   if (margin < *minm) *minm = margin;
   if (margin <= tie_rel) (*ties)++;
+}
+
+/* A near-tie of a decision of (m,n) on its subcarrier's thread. */
+static void note_mn(orc_state* st, int m, int n, double margin, int64_t* ties, double* minm) {
+  if (margin < *minm) *minm = margin;
+  if (margin <= st->prm.tie_rel) {
+    (*ties)++;
+    st->tie_mn[(size_t)m * st->N + n]++;
+  }
 }
 
 static int validate(const orc_problem* pb) {
@@ -317,8 +348,11 @@ ORC_API orc_state* orc_state_create(const orc_problem* pb, const orc_params* prm
   st->part_delta = (double*)malloc(sizeof(double) * N);
   st->part_ties = (int64_t*)malloc(sizeof(int64_t) * N);
   st->part_margin = (double*)malloc(sizeof(double) * N);
-  st->churn_sel = (int*)calloc((size_t)M * N, sizeof(int));
-  st->churn_A = (int*)calloc(K, sizeof(int));
+  st->tie_mn = (int32_t*)calloc((size_t)M * N, sizeof(int32_t));
+  st->tie_user = (int32_t*)calloc(K, sizeof(int32_t));
+  st->part_sicv = (double*)calloc(N, sizeof(double));
+  st->part_moved = (int*)calloc(N, sizeof(int));
+  st->part_dres = (double*)calloc(N, sizeof(double));
   st->min_margin = INFINITY;
   st->first_tie = -1;
   cold_start(st);
@@ -333,17 +367,13 @@ ORC_API void orc_state_destroy(orc_state* st) {
   free(st->be); free(st->zs); free(st->xi); free(st->zeta); free(st->H);
   free(st->part_psum); free(st->part_pel); free(st->part_r); free(st->part_rh);
   free(st->part_delta); free(st->part_ties); free(st->part_margin);
-  free(st->churn_sel); free(st->churn_A);
+  free(st->tie_mn); free(st->tie_user); free(st->part_sicv);
+  free(st->part_moved);
+  free(st->part_dres);
   free(st);
 }
 
 ORC_API void orc_state_set_E(orc_state* st, double E) { st->E = E; }
-
-/* Start of a Dinkelbach step: the churn counters restart. */
-ORC_API void orc_state_reset_churn(orc_state* st) {
-  memset(st->churn_sel, 0, sizeof(int) * (size_t)st->M * st->N);
-  memset(st->churn_A, 0, sizeof(int) * st->K);
-}
 
 /* Alg. 1 initialisation: alpha = 1, beta = 0 (high-SIR approximation). */
 ORC_API void orc_state_reset_scale(orc_state* st) {
@@ -371,9 +401,21 @@ typedef struct {
   double cg[MAXL];   /* c * Gamma_{m,n,user}: price of interference on this user */
 } mview;
 
-/* ICI and per-RRH evaluation on subcarrier n; optionally refits SCALE. */
+/* Relative C14 margin of users a, b on (m,n) from u = (sigma + ICI)/Gamma:
+ * with s the user of larger raw gain (ties to the lower index) and w the
+ * other, Omega/nu = (u_s - u_w)/(u_s + u_w) (the SIC margin of
+ * orc_sic_margin divided through by Gamma_s Gamma_w). */
+static double pair_margin(double ga, double ua, int ka, double gb, double ub, int kb) {
+  const int a_strong = ga > gb || (ga == gb && ka < kb);
+  const double us = a_strong ? ua : ub, uw = a_strong ? ub : ua;
+  return (us - uw) / (us + uw);
+}
+
+/* ICI and per-RRH evaluation on subcarrier n; optionally refits SCALE.
+ * With ties != NULL the decoding-order margins are recorded as near-ties of
+ * their (m,n).  *sicv receives the C14 violation of the state's pairs. */
 static void eval_subcarrier(orc_state* st, int n, int refit, double* ici, mview* vw,
-                            int64_t* ties, double* minm) {
+                            int64_t* ties, double* minm, double* sicv) {
   const int M = st->M, K = st->K, L = st->L;
   const double sg = st->sigma;
   double Ptot[64];
@@ -412,8 +454,9 @@ static void eval_subcarrier(orc_state* st, int n, int refit, double* ici, mview*
         --j;
       }
     }
-    for (int q = 0; q + 1 < v->cnt; ++q)
-      note_margin((v->gt[q] - v->gt[q + 1]) / v->gt[q], st->prm.tie_rel, ties, minm);
+    if (ties)
+      for (int q = 0; q + 1 < v->cnt; ++q)
+        note_mn(st, m, n, (v->gt[q] - v->gt[q + 1]) / v->gt[q], ties, minm);
     v->pre[0] = 0.0;
     for (int q = 0; q < v->cnt; ++q) v->pre[q + 1] = v->pre[q] + st->p[SLOT(st, m, n, v->slot[q])];
     for (int q = 0; q < v->cnt; ++q) {
@@ -430,6 +473,21 @@ static void eval_subcarrier(orc_state* st, int n, int refit, double* ici, mview*
       v->cg[q] = v->c[q] * g;
     }
   }
+  /* C14 at the state: every co-scheduled pair's margin above SIC_TOL */
+  double viol = 0.0;
+  for (int m = 0; m < M; ++m) {
+    const mview* v = &vw[m];
+    for (int a = 0; a < v->cnt; ++a)
+      for (int b = a + 1; b < v->cnt; ++b) {
+        const int ka = v->user[a], kb = v->user[b];
+        const double ga = st->G[IDX3(st, m, n, ka)], gb = st->G[IDX3(st, m, n, kb)];
+        const double om = pair_margin(ga, (sg + ici[(size_t)m * K + ka]) / ga, ka, gb,
+                                      (sg + ici[(size_t)m * K + kb]) / gb, kb);
+        if (ties) note_mn(st, m, n, fabs(om - SIC_TOL), ties, minm);
+        if (om > SIC_TOL) viol += om - SIC_TOL;
+      }
+  }
+  *sicv = viol;
 }
 
 /* Per-subcarrier part of one dual sweep (Alg. 1 inner loop body). */
@@ -440,7 +498,7 @@ static void sweep_subcarrier(orc_state* st, int n, double delta_v, int refit) {
   double minm = INFINITY;
   double* ici = (double*)malloc(sizeof(double) * (size_t)M * K);
   mview* vw = (mview*)malloc(sizeof(mview) * M);
-  eval_subcarrier(st, n, refit, ici, vw, &ties, &minm);
+  eval_subcarrier(st, n, refit, ici, vw, &ties, &minm, &st->part_sicv[n]);
 
   /* Partial sums at the state: power per RRH, rates per user. */
   for (int m = 0; m < M; ++m) {
@@ -481,6 +539,7 @@ static void sweep_subcarrier(orc_state* st, int n, double delta_v, int refit) {
    * the multiplier of each co-scheduled pair adds zeta~ dOmega/dp_j to the
    * price of RRH j on n; then the pair's subgradient step. */
   double zs_new[64][MAXL][MAXL];
+  double dres = 0.0;
   for (int m = 0; m < M; ++m) {
     const mview* v = &vw[m];
     for (int a = 0; a < v->cnt; ++a)
@@ -505,6 +564,7 @@ static void sweep_subcarrier(orc_state* st, int n, double delta_v, int refit) {
           psic[j] += z * dj;
         }
         const double zn = fmax(z + delta_v * om, 0.0);
+        dres = fmax(dres, fabs(zn - z) / delta_v);
         zs_new[m][sa][sb] = zn;
         zs_new[m][sb][sa] = zn;
       }
@@ -538,7 +598,7 @@ static void sweep_subcarrier(orc_state* st, int n, double delta_v, int refit) {
         int pos = 0;
         for (int t = 0; t < v->cnt; ++t) {
           if (v->gt[t] > gk || (v->gt[t] == gk && v->user[t] < k)) pos++;
-          note_margin(fabs(v->gt[t] - gk) / fmax(v->gt[t], gk), tr, &ties, &minm);
+          note_mn(st, m, n, fabs(v->gt[t] - gk) / fmax(v->gt[t], gk), &ties, &minm);
         }
         Sb = v->pre[pos];
         for (int t = pos; t < v->cnt; ++t) pintra += v->cg[t];
@@ -572,43 +632,54 @@ static void sweep_subcarrier(orc_state* st, int n, double delta_v, int refit) {
     }
   }
 
-  /* Selection and closed-form powers for the new selection. */
+  int moved = 0;
+  /* Selection and closed-form powers for the new selection: RRH m's
+   * candidates in order of H (ties to the lower user), each taken only if
+   * every pair it forms with the users taken before it meets C14 (margin
+   * <= 0 at the state's interference), until l are taken. */
   double dmax = 0.0;
   for (int m = 0; m < M; ++m) {
     const mview* v = &vw[m];
-    int pick[MAXL], np;
-    const int lim = st->prm.churn_limit;
-    const int frozen = lim > 0 && st->churn_sel[(size_t)m * st->N + n] >= lim;
-    top_by_key(cand_H(m), cand_k(m), ncand[m], L, pick, &np);
-    if (!frozen && ncand[m] > L) {
-      /* margin between the l-th and the (l+1)-th candidate */
-      int ord[MAXL + 1], no;
-      top_by_key(cand_H(m), cand_k(m), ncand[m], L + 1, ord, &no);
-      const double hl = cand_H(m)[ord[L - 1]], hn = cand_H(m)[ord[L]];
-      note_margin((hl - hn) / hl, tr, &ties, &minm);
+    int chosen[MAXL], np = 0, last = -1;
+    int* ord = (int*)malloc(sizeof(int) * (ncand[m] > 0 ? ncand[m] : 1));
+    int no = 0;
+    top_by_key(cand_H(m), cand_k(m), ncand[m], ncand[m], ord, &no);
+    for (int e = 0; e < no && np < L; ++e) {
+      const int k = cand_k(m)[ord[e]];
+      const double gk = st->G[IDX3(st, m, n, k)], uk = (sg + ici[(size_t)m * K + k]) / gk;
+      int ok = 1;
+      for (int a = 0; a < np; ++a) {
+        const int j = chosen[a];
+        const double gj = st->G[IDX3(st, m, n, j)], uj = (sg + ici[(size_t)m * K + j]) / gj;
+        const double om = pair_margin(gk, uk, k, gj, uj, j);
+        note_mn(st, m, n, fabs(om), &ties, &minm);
+        if (om > 0.0) ok = 0;
+      }
+      if (ok) chosen[np++] = k;
+      last = e;
     }
-    if (nbdry[m] > 0 && ncand[m] <= L + nbdry[m]) ties += nbdry[m];
+    /* the order of the candidates considered, and the first one not
+     * considered, decide the selection */
+    for (int e = 0; e <= last && e + 1 < no; ++e) {
+      const double h0 = cand_H(m)[ord[e]], h1 = cand_H(m)[ord[e + 1]];
+      note_mn(st, m, n, (h0 - h1) / h0, &ties, &minm);
+    }
+    free(ord);
+    if (nbdry[m] > 0 && ncand[m] <= L + nbdry[m]) {
+      ties += nbdry[m];
+      st->tie_mn[(size_t)m * st->N + n] += nbdry[m];
+    }
+
+    int same = np == v->cnt;
+    for (int s = 0; s < np && same; ++s) {
+      int found = 0;
+      for (int t = 0; t < v->cnt; ++t) found |= v->user[t] == chosen[s];
+      same = found;
+    }
+    if (!same) moved = 1;
 
     int new_user[MAXL];
     double new_p[MAXL], new_al[MAXL], new_be[MAXL];
-    int chosen[MAXL];
-    if (frozen) {
-      /* churn cap reached: keep the incumbents still associated with m */
-      np = 0;
-      for (int t = 0; t < v->cnt; ++t)
-        if (st->A[v->user[t]] == m) chosen[np++] = v->user[t];
-    } else {
-      for (int s = 0; s < np; ++s) chosen[s] = cand_k(m)[pick[s]];
-      /* count a change of the selected set */
-      int same = (np == v->cnt);
-      for (int s = 0; s < np && same; ++s) {
-        int found = 0;
-        for (int t = 0; t < v->cnt; ++t)
-          if (v->user[t] == chosen[s]) found = 1;
-        same = found;
-      }
-      if (!same) st->churn_sel[(size_t)m * st->N + n]++;
-    }
     for (int s = 0; s < L; ++s) new_user[s] = -1;
     for (int s = 0; s < np; ++s) {
       const int k = chosen[s];
@@ -629,7 +700,7 @@ static void sweep_subcarrier(orc_state* st, int n, double delta_v, int refit) {
       const double num = wmu * alph / LN2 + p_old * pminus;
       double pn = (cp > 0.0) ? fmin(fmax(num / cp, 0.0), st->pmask[m]) : st->pmask[m];
       const double floor_p = POWER_FLOOR_REL * st->pmask[m];
-      if (pn > 0.0) note_margin(fabs(pn - floor_p) / floor_p, tr, &ties, &minm);
+      if (pn > 0.0) note_mn(st, m, n, fabs(pn - floor_p) / floor_p, &ties, &minm);
       if (pn < floor_p) pn = 0.0;
       new_user[s] = k;
       new_p[s] = pn;
@@ -673,6 +744,8 @@ static void sweep_subcarrier(orc_state* st, int n, double delta_v, int refit) {
     }
   }
   st->part_delta[n] = dmax;
+  st->part_moved[n] = moved;
+  st->part_dres[n] = dres;
   st->part_ties[n] = ties;
   st->part_margin[n] = minm;
 #undef cand_H
@@ -686,6 +759,53 @@ static void sweep_subcarrier(orc_state* st, int n, double delta_v, int refit) {
 
 /* ------------------------------------------------------------ the sweep */
 
+/* Totals of a state from its per-subcarrier parts, each summed serially in
+ * increasing n: the weighted elastic sum rate R (Sec. II-A), the power P of
+ * the power model, and the violations of C13 (sum over streaming users of
+ * (1 - QOS_TOL) - r_k/Psi_k where positive), C12 (sum over RRHs of
+ * sum_p/pmax - (1 + BUDGET_TOL) where positive) and C14 (sum of the pair
+ * margins above SIC_TOL).  A threshold decision within tie_rel is a
+ * near-tie. */
+static int64_t state_totals(orc_state* st, const double* part_r, const double* part_pel,
+                            const double* part_psum, const double* part_sicv, double* user_rate) {
+  const int M = st->M, N = st->N, K = st->K;
+  int64_t ties = 0;
+  double Rs = 0.0, Ps = st->pstatic, vq = 0.0, vp = 0.0, vs = 0.0;
+  for (int k = 0; k < K; ++k) {
+    double r = 0.0;
+    for (int n = 0; n < N; ++n) r += part_r[(size_t)n * K + k];
+    if (user_rate) user_rate[k] = r;
+    if (st->elastic[k]) {
+      Rs += r;
+    } else {
+      const double x = r / st->psi[k];
+      if (fabs(x - (1.0 - QOS_TOL)) <= st->prm.tie_rel) {
+        ties++;
+        st->tie_user[k]++;
+      }
+      if (x < 1.0 - QOS_TOL) vq += (1.0 - QOS_TOL) - x;
+    }
+  }
+  for (int m = 0; m < M; ++m) {
+    double pe = 0.0, ps = 0.0;
+    for (int n = 0; n < N; ++n) {
+      pe += part_pel[(size_t)n * M + m];
+      ps += part_psum[(size_t)n * M + m];
+    }
+    Ps += st->eta[m] * pe;
+    const double y = ps / st->pmax[m];
+    if (fabs(y - (1.0 + BUDGET_TOL)) <= st->prm.tie_rel) ties++;
+    if (y > 1.0 + BUDGET_TOL) vp += y - (1.0 + BUDGET_TOL);
+  }
+  for (int n = 0; n < N; ++n) vs += part_sicv[n];
+  st->ev_R = Rs;
+  st->ev_P = Ps;
+  st->ev_Vq = vq;
+  st->ev_Vp = vp;
+  st->ev_Vs = vs;
+  return ties;
+}
+
 ORC_API double orc_state_sweep(orc_state* st, int32_t v, int32_t refit) {
   const int M = st->M, N = st->N, K = st->K, L = st->L;
   const double delta_v = st->prm.step0 / sqrt(1.0 + (double)v);
@@ -696,26 +816,35 @@ ORC_API double orc_state_sweep(orc_state* st, int32_t v, int32_t refit) {
   /* Sums over subcarriers, serially in increasing n. */
   double delta = 0.0;
   int64_t ties = 0;
+  st->moved = 0;
   for (int n = 0; n < N; ++n) {
+    st->moved |= st->part_moved[n];
     delta = fmax(delta, st->part_delta[n]);
+    delta = fmax(delta, st->part_dres[n]);
     ties += st->part_ties[n];
     if (st->part_margin[n] < st->min_margin) st->min_margin = st->part_margin[n];
   }
+  /* The state this sweep read: sum rate R, power P, constraint violations. */
+  ties += state_totals(st, st->part_r, st->part_pel, st->part_psum, st->part_sicv, NULL);
   /* C12 subgradient: xi'_m <- [xi'_m + delta (sum p - pmax)/pmax * N l/(ln2 pmax)]^+ */
   for (int m = 0; m < M; ++m) {
     double ps = 0.0;
     for (int n = 0; n < N; ++n) ps += st->part_psum[(size_t)n * M + m];
     const double scale = (double)N * L / (LN2 * st->pmax[m]);
-    st->xi[m] = fmax(st->xi[m] + delta_v * scale * (ps - st->pmax[m]) / st->pmax[m], 0.0);
+    const double xn = fmax(st->xi[m] + delta_v * scale * (ps - st->pmax[m]) / st->pmax[m], 0.0);
+    delta = fmax(delta, fabs(xn - st->xi[m]) / (delta_v * scale));
+    st->xi[m] = xn;
   }
   /* C13 subgradient on the SCALE surrogate rate of each streaming user; the
-   * relative violation (Psi - r_hat)/Psi is clipped to [-1, 1]. */
+   * relative violation (Psi - r_hat)/Psi is clipped to [-qos_down, 1]. */
   for (int k = 0; k < K; ++k) {
     if (st->elastic[k]) continue;
     double rh = 0.0;
     for (int n = 0; n < N; ++n) rh += st->part_rh[(size_t)n * K + k];
-    const double viol = fmin(fmax((st->psi[k] - rh) / st->psi[k], -1.0), 1.0);
-    st->zeta[k] = fmax(st->zeta[k] + delta_v * viol, 0.0);
+    const double viol = fmin(fmax((st->psi[k] - rh) / st->psi[k], -st->prm.qos_down), 1.0);
+    const double zn = fmax(st->zeta[k] + delta_v * viol, 0.0);
+    delta = fmax(delta, fabs(zn - st->zeta[k]) / delta_v);
+    st->zeta[k] = zn;
   }
   /* RRH association from the summed per-triple Lagrangian maxima. */
   for (int k = 0; k < K; ++k) {
@@ -733,18 +862,19 @@ ORC_API double orc_state_sweep(orc_state* st, int32_t v, int32_t refit) {
       }
     }
     const int before = st->A[k];
-    if (st->prm.churn_limit > 0 && st->churn_A[k] >= st->prm.churn_limit) continue;
     if (best > 0.0) {
-      if (M > 1 && second > 0.0) note_margin((best - second) / best, st->prm.tie_rel, &ties, &st->min_margin);
+      if (M > 1 && second > 0.0) {
+        const int64_t t0 = ties;
+        note_margin((best - second) / best, st->prm.tie_rel, &ties, &st->min_margin);
+        if (ties > t0) st->tie_user[k]++;
+      }
       st->A[k] = bm;
     } else if (st->elastic[k]) {
       st->A[k] = -1;
     }
-    if (st->A[k] != before) {
-      st->assoc_changed++;
-      st->churn_A[k]++;
-    }
+    if (st->A[k] != before) st->assoc_changed++;
   }
+  if (st->assoc_changed) st->moved = 1;
   if (ties > 0) {
     if (st->first_tie < 0) st->first_tie = st->sweeps_done;
     st->ties += ties;
@@ -760,47 +890,40 @@ ORC_API void orc_state_eval(orc_state* st, double* R, double* P, double* R_hat,
   double* rk = (double*)calloc((size_t)N * K, sizeof(double));
   double* rhk = (double*)calloc((size_t)N * K, sizeof(double));
   double* pe = (double*)calloc((size_t)N * M, sizeof(double));
+  double* ps = (double*)calloc((size_t)N * M, sizeof(double));
+  double* sv = (double*)calloc((size_t)N, sizeof(double));
 #pragma omp parallel for schedule(dynamic, 1)
   for (int n = 0; n < N; ++n) {
-    int64_t t = 0;
-    double mm = INFINITY;
     double* ici = (double*)malloc(sizeof(double) * (size_t)M * K);
     mview* vw = (mview*)malloc(sizeof(mview) * M);
-    eval_subcarrier(st, n, 0, ici, vw, &t, &mm);
+    eval_subcarrier(st, n, 0, ici, vw, NULL, NULL, &sv[n]);
     for (int m = 0; m < M; ++m)
       for (int q = 0; q < vw[m].cnt; ++q) {
         const int k = vw[m].user[q];
+        const double pq = st->p[SLOT(st, m, n, vw[m].slot[q])];
         rk[(size_t)n * K + k] += st->w[(size_t)m * K + k] * vw[m].r[q];
         rhk[(size_t)n * K + k] += st->w[(size_t)m * K + k] * vw[m].rh[q];
-        if (st->elastic[k]) pe[(size_t)n * M + m] += st->p[SLOT(st, m, n, vw[m].slot[q])];
+        ps[(size_t)n * M + m] += pq;
+        if (st->elastic[k]) pe[(size_t)n * M + m] += pq;
       }
     free(ici);
     free(vw);
   }
-  double Rs = 0.0, Rh = 0.0, Ps = st->pstatic;
+  st->ties += state_totals(st, rk, pe, ps, sv, user_rate);
+  double Rh = 0.0;
   for (int k = 0; k < K; ++k) {
-    double r = 0.0, h = 0.0;
-    for (int n = 0; n < N; ++n) {
-      r += rk[(size_t)n * K + k];
-      h += rhk[(size_t)n * K + k];
-    }
-    if (user_rate) user_rate[k] = r;
-    if (st->elastic[k]) {
-      Rs += r;
-      Rh += h;
-    }
+    double h = 0.0;
+    for (int n = 0; n < N; ++n) h += rhk[(size_t)n * K + k];
+    if (st->elastic[k]) Rh += h;
   }
-  for (int m = 0; m < M; ++m) {
-    double s = 0.0;
-    for (int n = 0; n < N; ++n) s += pe[(size_t)n * M + m];
-    Ps += st->eta[m] * s;
-  }
-  *R = Rs;
-  *P = Ps;
+  *R = st->ev_R;
+  *P = st->ev_P;
   if (R_hat) *R_hat = Rh;
   free(rk);
   free(rhk);
   free(pe);
+  free(ps);
+  free(sv);
 }
 
 /* Final state in the output layout: slots in decoding order. */
@@ -809,12 +932,15 @@ ORC_API void orc_state_export(orc_state* st, orc_result* res) {
   const int NP = L * (L - 1) / 2;
   double* ici = (double*)malloc(sizeof(double) * (size_t)M * K);
   mview* vw = (mview*)malloc(sizeof(mview) * M);
+  if (res->rrh_of_user)
+    for (int k = 0; k < K; ++k) res->rrh_of_user[k] = -1;
   for (int n = 0; n < N; ++n) {
-    int64_t t = 0;
-    double mm = INFINITY;
-    eval_subcarrier(st, n, 0, ici, vw, &t, &mm);
+    double sv;
+    eval_subcarrier(st, n, 0, ici, vw, NULL, NULL, &sv);
     for (int m = 0; m < M; ++m) {
       const mview* v = &vw[m];
+      if (res->rrh_of_user)
+        for (int q = 0; q < v->cnt; ++q) res->rrh_of_user[v->user[q]] = m;
       for (int q = 0; q < L; ++q) {
         const size_t o = SLOT(st, m, n, q);
         if (res->sel) res->sel[o] = (q < v->cnt) ? v->user[q] : -1;
@@ -833,8 +959,10 @@ ORC_API void orc_state_export(orc_state* st, orc_result* res) {
   }
   free(ici);
   free(vw);
-  if (res->rrh_of_user)
-    for (int k = 0; k < K; ++k) res->rrh_of_user[k] = st->A[k];
+  if (res->tie_mn)
+    for (size_t i = 0; i < (size_t)M * N; ++i) res->tie_mn[i] = st->tie_mn[i];
+  if (res->tie_user)
+    for (int k = 0; k < K; ++k) res->tie_user[k] = st->tie_user[k];
   if (res->xi)
     for (int m = 0; m < M; ++m) res->xi[m] = st->xi[m];
   if (res->zeta)
@@ -877,7 +1005,110 @@ ORC_API void orc_state_set_powers(orc_state* st, const double* power) {
 
 /* ---------------------------------------------------------- full solve */
 
-/* Dinkelbach outer loop (Sec. IV) around the dual sweeps of Alg. 1. */
+/* Primal state of an iterate: association, selection, powers, SCALE
+ * coefficients and the C14 multipliers that live with the slot pairs.  The
+ * multipliers xi' and zeta' are not part of it: they continue from the last
+ * sweep. */
+typedef struct {
+  int* A;
+  int* sel;
+  double *p, *al, *be, *zs;
+} orc_snap;
+
+static void snap_alloc(const orc_state* st, orc_snap* s) {
+  const size_t ns = (size_t)st->M * st->N * st->L;
+  s->A = (int*)malloc(sizeof(int) * st->K);
+  s->sel = (int*)malloc(sizeof(int) * ns);
+  s->p = (double*)malloc(sizeof(double) * ns);
+  s->al = (double*)malloc(sizeof(double) * ns);
+  s->be = (double*)malloc(sizeof(double) * ns);
+  s->zs = (double*)malloc(sizeof(double) * ns * st->L);
+}
+
+static void snap_free(orc_snap* s) {
+  free(s->A);
+  free(s->sel);
+  free(s->p);
+  free(s->al);
+  free(s->be);
+  free(s->zs);
+}
+
+static void snap_copy(const orc_state* st, int* A, int* sel, double* p, double* al, double* be,
+                      double* zs, const int* A0, const int* sel0, const double* p0,
+                      const double* al0, const double* be0, const double* zs0) {
+  const size_t ns = (size_t)st->M * st->N * st->L;
+  memcpy(A, A0, sizeof(int) * st->K);
+  memcpy(sel, sel0, sizeof(int) * ns);
+  memcpy(p, p0, sizeof(double) * ns);
+  memcpy(al, al0, sizeof(double) * ns);
+  memcpy(be, be0, sizeof(double) * ns);
+  memcpy(zs, zs0, sizeof(double) * ns * st->L);
+}
+
+static void snap_take(const orc_state* st, orc_snap* s) {
+  snap_copy(st, s->A, s->sel, s->p, s->al, s->be, s->zs, st->A, st->sel, st->p, st->al, st->be,
+            st->zs);
+}
+
+static void snap_put(orc_state* st, const orc_snap* s) {
+  snap_copy(st, st->A, st->sel, st->p, st->al, st->be, st->zs, s->A, s->sel, s->p, s->al, s->be,
+            s->zs);
+}
+
+static void snap_assign(const orc_state* st, orc_snap* d, const orc_snap* s) {
+  snap_copy(st, d->A, d->sel, d->p, d->al, d->be, d->zs, s->A, s->sel, s->p, s->al, s->be, s->zs);
+}
+
+/* Relative change of the violation that separates two iterates in the
+ * ranking below. */
+#define VIOL_REL 1e-6
+
+/* Violations Va against Vb: -1 when Va is lower by more than VIOL_REL
+ * (relative), 1 when higher, 0 otherwise (zero only equals zero). */
+static int cmp_viol(double Va, double Vb, double tie_rel, int64_t* ties, double* minm) {
+  if (Va == 0.0 && Vb == 0.0) return 0;
+  if (Va == 0.0) return -1;
+  if (Vb == 0.0) return 1;
+  const double lo = Vb * (1.0 - VIOL_REL), hi = Vb * (1.0 + VIOL_REL);
+  note_margin(fmin(fabs(Va - lo), fabs(Va - hi)) / Vb, tie_rel, ties, minm);
+  if (Va < lo) return -1;
+  if (Va > hi) return 1;
+  return 0;
+}
+
+/* Ranking of the iterate a just evaluated against the best iterate b of the
+ * Dinkelbach step: less C12/C13 violation V first, then less C14 violation
+ * V2 (feasible = both zero), then the larger Dinkelbach objective
+ * f = R - E P.  *replace: a becomes the best; *progress: it is better by more
+ * than the violation band or, at equal violation, by more than rel times the
+ * best's rate R_b (rel = the Dinkelbach tolerance: smaller gains are below
+ * what the outer loop resolves).  moved: a and b differ in a selected set or
+ * an association (otherwise choosing between them by f is no discrete
+ * decision). */
+static void rank_iterate(double Va, double Va2, double fa, double Vb, double Vb2, double fb,
+                         double Rb, double rel, int moved, double tie_rel, int64_t* ties,
+                         double* minm, int* replace, int* progress) {
+  int c = cmp_viol(Va, Vb, tie_rel, ties, minm);
+  if (c == 0) c = cmp_viol(Va2, Vb2, tie_rel, ties, minm);
+  if (c != 0) {
+    *replace = *progress = c < 0;
+    return;
+  }
+  const double thr = rel * fabs(Rb);
+  if (Rb != 0.0) {
+    note_margin(fabs(fa - fb - thr) / fabs(Rb), tie_rel, ties, minm);
+    if (moved) note_margin(fabs(fa - fb) / fabs(Rb), tie_rel, ties, minm);
+  }
+  *replace = fa > fb;
+  *progress = fa - fb > thr;
+}
+
+/* Dinkelbach outer loop (Sec. III-IV) around the dual sweeps of Alg. 1.
+ * Step i runs dual sweeps at E^i from the previous step's returned state and
+ * returns the best state it visited (see rank_iterate()); F_i = R - E^i P at
+ * that state; the solve stops when that state is feasible and
+ * F_i <= tol_dinkelbach R, otherwise E^{i+1} = R/P of that state. */
 ORC_API int orc_solve(const orc_problem* pb, const orc_params* prm, const orc_warm* warm,
                       orc_result* res) {
   const int rc = validate(pb);
@@ -889,31 +1120,61 @@ ORC_API int orc_solve(const orc_problem* pb, const orc_params* prm, const orc_wa
   double R = 0.0, P = st->pstatic;
   int i = 0, total = 0;
   double* rate = (double*)malloc(sizeof(double) * K);
+  orc_snap cur, best;
+  snap_alloc(st, &cur);
+  snap_alloc(st, &best);
   st->E = 0.0; /* E^0 = 0 */
-  /* A warm initial allocation is the Dinkelbach iteration's p^0 itself: its
-   * first step runs no dual sweeps, so E^1 = R(p^0)/P(p^0). */
-  int skip_sweeps = (warm && warm->p0) ? 1 : 0;
+  /* A warm initial allocation is Dinkelbach's p^0 when it is feasible: a
+   * first step without sweeps evaluates it, E^1 = R(p^0)/P(p^0).  Otherwise
+   * E^1 = 0 and the sweeps start from it. */
+  int eval_only = (warm && warm->p0) ? 1 : 0;
   for (;;) {
-    orc_state_reset_scale(st);
-    orc_state_reset_churn(st);
     int v = 0;
-    for (; !skip_sweeps;) {
-      const int refit = prm->refit_period > 0 && (v % prm->refit_period) == 0;
-      const double d = orc_state_sweep(st, v, refit);
-      ++v;
-      ++total;
-      if (isnan(d)) {
-        flags |= ORC_NONFINITE;
-        break;
+    if (eval_only) {
+      orc_state_eval(st, &R, &P, NULL, rate);
+    } else {
+      orc_state_reset_scale(st);
+      int have_best = 0, stall = 0, moved = 0;
+      double bV = 0.0, bV2 = 0.0, bf = 0.0, bR = 0.0;
+      for (;;) {
+        const int refit = prm->refit_period > 0 && (v % prm->refit_period) == 0;
+        snap_take(st, &cur);
+        const double d = orc_state_sweep(st, v, refit);
+        ++v;
+        ++total;
+        if (isnan(d)) {
+          flags |= ORC_NONFINITE;
+          break;
+        }
+        /* the state read by this sweep against the best so far ("moved":
+         * a sweep since the best changed a selected set or an association) */
+        const double V = st->ev_Vq + st->ev_Vp, V2 = st->ev_Vs;
+        const double f = st->ev_R - st->E * st->ev_P;
+        int replace = 1, progress = 1;
+        if (have_best)
+          rank_iterate(V, V2, f, bV, bV2, bf, bR, prm->tol_dinkelbach, moved, prm->tie_rel,
+                       &st->ties, &st->min_margin, &replace, &progress);
+        if (replace) {
+          snap_assign(st, &best, &cur);
+          have_best = 1;
+          bV = V;
+          bV2 = V2;
+          bf = f;
+          bR = st->ev_R;
+          moved = 0;
+        }
+        stall = progress ? 0 : stall + 1;
+        moved |= st->moved;
+        if (v >= prm->sweeps_per_dinkelbach) break;
+        if (!prm->fixed_count) {
+          if (fabs(d - prm->tol_dual) <= 1e-6 * prm->tol_dual) st->ties++;
+          if (d < prm->tol_dual) break;
+          if (prm->stall_sweeps > 0 && stall >= prm->stall_sweeps && bV == 0.0 && bV2 == 0.0) break;
+        }
       }
-      if (v >= prm->sweeps_per_dinkelbach) break;
-      if (!prm->fixed_count) {
-        if (fabs(d - prm->tol_dual) <= 1e-6 * prm->tol_dual) st->ties++;
-        if (d < prm->tol_dual) break;
-      }
+      if (have_best) snap_put(st, &best);
+      orc_state_eval(st, &R, &P, NULL, rate);
     }
-    skip_sweeps = 0;
-    orc_state_eval(st, &R, &P, NULL, rate);
     const double F = R - st->E * P;
     if (res->trace_E) res->trace_E[i] = st->E;
     if (res->trace_F) res->trace_F[i] = F;
@@ -922,24 +1183,44 @@ ORC_API int orc_solve(const orc_problem* pb, const orc_params* prm, const orc_wa
     if (res->trace_sweeps) res->trace_sweeps[i] = v;
     ++i;
     if (flags & ORC_NONFINITE) break;
+    if (eval_only) {
+      eval_only = 0;
+      const int feasible = st->ev_Vq == 0.0 && st->ev_Vp == 0.0 && st->ev_Vs == 0.0;
+      if (i >= prm->max_dinkelbach) {
+        flags |= ORC_NOT_CONVERGED;
+        break;
+      }
+      st->E = feasible ? R / P : 0.0;
+      continue;
+    }
+    /* Dinkelbach's test applies to feasible iterates; an infeasible step is
+     * followed by another (the multipliers keep moving towards feasibility) */
+    const int feasible = st->ev_Vq == 0.0 && st->ev_Vp == 0.0 && st->ev_Vs == 0.0;
     if (fabs(F - prm->tol_dinkelbach * R) <= 1e-6 * prm->tol_dinkelbach * fabs(R)) st->ties++;
-    if (F <= prm->tol_dinkelbach * R) break;
+    if (feasible && F <= prm->tol_dinkelbach * R) break;
     if (i >= prm->max_dinkelbach) {
       flags |= ORC_NOT_CONVERGED;
       break;
     }
     st->E = R / P; /* E^{i+1} = R(p^i)/P(p^i) */
   }
+  snap_free(&cur);
+  snap_free(&best);
   orc_state_export(st, res);
+  if (st->ev_Vq > 0.0) flags |= ORC_QOS_INFEASIBLE;
+  if (st->ev_Vp > 0.0) flags |= ORC_BUDGET_INFEASIBLE;
+  if (st->ev_Vs > 0.0) flags |= ORC_SIC_INFEASIBLE;
   for (int k = 0; k < K; ++k) {
     if (res->user_rate) res->user_rate[k] = rate[k];
-    if (!st->elastic[k] && rate[k] < st->psi[k] * (1.0 - 1e-6)) flags |= ORC_QOS_INFEASIBLE;
     if (!isfinite(rate[k])) flags |= ORC_NONFINITE;
   }
   if (st->ties > 0) flags |= ORC_NEAR_TIE;
   res->ee = (P > 0.0) ? R / P : 0.0;
   res->rate_sum = R;
   res->power_sum = P;
+  res->viol_qos = st->ev_Vq;
+  res->viol_budget = st->ev_Vp;
+  res->viol_sic = st->ev_Vs;
   res->dinkelbach_iters = i;
   res->sweeps = total;
   res->status_flags = flags;

@@ -51,11 +51,15 @@ typedef struct {
   int32_t refit_period;          /* refit alpha/beta every this many sweeps (<=0: never) */
   int32_t fixed_count;           /* 1: exactly sweeps_per_dinkelbach sweeps */
   double tol_dinkelbach;         /* stop when F_i <= tol * R_i */
-  double tol_dual;               /* stop dual loop when max|dp|/pmask < tol */
+  double tol_dual;               /* stop the dual loop when max|dp|/pmask and every projected
+                                    multiplier subgradient are below tol */
   double step0;                  /* subgradient step delta_v = step0/sqrt(1+v) */
   double tie_rel;                /* relative margin below which a decision is a near-tie */
-  int32_t churn_limit;           /* selection/association changes allowed per
-                                    Dinkelbach step before freezing (<=0: no cap) */
+  int32_t stall_sweeps;          /* end the dual loop after this many sweeps without a
+                                    better state once the best is feasible (<=0: never;
+                                    not with fixed_count) */
+  double qos_down;               /* lower clip of the relative C13 violation in the
+                                    zeta' step (the upper clip is 1) */
 } orc_params;
 
 typedef struct {
@@ -65,21 +69,28 @@ typedef struct {
 } orc_warm;
 
 enum {
-  ORC_NOT_CONVERGED = 1u,
-  ORC_QOS_INFEASIBLE = 2u,
-  ORC_NEAR_TIE = 4u,
-  ORC_NONFINITE = 8u
+  ORC_NOT_CONVERGED = 1u,      /* Dinkelbach stopped at max_dinkelbach */
+  ORC_QOS_INFEASIBLE = 2u,     /* C13: a streaming user below (1 - 1e-6) Psi */
+  ORC_NEAR_TIE = 4u,           /* some decision had a relative margin <= tie_rel */
+  ORC_NONFINITE = 8u,
+  ORC_SIC_INFEASIBLE = 16u,    /* C14: a co-scheduled pair with margin above 1e-9 */
+  ORC_BUDGET_INFEASIBLE = 64u  /* C12: an RRH above (1 + 1e-6) of its budget */
 };
 
 typedef struct {
   int32_t* sel;         /* [M][N][l] users in SIC decoding order, -1 empty */
   double* slot_power;   /* [M][N][l] */
-  int32_t* rrh_of_user; /* [K] association used by the final selection, -1 unserved */
+  int32_t* rrh_of_user; /* [K] RRH whose slots hold the user in sel, -1 unserved */
   double* xi;           /* [M] */
   double* zeta;         /* [K] (0 for elastic users) */
   double* zeta_sic;     /* [M][N][l(l-1)/2], pair (a,b) of decoding positions a<b */
   double* user_rate;    /* [K] r_k at exit */
+  int32_t* tie_mn;      /* [M][N] or NULL: near-tie decisions of each (m,n) over the solve
+                           (decoding order, insertion position, selection order, C14
+                           compatibility and margin, H > 0 boundary, power floor) */
+  int32_t* tie_user;    /* [K] or NULL: near-tie association and C13-threshold decisions */
   double ee, rate_sum, power_sum;
+  double viol_qos, viol_budget, viol_sic; /* violations of C13, C12, C14 at exit */
   int32_t dinkelbach_iters, sweeps;
   uint32_t status_flags;
   int64_t near_ties;
@@ -104,9 +115,10 @@ orc_state* orc_state_create(const orc_problem* prob, const orc_params* prm,
 void orc_state_destroy(orc_state* st);
 void orc_state_set_E(orc_state* st, double E);
 void orc_state_reset_scale(orc_state* st);
-void orc_state_reset_churn(orc_state* st);
-/* One Jacobi dual sweep at the current E; returns max|dp|/pmask, or +inf when
- * the sweep moved any user to another RRH. */
+/* One Jacobi dual sweep at the current E.  Returns the larger of max|dp|/pmask
+ * and the largest multiplier step divided by the sweep's step size (its
+ * scale factor included: the projected subgradient), or +inf when the sweep
+ * moved any user to another RRH. */
 double orc_state_sweep(orc_state* st, int32_t v, int32_t refit);
 /* Evaluate the current state: true sum rate R, power P, SCALE surrogate rate
  * R_hat (with the current alpha/beta), per-user rates. */
