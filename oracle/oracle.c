@@ -39,9 +39,13 @@
  *    dual loop also ends after stall_sweeps sweeps without a better state
  *    once the best is feasible; the multipliers xi' and zeta' continue from
  *    the last sweep;
- *  - a warm start's allocation is Dinkelbach's p^0 only when it is feasible
- *    (then E^1 = R(p^0)/P(p^0)); otherwise E^1 = 0 and it is the first
- *    step's starting state;
+ *  - a warm start's allocation is Dinkelbach's p^0: E^1 = R(p^0)/P(p^0)
+ *    whether or not it is feasible (F is strictly decreasing in E with its
+ *    root at the optimum, Theorem 1 and Lemma 1, so the iteration converges
+ *    from any E; from above the optimum F < 0 and E moves down), and it is
+ *    the first step's starting state;
+ *  - Dinkelbach's stop test is the root condition |F| <= tol R on a
+ *    feasible state (F >= 0 whenever E is at most the optimum);
  *  - all sweeps are Jacobi: every quantity of a sweep is read from the state
  *    the sweep starts from.
  */
@@ -1108,7 +1112,7 @@ static void rank_iterate(double Va, double Va2, double fa, double Vb, double Vb2
  * Step i runs dual sweeps at E^i from the previous step's returned state and
  * returns the best state it visited (see rank_iterate()); F_i = R - E^i P at
  * that state; the solve stops when that state is feasible and
- * F_i <= tol_dinkelbach R, otherwise E^{i+1} = R/P of that state. */
+ * |F_i| <= tol_dinkelbach R, otherwise E^{i+1} = R/P of that state. */
 ORC_API int orc_solve(const orc_problem* pb, const orc_params* prm, const orc_warm* warm,
                       orc_result* res) {
   const int rc = validate(pb);
@@ -1124,9 +1128,8 @@ ORC_API int orc_solve(const orc_problem* pb, const orc_params* prm, const orc_wa
   snap_alloc(st, &cur);
   snap_alloc(st, &best);
   st->E = 0.0; /* E^0 = 0 */
-  /* A warm initial allocation is Dinkelbach's p^0 when it is feasible: a
-   * first step without sweeps evaluates it, E^1 = R(p^0)/P(p^0).  Otherwise
-   * E^1 = 0 and the sweeps start from it. */
+  /* A warm initial allocation is Dinkelbach's p^0: a first step without
+   * sweeps evaluates it, E^1 = R(p^0)/P(p^0), and the sweeps start from it. */
   int eval_only = (warm && warm->p0) ? 1 : 0;
   for (;;) {
     int v = 0;
@@ -1185,19 +1188,18 @@ ORC_API int orc_solve(const orc_problem* pb, const orc_params* prm, const orc_wa
     if (flags & ORC_NONFINITE) break;
     if (eval_only) {
       eval_only = 0;
-      const int feasible = st->ev_Vq == 0.0 && st->ev_Vp == 0.0 && st->ev_Vs == 0.0;
       if (i >= prm->max_dinkelbach) {
         flags |= ORC_NOT_CONVERGED;
         break;
       }
-      st->E = feasible ? R / P : 0.0;
+      st->E = R / P;
       continue;
     }
     /* Dinkelbach's test applies to feasible iterates; an infeasible step is
      * followed by another (the multipliers keep moving towards feasibility) */
     const int feasible = st->ev_Vq == 0.0 && st->ev_Vp == 0.0 && st->ev_Vs == 0.0;
-    if (fabs(F - prm->tol_dinkelbach * R) <= 1e-6 * prm->tol_dinkelbach * fabs(R)) st->ties++;
-    if (feasible && F <= prm->tol_dinkelbach * R) break;
+    if (fabs(fabs(F) - prm->tol_dinkelbach * R) <= 1e-6 * prm->tol_dinkelbach * fabs(R)) st->ties++;
+    if (feasible && fabs(F) <= prm->tol_dinkelbach * R) break;
     if (i >= prm->max_dinkelbach) {
       flags |= ORC_NOT_CONVERGED;
       break;

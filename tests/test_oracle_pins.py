@@ -813,14 +813,23 @@ def test_warm_start_from_a_feasible_allocation():
 
 def test_warm_start_from_an_infeasible_allocation():
     """An infeasible warm allocation (the streaming users given no power) is
-    not a Dinkelbach starting point: E^1 = 0 and the sweeps start from it;
-    the result still meets every minimum rate."""
+    still Dinkelbach's p^0: E^1 = R(p^0)/P(p^0) (the independent evaluator's
+    value), which lies above what any feasible allocation reaches here, so
+    F < 0 at first and E moves down (F is strictly decreasing in E, Lemma 1).
+    The solve ends at the root condition |F| <= tol R on a feasible state
+    that meets every minimum rate."""
     d = synth.make_drop(synth.CFG2, 12, 0)
     op = oracle.Params(fixed_count=0)
     cold = oracle.solve(d, op)
     P0 = refeval.dense_from_slots(d, cold.sel, cold.slot_power)
     P0[:, :, d.user_type == 1] = 0.0
     r = oracle.solve(d, op, warm=dict(p0=P0))
-    assert r.trace_sweeps[0] == 0 and r.trace_E[1] == 0.0
+    ev = refeval.evaluate(d, P0)
+    assert r.trace_sweeps[0] == 0
+    assert r.trace_E[1] == pytest.approx(ev["ee"], rel=1e-12)
+    assert r.trace_E[1] > cold.ee and r.trace_F[1] < 0
+    n = r.dinkelbach_iters
+    assert abs(r.trace_F[n - 1]) <= op.tol_dinkelbach * r.trace_R[n - 1]
+    assert r.status_flags & (oracle.NOT_CONVERGED | oracle.QOS_INFEASIBLE | oracle.SIC_INFEASIBLE) == 0
     s = d.user_type == 1
     assert (r.user_rate[s] >= psi_of(d)[s] * (1 - 1e-6)).all()
