@@ -387,7 +387,7 @@ def main():
             "sweeps_mean_cold": line["sweeps_mean"],
             "ee_ratio_warm_over_cold_mean": float(ee_ratio.mean()),
             "ee_ratio_min": float(ee_ratio.min()),
-            "fallbacks": int(sum(bool(r.status_flags & 16) for r in wr)),
+            "fallbacks": int(sum(bool(r.status_flags & pa.WARM_FALLBACK) for r in wr)),
             "mlp_ms": mlp_ms,
             "mlp_roofline": {"bound": "mfma", "achieved": tfl, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                              "frac": tfl / BF16_PEAK_TFLOPS, "flop_per_row": MLP_FLOP_PER_ROW, "rows": rows},

@@ -59,8 +59,10 @@ extern "C" {
 
 /* alloc_result.status_flags */
 #define ALLOC_NOT_CONVERGED 1u  /* Dinkelbach stopped at max_dinkelbach */
-#define ALLOC_QOS_INFEASIBLE 2u /* a streaming user ends below (1-1e-6) of its minimum rate */
+#define ALLOC_QOS_INFEASIBLE 2u /* C13: a streaming user ends below (1-1e-6) of its minimum rate */
 #define ALLOC_NONFINITE 8u      /* a non-finite rate or power appeared */
+#define ALLOC_SIC_INFEASIBLE 16u /* C14: a co-scheduled pair ends with SIC margin above 1e-9 */
+#define ALLOC_BUDGET_INFEASIBLE 64u /* C12: an RRH ends above (1+1e-6) of its power budget */
 #define ALLOC_GROUP_TIMEOUT 32u /* batched solver: the workgroups sharing this drop did not
                                    meet within 20 s (never expected: the persistent grid
                                    stays resident); the result is not valid */
@@ -69,7 +71,11 @@ typedef struct alloc_ctx alloc_ctx;
 
 /* Create a context on HIP device `device` that enqueues on `hip_stream`
  * (a hipStream_t, e.g. torch.cuda.current_stream().cuda_stream; NULL = the
- * null stream).  Returns 0 and sets *out, or a negative code. */
+ * null stream).  Returns 0 and sets *out, or a negative code.
+ * alloc_ctx_destroy while batches (alloc_batch) or networks (alloc_mlp) made
+ * on the context are alive only closes it: those keep working, direct calls
+ * on the context return ALLOC_EINVAL, and it is freed when the last of them
+ * is destroyed. */
 ALLOC_API int alloc_ctx_create(int device, void* hip_stream, alloc_ctx** out);
 ALLOC_API void alloc_ctx_destroy(alloc_ctx* ctx);
 
@@ -96,12 +102,18 @@ typedef struct {
   int32_t sweeps_per_dinkelbach; /* 200: dual sweeps per step (cap, or exact count) */
   int32_t refit_period;          /* 1: SCALE refit every this many sweeps (<=0 never) */
   int32_t fixed_count;           /* 1: run exactly sweeps_per_dinkelbach sweeps */
-  int32_t churn_limit;           /* 8: selection/association changes per (m,n)/user
-                                    and Dinkelbach step before freezing (<=0 no cap) */
-  double tol_dinkelbach;         /* 1e-6: stop when R - E P <= tol * R */
-  double tol_dual;               /* 1e-7: dual loop stops when max|dp|/pmask < tol
-                                    and no association changed (fixed_count = 0) */
+  int32_t stall_sweeps;          /* 30: with fixed_count = 0, the dual loop also ends
+                                    after this many sweeps without a better state once
+                                    the best state is feasible (<= 0: never) */
+  double tol_dinkelbach;         /* 1e-6: stop when the returned state is feasible and
+                                    R - E P <= tol * R; also the relative gain of
+                                    R - E P that counts as progress of the dual loop */
+  double tol_dual;               /* 1e-7: dual loop stops when max|dp|/pmask and every
+                                    projected multiplier subgradient are below tol and
+                                    no association changed (fixed_count = 0) */
   double step0;                  /* 0.1: subgradient step step0/sqrt(1+v) */
+  double qos_down;               /* 0.2: the relative C13 violation (Psi - r_hat)/Psi of
+                                    the zeta' step is clipped to [-qos_down, 1] */
   uint32_t flags;                /* ALLOC_GAIN_ON_DEVICE | ALLOC_OUT_ON_DEVICE */
   int32_t max_groups;            /* 0: cap on the workgroups of the solve grid
                                     (0 = one per compute unit, <= N, and one per
@@ -131,8 +143,11 @@ ALLOC_API void alloc_params_default(alloc_params* p);
 
 /* Optional warm start: any pointer may be NULL (double; host, or device with
  * ALLOC_WARM_ON_DEVICE).  With p0 the initial allocation is built from it and
- * is Dinkelbach's p^0 (Sec. III): the first step evaluates it without dual
- * sweeps, E^1 = R(p^0)/P(p^0).  Users go to the RRH of largest total p0
+ * is Dinkelbach's p^0 (Sec. III), feasible or not: the first step evaluates
+ * it without dual sweeps, E^1 = R(p^0)/P(p^0), and the sweeps start from it
+ * (R - E P is strictly decreasing in E with its root at the optimum, Lemma 1
+ * and Theorem 1, so the iteration converges from above the optimum too, and
+ * the solve stops at |R - E P| <= tol R).  Users go to the RRH of largest total p0
  * (a user with no positive p0 keeps the cold-start RRH, the one of largest
  * sum over n of log2(1 + Gamma pmask/sigma)); each (m,n) takes the l users of
  * largest positive p0 among its users, at power min(p0, pmask).  Without p0
@@ -152,16 +167,16 @@ typedef struct {
   int32_t* sel;        /* [M][N][l] users of (m,n) in SIC decoding order, -1 = empty */
   double* slot_power;  /* [M][N][l] power of those users (W) */
   float* power;        /* [M][N][K] dense powers (W) */
-  int32_t* rrh_of_user; /* [K] association A_k from the last sweep (the RRH the user may be
-                           served by in the next one), -1 = unserved.  When the dual loop
-                           ends at its sweep cap, a user whose A_k that sweep moved is still
-                           served by its previous RRH in sel / slot_power. */
+  int32_t* rrh_of_user; /* [K] the RRH whose slots hold the user in sel, -1 = unserved */
   double* xi;          /* [M] */
   double* zeta;        /* [K] (0 for elastic users) */
   double* zeta_sic;    /* [M][N][l(l-1)/2] C14 multiplier of decoding positions (a<b) */
   double* user_rate;   /* [K] r_k (bits/s/Hz, summed over subcarriers) */
   double ee;           /* R/P at the returned allocation (bits/s/Hz/W) */
   double rate_sum, power_sum;
+  double viol_qos;     /* C13: sum over streaming users of (1-1e-6) - r_k/Psi_k where positive */
+  double viol_budget;  /* C12: sum over RRHs of sum_p/pmax - (1+1e-6) where positive */
+  double viol_sic;     /* C14: sum over co-scheduled pairs of margin - 1e-9 where positive */
   int32_t dinkelbach_iters, sweeps;
   uint32_t status_flags;
 } alloc_result;

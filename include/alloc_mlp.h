@@ -2,9 +2,9 @@
  * alloc_mlp.h -- C ABI of the warm-start network for the allocator of
  * include/alloc.h (MI355X, BF16 matrix cores, FP32 accumulation).
  *
- * The paper's Dinkelbach iteration (Sec. III) starts from any feasible
- * allocation p^0 and its dual loop (Sec. IV-A, Alg. 1) from any non-negative
- * multipliers; the paper leaves both unspecified.  This network predicts
+ * The paper's Dinkelbach iteration (Sec. III) starts from an allocation p^0
+ * and its dual loop (Sec. IV-A, Alg. 1) from non-negative multipliers; the
+ * paper leaves both unspecified.  This network predicts
  * them from per-triple features, so that the first Dinkelbach parameter
  * E^1 = R(p^0)/P(p^0) is already close to the optimum and the multipliers
  * start near their final values.  The network is not part of the paper.
@@ -54,9 +54,11 @@ extern "C" {
 #define ALLOC_MLP_NOUT 3
 #define ALLOC_MLP_NPARAMS 133635
 
-/* alloc_result.status_flags: the warm-started solve ended non-finite or with
- * no allocation (EE <= 0), and the returned result is the cold-started solve's */
-#define ALLOC_WARM_FALLBACK 16u
+/* alloc_result.status_flags: the warm-started solve ended non-finite, with no
+ * allocation (EE <= 0) or infeasible (ALLOC_QOS_INFEASIBLE,
+ * ALLOC_BUDGET_INFEASIBLE, ALLOC_SIC_INFEASIBLE), and the returned result is
+ * the cold-started solve's */
+#define ALLOC_WARM_FALLBACK 128u
 
 typedef struct alloc_mlp alloc_mlp;
 
@@ -117,9 +119,9 @@ ALLOC_API int alloc_mlp_warm(alloc_mlp* net, const alloc_problem* prob, uint32_t
 
 /* Network inference, then alloc_solve from that warm start.  Falls back to
  * the cold start (and sets ALLOC_WARM_FALLBACK) when the warm-started solve
- * ends with ALLOC_NONFINITE or with EE <= 0 (nothing allocated).  QoS
- * infeasibility is reported, not a fallback: the cold start ends
- * QoS-infeasible on most drops of the streaming-heavy configurations too. */
+ * ends non-finite, with EE <= 0 (nothing allocated) or infeasible (C12, C13
+ * or C14 flagged): the cold-started solve is then returned, whatever its own
+ * flags. */
 ALLOC_API int alloc_solve_mlp(alloc_mlp* net, const alloc_problem* prob, const alloc_params* prm,
                               alloc_result* res);
 

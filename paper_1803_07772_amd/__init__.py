@@ -22,6 +22,10 @@ ALLOC_WARM_ON_DEVICE = 4
 NOT_CONVERGED = 1
 QOS_INFEASIBLE = 2
 NONFINITE = 8
+SIC_INFEASIBLE = 16
+GROUP_TIMEOUT = 32
+BUDGET_INFEASIBLE = 64
+WARM_FALLBACK = 128
 
 _lib = None
 
@@ -45,9 +49,9 @@ class _Problem(ctypes.Structure):
 class _Params(ctypes.Structure):
     _fields_ = [("max_dinkelbach", ctypes.c_int32), ("sweeps_per_dinkelbach", ctypes.c_int32),
                 ("refit_period", ctypes.c_int32), ("fixed_count", ctypes.c_int32),
-                ("churn_limit", ctypes.c_int32), ("tol_dinkelbach", ctypes.c_double),
+                ("stall_sweeps", ctypes.c_int32), ("tol_dinkelbach", ctypes.c_double),
                 ("tol_dual", ctypes.c_double), ("step0", ctypes.c_double),
-                ("flags", ctypes.c_uint32), ("max_groups", ctypes.c_int32),
+                ("qos_down", ctypes.c_double), ("flags", ctypes.c_uint32), ("max_groups", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("lds_kb", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("wave", ctypes.c_int32)]
 
@@ -62,7 +66,9 @@ class _Result(ctypes.Structure):
                 ("xi", ctypes.c_void_p), ("zeta", ctypes.c_void_p),
                 ("zeta_sic", ctypes.c_void_p), ("user_rate", ctypes.c_void_p),
                 ("ee", ctypes.c_double), ("rate_sum", ctypes.c_double),
-                ("power_sum", ctypes.c_double), ("dinkelbach_iters", ctypes.c_int32),
+                ("power_sum", ctypes.c_double), ("viol_qos", ctypes.c_double),
+                ("viol_budget", ctypes.c_double), ("viol_sic", ctypes.c_double),
+                ("dinkelbach_iters", ctypes.c_int32),
                 ("sweeps", ctypes.c_int32), ("status_flags", ctypes.c_uint32)]
 
 
@@ -73,7 +79,7 @@ _PROBLEM_DTYPE = np.dtype({"names": [f for f, _ in _Problem._fields_],
                            "offsets": [getattr(_Problem, f).offset for f, _ in _Problem._fields_],
                            "itemsize": ctypes.sizeof(_Problem)})
 _RESULT_DTYPE = np.dtype({"names": [f for f, _ in _Result._fields_],
-                          "formats": ["<u8"] * 8 + ["<f8"] * 3 + ["<i4", "<i4", "<u4"],
+                          "formats": ["<u8"] * 8 + ["<f8"] * 6 + ["<i4", "<i4", "<u4"],
                           "offsets": [getattr(_Result, f).offset for f, _ in _Result._fields_],
                           "itemsize": ctypes.sizeof(_Result)})
 
@@ -140,10 +146,11 @@ class Params:
     sweeps_per_dinkelbach: int = 200
     refit_period: int = 1
     fixed_count: int = 1
-    churn_limit: int = 8
+    stall_sweeps: int = 30
     tol_dinkelbach: float = 1e-6
     tol_dual: float = 1e-7
     step0: float = 0.1
+    qos_down: float = 0.2
     max_groups: int = 0
     tile: int = 0
     lds_kb: int = 0
@@ -152,17 +159,17 @@ class Params:
 
     def _c(self, flags: int) -> _Params:
         return _Params(self.max_dinkelbach, self.sweeps_per_dinkelbach, self.refit_period,
-                       self.fixed_count, self.churn_limit, self.tol_dinkelbach, self.tol_dual,
-                       self.step0, flags, self.max_groups, self.tile, self.lds_kb, self.block,
-                       self.wave)
+                       self.fixed_count, self.stall_sweeps, self.tol_dinkelbach, self.tol_dual,
+                       self.step0, self.qos_down, flags, self.max_groups, self.tile, self.lds_kb,
+                       self.block, self.wave)
 
 
 def default_params() -> Params:
     p = _Params()
     load().alloc_params_default(ctypes.byref(p))
     return Params(p.max_dinkelbach, p.sweeps_per_dinkelbach, p.refit_period, p.fixed_count,
-                  p.churn_limit, p.tol_dinkelbach, p.tol_dual, p.step0, p.max_groups, p.tile, p.lds_kb,
-                  p.block, p.wave)
+                  p.stall_sweeps, p.tol_dinkelbach, p.tol_dual, p.step0, p.qos_down, p.max_groups,
+                  p.tile, p.lds_kb, p.block, p.wave)
 
 
 @dataclasses.dataclass
@@ -180,6 +187,9 @@ class Result:
     dinkelbach_iters: int
     sweeps: int
     status_flags: int
+    viol_qos: float = 0.0
+    viol_budget: float = 0.0
+    viol_sic: float = 0.0
     power: np.ndarray | None = None
 
 
@@ -228,14 +238,15 @@ def result_struct(drop, dense_power=False):
                   dense.ctypes.data if dense is not None else None,
                   out["rrh_of_user"].ctypes.data, out["xi"].ctypes.data,
                   out["zeta"].ctypes.data, out["zeta_sic"].ctypes.data if NP else None,
-                  out["user_rate"].ctypes.data, 0.0, 0.0, 0.0, 0, 0, 0)
+                  out["user_rate"].ctypes.data, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0)
     return res, out, dense
 
 
 def to_result(res, out, dense) -> "Result":
     return Result(ee=res.ee, rate_sum=res.rate_sum, power_sum=res.power_sum,
                   dinkelbach_iters=res.dinkelbach_iters, sweeps=res.sweeps,
-                  status_flags=res.status_flags, power=dense, **out)
+                  status_flags=res.status_flags, viol_qos=res.viol_qos,
+                  viol_budget=res.viol_budget, viol_sic=res.viol_sic, power=dense, **out)
 
 
 class Context:
@@ -397,7 +408,8 @@ class Context:
                              zeta_sic=zs[oP[b]:oP[b + 1]].reshape(M[b], N[b], NP[b]),
                              user_rate=ur[k0:k1], ee=r.ee, rate_sum=r.rate_sum,
                              power_sum=r.power_sum, dinkelbach_iters=r.dinkelbach_iters,
-                             sweeps=r.sweeps, status_flags=r.status_flags, power=dense))
+                             sweeps=r.sweeps, status_flags=r.status_flags, viol_qos=r.viol_qos,
+                             viol_budget=r.viol_budget, viol_sic=r.viol_sic, power=dense))
         return rs
 
     def solve(self, drop, params: Params | None = None, gain=None, warm=None, pmask=None,

@@ -44,24 +44,57 @@ constexpr int kGridBlock = 512;  // workgroup of the grid solver
 // decaying powers never reach the subnormal range.
 constexpr double kPowerFloorRel = 1e-20;
 
+// Feasibility of an evaluated state: C13 r_k >= Psi_k (1 - kQosTol), C12
+// sum p <= pmax (1 + kBudgetTol), C14 pair margin <= kSicTol.  Two nonzero
+// violations within kViolRel of each other rank as equal.
+constexpr double kQosTol = 1e-6;
+constexpr double kBudgetTol = 1e-6;
+constexpr double kSicTol = 1e-9;
+constexpr double kViolRel = 1e-6;
+
 enum Mode : int { kSweep = 0, kEval = 1, kDone = 2 };
 
 // Loop-control state.  Every workgroup holds an identical copy.
+//
+// The dual sweeps are not a descent method, so a Dinkelbach step returns the
+// best state it visited: feasible (C12-C14) before infeasible, less C12/C13
+// violation first, then less C14 violation, then the larger R - E P.  The
+// primal state (association, selection, powers, SCALE coefficients, C14
+// multipliers) lives in three buffers: the one the next pass reads (rd), the
+// one a sweep writes (wr) and the best state of the step (best).  After a
+// sweep its output becomes the state to read; the state it read becomes the
+// best or is free for the next sweep's output: a pointer rotation, no copies.
 struct Ctrl {
-  double E;       // Dinkelbach parameter of the current step
-  double R, P;    // rate and power of the last evaluated state
-  int i;          // Dinkelbach steps completed
-  int v;          // sweeps done in the current step
+  double E;           // Dinkelbach parameter of the current step
+  double R, P;        // rate and power of the last evaluated state
+  double Vq, Vp, Vs;  // its violations of C13, C12, C14
+  double bV, bV2;     // best state of the step: C12 + C13 and C14 violation,
+  double bf, bR;      //   R - E P and R
+  int i;              // Dinkelbach steps completed
+  int v;              // sweeps done in the current step
   int mode;
-  int total;      // sweeps done in total
-  int reset;      // next sweep starts a Dinkelbach step
-  int pass;       // passes (sweeps and evaluations) done
+  int total;          // sweeps done in total
+  int reset;          // next sweep starts a Dinkelbach step
+  int pass;           // passes (sweeps and evaluations) done
+  int rd, wr, best;   // state buffers (0..2)
+  int have_best;      // best is set in this step
+  int stall;          // sweeps since the last gain of the best
+  int first_eval;     // the next evaluation is the warm start's p^0
   uint32_t flags;
 };
 
 struct Sched {
-  int max_d, sweeps, refit_period, fixed, churn, tile;
-  double tol_d, tol_dual, step0;
+  int max_d, sweeps, refit_period, fixed, stall, tile;
+  double tol_d, tol_dual, step0, qos_down;
+};
+
+// Reduced values of one pass, the input of the loop control.
+struct Eval {
+  double R, P;        // weighted elastic rate, power of the state read
+  double Vq, Vp, Vs;  // its violations of C13, C12, C14
+  double dm;          // largest |dp|/pmask and C14 multiplier step / delta
+  double xres, zres;  // largest xi' and zeta' steps / their step sizes
+  int changes;        // users whose association the sweep changed
 };
 
 // Division by a run-time invariant d by multiply-high and shifts
@@ -118,16 +151,15 @@ struct Drop {
   const double* pmask;     // [M]
   const double* w;         // [M][K] or nullptr (all ones)
   double sigma, pstatic;
-  int* A;                  // [K]
-  int* sel;                // [M][N][L] storage order
-  double* p;               // [M][N][L]
-  double* al;              // [M][N][L]
-  double* be;              // [M][N][L]
-  double* zs;              // [M][N][L][L]
+  // primal state, three buffers each (see Ctrl)
+  int* A;                  // [3][K] association
+  int* sel;                // [3][M][N][L] storage order
+  double* p;               // [3][M][N][L]
+  double* al;              // [3][M][N][L]
+  double* be;              // [3][M][N][L]
+  double* zs;              // [3][M][N][L][L]
   double* xi;              // [M]
   double* zeta;            // [K]
-  int* churn_sel;          // [M][N]
-  int* churn_A;            // [K]
   // partials, one row per workgroup
   double* S_part;          // [G][M][K] association metric
   double* r_part;          // [G][K] true rate
@@ -136,8 +168,11 @@ struct Drop {
   double* pel_part;        // [G][M] power, elastic users
   double* R_part;          // [G] weighted elastic rate
   double* d_part;          // [G] max |dp|/pmask
+  double* sv_part;         // [G] C14 violation
+  double* vq_part;         // [G] C13 violation of the workgroup's users
+  double* zr_part;         // [G] largest zeta' step of its users / delta
   int* chg_count;          // [2] association changes, indexed by pass parity
-  double* red;             // [4] R, P, delta (written by workgroup 0)
+  double* red;             // [8] R, P, dm, xres, Vp, Vs (written by workgroup 0)
   double* user_rate;       // [K]
   // decoding-order copies of the last evaluated state
   int* out_sel;            // [M][N][L]
@@ -210,11 +245,12 @@ struct Lds {
   LDS double* tps;    // [T][M]
   LDS double* tpe;    // [T][M]
   LDS double* tR;     // [T][M]
-  LDS int* frozen;    // [T][M]
-  LDS int* churn;     // [T][M]
+  LDS double* tsv;    // [T][M] C14 violation of RRH m's pairs
+  LDS double* uc;     // [T][K] u of user k on its own RRH
+  LDS float* gc;      // [T][K] gain of user k on its own RRH
+  LDS int* ord;       // [T][K] each RRH group's candidates in order of H
   LDS double* pij;    // [T][M][M]
   LDS double* contrib; // [T][M][M]
-  LDS int* chosen;    // [T][M][L]
   LDS double* xi;     // [M]
   LDS double* eta;    // [M]
   LDS double* pmask;  // [M]
@@ -222,6 +258,7 @@ struct Lds {
   LDS double* peacc;  // [M]
   LDS double* Racc;   // [M]
   LDS double* dmax;   // [M]
+  LDS double* svacc;  // [M] C14 violation
   LDS double* red;    // [threads] scratch for reductions
   LDS double* tmp;    // [M+2] reduction results
 };
@@ -251,8 +288,8 @@ __host__ __device__ inline size_t carve_lds(LDS char* base, int M, int K, int L,
   // Arrays whose live ranges within a tile do not overlap share storage: H
   // and the intra-cell price of each user on its own RRH (steps 6-7) take
   // the gains' place (steps 1-5); the inter-cell and C14 price terms (step
-  // 5) the per-user rates' (steps 1-4); the selection (steps 6-7) the prices
-  // c and c Gamma (steps 4-5).
+  // 5) the per-user rates' (steps 1-4), and so does the candidates' order
+  // (steps 6-7).
   {
     if (parts & kTile) o = (o + 15) & ~size_t(15);  // the gains take 16-byte stores
     LDS char* r = take(std::max(sizeof(float) * TM * K, sizeof(double) * 2 * TK));
@@ -267,13 +304,15 @@ __host__ __device__ inline size_t carve_lds(LDS char* base, int M, int K, int L,
     s.rhk = r ? s.rk + TK : nullptr;
     s.pij = (LDS double*)r;
     s.contrib = r ? s.pij + TM * M : nullptr;
+    s.ord = (LDS int*)r;
   }
   {
     LDS char* r = take(sizeof(double) * 2 * TML);
     s.vc = (LDS double*)r;
     s.vcg = r ? s.vc + TML : nullptr;
-    s.chosen = (LDS int*)r;
   }
+  s.uc = (LDS double*)take(sizeof(double) * TK);
+  s.gc = (LDS float*)take(sizeof(float) * TK);
   part = kAccum;
   s.Sacc = (LDS double*)take(sizeof(double) * M * K);
   s.racc = (LDS double*)take(sizeof(double) * K);
@@ -282,6 +321,7 @@ __host__ __device__ inline size_t carve_lds(LDS char* base, int M, int K, int L,
   s.peacc = (LDS double*)take(sizeof(double) * M);
   s.Racc = (LDS double*)take(sizeof(double) * M);
   s.dmax = (LDS double*)take(sizeof(double) * M);
+  s.svacc = (LDS double*)take(sizeof(double) * M);
   part = kShared;
   s.mu = (LDS double*)take(sizeof(double) * K);
   s.Al = (LDS int*)take(sizeof(int) * K);
@@ -316,8 +356,7 @@ __host__ __device__ inline size_t carve_lds(LDS char* base, int M, int K, int L,
   s.tps = (LDS double*)take(sizeof(double) * TM);
   s.tpe = (LDS double*)take(sizeof(double) * TM);
   s.tR = (LDS double*)take(sizeof(double) * TM);
-  s.frozen = (LDS int*)take(sizeof(int) * TM);
-  s.churn = (LDS int*)take(sizeof(int) * TM);
+  s.tsv = (LDS double*)take(sizeof(double) * TM);
   if (out) *out = s;
   return o;
 }
@@ -394,14 +433,14 @@ __device__ inline int load_shared(const int* p) {
 
 // ------------------------------------------------------------- per sweep
 
-// Start of a pass: multipliers, association and RRH groups into LDS,
-// accumulators cleared.
-__device__ void begin_pass(const Drop& d, Lds& s) {
+// Start of a pass: multipliers, association (of state buffer rd) and RRH
+// groups into LDS, accumulators cleared.
+__device__ void begin_pass(const Drop& d, Lds& s, int rd) {
   const int M = d.M, K = d.K, tid = threadIdx.x, nth = blockDim.x;
   for (int k = tid; k < K; k += nth) {
     s.el[k] = gl(d.elastic)[k];
     s.mu[k] = gl(d.elastic)[k] ? 1.0 : gl(d.zeta)[k];
-    s.Al[k] = gl(d.A)[k];
+    s.Al[k] = gl(d.A)[(size_t)rd * K + k];
     s.racc[k] = 0.0;
     s.rhacc[k] = 0.0;
   }
@@ -414,6 +453,7 @@ __device__ void begin_pass(const Drop& d, Lds& s) {
     s.peacc[m] = 0.0;
     s.Racc[m] = 0.0;
     s.dmax[m] = 0.0;
+    s.svacc[m] = 0.0;
   }
   __syncthreads();
   // Users grouped by RRH in ascending user order: each wave ranks its lanes
@@ -463,6 +503,7 @@ __device__ __forceinline__ int mad24(int a, int b, int c) { return mul24(a, b) +
 struct PassConst {
   double E, delta_v;
   int refit, reset, update, write_out;
+  int rd, wr;  // state buffer read, and written by a sweep
 };
 
 // The threads that run one tile together: the whole workgroup (barriers), or
@@ -506,6 +547,13 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
   const int M = d.M, N = d.N, K = d.K, L = d.L, tid = tm.tid, nth = tm.nth;
   const Divs& dv = d.dv;
   const double sg = d.sigma;
+  // state buffers: slot arrays [M][N][L], pair multipliers [M][N][L][L]
+  const size_t nsl = (size_t)M * N * L;
+  GLB const int* rsel = gl(d.sel) + pc.rd * nsl;
+  GLB const double* rp = gl(d.p) + pc.rd * nsl;
+  GLB const double* ral = gl(d.al) + pc.rd * nsl;
+  GLB const double* rbe = gl(d.be) + pc.rd * nsl;
+  GLB const double* rzs = gl(d.zs) + pc.rd * nsl * L;
 #define NOF(t) (n0 + (t) * nstep)
 
   // 1. gains, slot state and per-RRH totals into LDS.  Within a round every
@@ -547,29 +595,28 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
       const int i = tid + r0 * nth;
       int sel = -1;
       double p = 0.0, al = 1.0, be = 0.0, z = 0.0, pq[kMaxL];
-      int sq[kMaxL], ch = 0;
+      int sq[kMaxL];
       if (i < nS) {
         const int t = dv.ML.div(i), r = i - mul24(t, M * L), m = dv.L.div(r), q = r - mul24(m, L);
         const size_t gi = ((size_t)m * N + NOF(t)) * L + q;
-        sel = gl(d.sel)[gi];
-        p = gl(d.p)[gi];
+        sel = rsel[gi];
+        p = rp[gi];
         if (!pc.reset) {
-          al = gl(d.al)[gi];
-          be = gl(d.be)[gi];
+          al = ral[gi];
+          be = rbe[gi];
         }
       }
       if (i < nZ) {
         const int t = dv.MLL.div(i), r = i - mul24(t, M * L * L), m = dv.LL.div(r), ab = r - mul24(m, L * L);
-        z = gl(d.zs)[((size_t)m * N + NOF(t)) * L * L + ab];
+        z = rzs[((size_t)m * N + NOF(t)) * L * L + ab];
       }
       if (i < nP) {
         const int t = dv.M.div(i), m = i - mul24(t, M);
         const size_t gi = ((size_t)m * N + NOF(t)) * L;
-        if (!pc.reset) ch = gl(d.churn_sel)[(size_t)m * N + NOF(t)];
 #pragma unroll
         for (int q = 0; q < kMaxL; ++q) {
-          sq[q] = q < L ? gl(d.sel)[gi + q] : -1;
-          pq[q] = q < L ? gl(d.p)[gi + q] : 0.0;
+          sq[q] = q < L ? rsel[gi + q] : -1;
+          pq[q] = q < L ? rp[gi + q] : 0.0;
         }
       }
       if (vec4) {
@@ -594,7 +641,6 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
         s.szn[i] = 0.0;
       }
       if (i < nP) {
-        s.churn[i] = ch;
         double acc = 0.0;  // total power of RRH m on the subcarrier
 #pragma unroll
         for (int q = 0; q < kMaxL; ++q)
@@ -619,11 +665,18 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
       suf += s.Ptot[IX_SM(t, m)] * (double)s.g[IX_MK(t, m, k)];
     }
     double pre = 0.0;
+    const int own = s.Al[k];
     for (int m = 0; m < M; ++m) {
-      const double gm = (double)s.g[IX_MK(t, m, k)];
+      const float gf = s.g[IX_MK(t, m, k)];
+      const double gm = (double)gf;
       const double ici = pre + s.u[IX_MK(t, m, k)];
       pre += s.Ptot[IX_SM(t, m)] * gm;
-      s.u[IX_MK(t, m, k)] = (sg + ici) / gm;
+      const double uu = (sg + ici) / gm;
+      s.u[IX_MK(t, m, k)] = uu;
+      if (m == own) {  // kept for the C14 test of the selection (step 7)
+        s.uc[i] = uu;
+        s.gc[i] = gf;
+      }
     }
   }
   tm.sync();
@@ -703,6 +756,21 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
     s.tps[i] = ps;
     s.tpe[i] = pe;
     s.tR[i] = Rm;
+    // C14 at the state: each co-scheduled pair's relative margin
+    // (u_s - u_w)/(u_s + u_w), s the user of larger raw gain (ties to the
+    // lower index), counted above kSicTol
+    double sv = 0.0;
+    for (int a = 0; a < cnt; ++a)
+      for (int b = a + 1; b < cnt; ++b) {
+        const int ka = s.vuser[IX_ML(t, m, a)], kb = s.vuser[IX_ML(t, m, b)];
+        const float ga = s.g[IX_MK(t, m, ka)], gb = s.g[IX_MK(t, m, kb)];
+        const bool swap = gb > ga || (gb == ga && kb < ka);
+        const double us = swap ? s.vu[IX_ML(t, m, b)] : s.vu[IX_ML(t, m, a)];
+        const double uw = swap ? s.vu[IX_ML(t, m, a)] : s.vu[IX_ML(t, m, b)];
+        const double om = (us - uw) / (us + uw);
+        if (om > kSicTol) sv += om - kSicTol;
+      }
+    s.tsv[i] = sv;
     if (pc.write_out) {
       for (int a = cnt; a < L; ++a) {
         const size_t o = ((size_t)m * N + NOF(t)) * L + a;
@@ -732,6 +800,7 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
       s.psacc[m] = seq_sum(ns, s.psacc[m], [&](int t) { return s.tps[IX_SM(t, m)]; });
       s.peacc[m] = seq_sum(ns, s.peacc[m], [&](int t) { return s.tpe[IX_SM(t, m)]; });
       s.Racc[m] = seq_sum(ns, s.Racc[m], [&](int t) { return s.tR[IX_SM(t, m)]; });
+      s.svacc[m] = seq_sum(ns, s.svacc[m], [&](int t) { return s.tsv[IX_SM(t, m)]; });
     }
   };
   if (!pc.update) {
@@ -779,9 +848,16 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
     const double uw = swap ? s.vu[IX_ML(t, m, a)] : s.vu[IX_ML(t, m, b)];
     const double om = (us - uw) / (us + uw);
     const int sa = s.vslot[IX_ML(t, m, a)], sb = s.vslot[IX_ML(t, m, b)];
-    const double zn = fmax(s.szs[IX_MLL(t, m, sa, sb)] + pc.delta_v * om, 0.0);
+    const double z = s.szs[IX_MLL(t, m, sa, sb)];
+    const double zn = fmax(z + pc.delta_v * om, 0.0);
     s.szn[IX_MLL(t, m, sa, sb)] = zn;
     s.szn[IX_MLL(t, m, sb, sa)] = zn;
+    // the projected subgradient joins the power changes in the dual loop's
+    // stopping test (an order-free integer maximum, as below)
+    const double dz = fabs(zn - z) / pc.delta_v;
+    if (dz == dz)
+      __hip_atomic_fetch_max((LDS unsigned long long*)(s.dmax + m), (unsigned long long)__double_as_longlong(dz),
+                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   }
   rrh_sums();
   tm.sync();
@@ -797,13 +873,12 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
     const int cnt = s.vcnt[i];
     s.vT[IX_ML1(t, m, cnt)] = 0.0;
     for (int a = cnt - 1; a >= 0; --a) s.vT[IX_ML1(t, m, a)] = s.vT[IX_ML1(t, m, a + 1)] + s.vcg[IX_ML(t, m, a)];
-    s.frozen[i] = sc.churn > 0 && s.churn[i] >= sc.churn;
   }
   tm.sync();
 
-  // 6. per-triple Lagrangian maximum H (the selection starts empty: its
-  //    storage held the prices read in step 5)
-  for (int i = tid; i < ns * M * L; i += nth) s.chosen[i] = -1;
+  // 6. per-triple Lagrangian maximum H (the candidates' order starts empty:
+  //    its storage held the price terms read after step 5)
+  for (int i = tid; i < ns * K; i += nth) s.ord[i] = -1;
   auto h_item = [&](int t, int m, int k, double u) -> double {
     const double wmu = (d.w ? gl(d.w)[(size_t)m * K + k] : 1.0) * s.mu[k];
     const int cnt = s.vcnt[IX_SM(t, m)];
@@ -856,12 +931,12 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
     tm.sync();
   }
 
-  // 7. selection: the l best of RRH m's users with H > 0 (H desc, user asc),
-  //    by each candidate's rank within its group
+  // 7. selection.  Each candidate (H > 0 on its own RRH) takes the place of
+  //    its rank within its RRH group (H desc, user asc) ...
   for (int i = tid; i < ns * K; i += nth) {
     const int t = dv.K.div(i), k = i - mul24(t, K);
     const int m = s.Al[k];
-    if (m < 0 || s.frozen[IX_SM(t, m)]) continue;
+    if (m < 0) continue;
     const double h = s.Hc[i];
     if (!(h > 0.0)) continue;
     int rank = 0;
@@ -870,53 +945,57 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
       const double hj = s.Hc[IX_SK(t, j)];
       rank += (hj > h) || (hj == h && j < k);
     }
-    if (rank < L) s.chosen[IX_ML(t, m, rank)] = k;
+    s.ord[IX_SK(t, s.grp_off[m] + rank)] = k;
   }
   tm.sync();
-  // The new selection of each (subcarrier, RRH), its closed-form powers and
-  // the C14 multipliers' move into the new slots, one item per slot: each
-  // item settles its (subcarrier, RRH)'s selection itself from the ranks
-  // above (at most l entries), so the three need no barrier between them.
+  // ... then, one item per slot, each (subcarrier, RRH)'s new selection
+  // (settled by each of its slot items alone, so no barrier follows), its
+  // closed-form powers and the C14 multipliers' move into the new slots.
+  // The candidates are taken in order, each only if every pair it forms with
+  // those taken before it meets C14 (margin <= 0 at the state's
+  // interference), until l are taken (Sec. II-B, C8/C14).
   for (int i = tid; i < ns * M * L; i += nth) {
     const int t = dv.ML.div(i), r = i - mul24(t, M * L), m = dv.L.div(r), a = r - mul24(m, L);
     const int sm = IX_SM(t, m);
     const int cnt = s.vcnt[sm];
-    const bool fr = s.frozen[sm];
     int vk[kMaxL], vq[kMaxL], ch[kMaxL];
+    double cu[kMaxL];
+    float cgn[kMaxL];
 #pragma unroll
     for (int b = 0; b < kMaxL; ++b) {
       vk[b] = b < cnt ? s.vuser[IX_ML(t, m, b)] : -1;
       vq[b] = b < cnt ? s.vslot[IX_ML(t, m, b)] : -1;
       ch[b] = -1;
+      cu[b] = 0.0;
+      cgn[b] = 0.0f;
     }
     int np = 0;
-    if (fr) {  // churn cap reached: keep the incumbents still associated with m
-#pragma unroll
-      for (int b = 0; b < kMaxL; ++b)
-        if (b < cnt && s.Al[vk[b]] == m) ch[np++] = vk[b];
-    } else {  // the ranks' leading entries
-#pragma unroll
-      for (int b = 0; b < kMaxL; ++b)
-        if (b < L && np == b) {
-          const int c = s.chosen[IX_ML(t, m, b)];
-          if (c >= 0) ch[np++] = c;
-        }
-    }
-    if (a == 0) {  // the selection's churn counter
-      int churn = s.churn[sm];
-      if (!fr) {
-        bool same = np == cnt;
+    {
+      const int base = s.grp_off[m], gn = s.grp_off[m + 1] - base;
+      for (int e = 0; e < gn && np < L; ++e) {
+        const int k = s.ord[IX_SK(t, base + e)];
+        if (k < 0) break;
+        const double uk = s.uc[IX_SK(t, k)];
+        const float gk = s.gc[IX_SK(t, k)];
+        bool ok = true;
 #pragma unroll
         for (int b = 0; b < kMaxL; ++b)
           if (b < np) {
-            bool f = false;
-#pragma unroll
-            for (int b2 = 0; b2 < kMaxL; ++b2) f = f || (b2 < cnt && vk[b2] == ch[b]);
-            same = same && f;
+            const bool kstrong = gk > cgn[b] || (gk == cgn[b] && k < ch[b]);
+            const double us = kstrong ? uk : cu[b], uw = kstrong ? cu[b] : uk;
+            if ((us - uw) / (us + uw) > 0.0) ok = false;
           }
-        if (!same) ++churn;
+        if (ok) {
+#pragma unroll
+          for (int b = 0; b < kMaxL; ++b)
+            if (b == np) {
+              ch[b] = k;
+              cu[b] = uk;
+              cgn[b] = gk;
+            }
+          ++np;
+        }
       }
-      gl(d.churn_sel)[(size_t)m * N + NOF(t)] = churn;
     }
     int old[kMaxL];  // each new entry's slot before this sweep (-1 if new)
 #pragma unroll
@@ -959,7 +1038,8 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
     if (dm == dm)
       __hip_atomic_fetch_max((LDS unsigned long long*)(s.dmax + m), (unsigned long long)__double_as_longlong(dm),
                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    const size_t gi = ((size_t)m * N + NOF(t)) * L + a;
+    // the new state goes to buffer wr
+    const size_t gi = pc.wr * nsl + ((size_t)m * N + NOF(t)) * L + a;
     gl(d.sel)[gi] = k;
     gl(d.p)[gi] = pn;
     gl(d.al)[gi] = alph;
@@ -990,13 +1070,15 @@ __device__ void write_partials(const Drop& d, const Lds& s, int b) {
     gl(d.pel_part)[(size_t)b * M + m] = s.peacc[m];
   }
   if (tid == 0) {
-    double R = 0.0, dm = 0.0;
+    double R = 0.0, dm = 0.0, sv = 0.0;
     for (int m = 0; m < M; ++m) {
       R += s.Racc[m];
       dm = fmax(dm, s.dmax[m]);
+      sv += s.svacc[m];
     }
     gl(d.R_part)[b] = R;
     gl(d.d_part)[b] = dm;
+    gl(d.sv_part)[b] = sv;
   }
 }
 
@@ -1032,13 +1114,57 @@ __device__ void reduce_groups(Lds& s, const double* base, int G, int M, size_t g
   __syncthreads();
 }
 
-// Reductions across workgroups: users k = b, b+G, ... per workgroup;
+// C13 violation of one user: (1 - kQosTol) - r/Psi where positive, for a
+// streaming user.
+__device__ inline double qos_viol(double r, double psi) {
+  const double x = r / psi;
+  return x < 1.0 - kQosTol ? (1.0 - kQosTol) - x : 0.0;
+}
+
+// Subgradient step of zeta' on the SCALE surrogate rate: the relative C13
+// violation (Psi - r_hat)/Psi clipped to [-qos_down, 1]; returns the new
+// value, *res the step over delta.
+__device__ inline double zeta_step(double z, double psi, double rh, double delta_v, double qos_down, double* res) {
+  const double viol = fmin(fmax((psi - rh) / psi, -qos_down), 1.0);
+  const double zn = fmax(z + delta_v * viol, 0.0);
+  *res = fabs(zn - z) / delta_v;
+  return zn;
+}
+
+// Subgradient step of xi'_m on the C12 budget, scaled by N l/(ln2 pmax);
+// returns the new value, *res the step over (delta scale).
+__device__ inline double xi_step(double x, double ps, double pmax, int N, int L, double delta_v, double* res) {
+  const double scale = (double)N * L / (kLn2 * pmax);
+  const double xn = fmax(x + delta_v * scale * (ps - pmax) / pmax, 0.0);
+  *res = fabs(xn - x) / (delta_v * scale);
+  return xn;
+}
+
+// The association of one user from its summed Lagrangian maxima S[m]
+// (stride ms): the RRH of the largest positive sum (ties to the lower RRH);
+// without one an elastic user is unserved and a streaming user keeps its RRH.
+template <class F>
+__device__ inline int assoc_of(int M, int before, bool elastic, F&& S) {
+  double best = -INFINITY;
+  int bm = 0;
+  for (int m = 0; m < M; ++m)
+    if (S(m) > best) {
+      best = S(m);
+      bm = m;
+    }
+  if (best > 0.0) return bm;
+  return elastic ? -1 : before;
+}
+
+// Reductions across workgroups: users k = b, b+G, ... per workgroup (rates,
+// association into buffer wr, zeta' steps, partial C13 violation);
 // workgroup 0 also does the per-RRH and scalar sums.
 __device__ void reduce_pass(const Drop& d, const Sched& sc, const Ctrl& c, Lds& s, int b, int G,
                             bool update, double delta_v) {
   const int M = d.M, K = d.K, tid = threadIdx.x;
   const int par = c.pass & 1;
   int changes = 0;
+  double vq = 0.0, zr = 0.0;
   if (b == 0 && tid == 0) store_shared(&d.chg_count[par ^ 1], 0);  // next pass's counter
   for (int k = b; k < K; k += G) {
     reduce_groups<false>(s, d.r_part + k, G, 1, K, 0, s.tmp);
@@ -1047,93 +1173,161 @@ __device__ void reduce_pass(const Drop& d, const Sched& sc, const Ctrl& c, Lds& 
     if (tid == 0) {
       const double r = s.tmp[0], rh = s.tmp[1];
       gl(d.user_rate)[k] = r;
+      const bool el = gl(d.elastic)[k];
+      if (!el) vq += qos_viol(r, gl(d.psi)[k]);
       if (update) {
-        double best = -INFINITY;
-        int bm = 0;
-        for (int m = 0; m < M; ++m)
-          if (s.tmp[2 + m] > best) {
-            best = s.tmp[2 + m];
-            bm = m;
-          }
-        int ch_A = c.reset ? 0 : gl(d.churn_A)[k];
-        const int before = gl(d.A)[k];
-        if (!(sc.churn > 0 && ch_A >= sc.churn)) {
-          int after = before;
-          if (best > 0.0)
-            after = bm;
-          else if (gl(d.elastic)[k])
-            after = -1;
-          if (after != before) {
-            gl(d.A)[k] = after;
-            ++ch_A;
-            ++changes;
-          }
-        }
-        gl(d.churn_A)[k] = ch_A;
-        if (!gl(d.elastic)[k]) {
-          const double viol = fmin(fmax((gl(d.psi)[k] - rh) / gl(d.psi)[k], -1.0), 1.0);
-          gl(d.zeta)[k] = fmax(gl(d.zeta)[k] + delta_v * viol, 0.0);
+        const int before = gl(d.A)[(size_t)c.rd * K + k];
+        const int after = assoc_of(M, before, el, [&](int m) { return s.tmp[2 + m]; });
+        gl(d.A)[(size_t)c.wr * K + k] = after;
+        if (after != before) ++changes;
+        if (!el) {
+          double res;
+          gl(d.zeta)[k] = zeta_step(gl(d.zeta)[k], gl(d.psi)[k], rh, delta_v, sc.qos_down, &res);
+          zr = fmax(zr, res);
         }
       }
     }
     __syncthreads();
   }
-  if (tid == 0 && changes > 0)
-    __hip_atomic_fetch_add(&d.chg_count[par], changes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (tid == 0) {
+    if (changes > 0) __hip_atomic_fetch_add(&d.chg_count[par], changes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    gl(d.vq_part)[b] = vq;
+    gl(d.zr_part)[b] = zr;
+  }
   if (b == 0) {
-    // per-RRH sums, xi' step, R, P, max delta (fixed-order trees)
+    // per-RRH sums, xi' step, R, P, max delta, C12 and C14 violations
+    // (fixed-order trees)
     reduce_groups<false>(s, d.psum_part, G, M, M, 1, s.psacc);
     reduce_groups<false>(s, d.pel_part, G, M, M, 1, s.peacc);
     reduce_groups<false>(s, d.R_part, G, 1, 1, 0, s.tmp);
     reduce_groups<true>(s, d.d_part, G, 1, 1, 0, s.tmp + 1);
-    if (update)
-      for (int m = tid; m < M; m += blockDim.x) {
-        const double ps = s.psacc[m];
-        const double scale = (double)d.N * d.L / (kLn2 * gl(d.pmax)[m]);
-        gl(d.xi)[m] = fmax(gl(d.xi)[m] + delta_v * scale * (ps - gl(d.pmax)[m]) / gl(d.pmax)[m], 0.0);
-      }
+    reduce_groups<false>(s, d.sv_part, G, 1, 1, 0, s.tmp + 2);
     if (tid == 0) {
-      double P = d.pstatic;
-      for (int m = 0; m < M; ++m) P += gl(d.eta)[m] * s.peacc[m];
+      double P = d.pstatic, Vp = 0.0, xr = 0.0;
+      for (int m = 0; m < M; ++m) {
+        const double ps = s.psacc[m], pmax = gl(d.pmax)[m];
+        P += gl(d.eta)[m] * s.peacc[m];
+        const double y = ps / pmax;
+        if (y > 1.0 + kBudgetTol) Vp += y - (1.0 + kBudgetTol);
+        if (update) {
+          double res;
+          gl(d.xi)[m] = xi_step(gl(d.xi)[m], ps, pmax, d.N, d.L, delta_v, &res);
+          xr = fmax(xr, res);
+        }
+      }
       store_shared(&d.red[0], s.tmp[0]);
       store_shared(&d.red[1], P);
       store_shared(&d.red[2], s.tmp[1]);
+      store_shared(&d.red[3], xr);
+      store_shared(&d.red[4], Vp);
+      store_shared(&d.red[5], s.tmp[2]);
     }
   }
 }
 
-// Loop control, identical in every workgroup (mirrors the Dinkelbach and
-// dual-loop stopping rules).
-// One step of the loop control from the reduced values of the pass just done.
-__device__ void advance(const Sched& sc, Ctrl& c, double R, double P, double dm, int changes) {
+// Two violations a (new) and b (best): -1 when a is lower by more than
+// kViolRel (relative), 1 when higher, 0 otherwise (zero equals only zero).
+__device__ inline int cmp_viol(double a, double b) {
+  if (a == 0.0 && b == 0.0) return 0;
+  if (a == 0.0) return -1;
+  if (b == 0.0) return 1;
+  if (a < b * (1.0 - kViolRel)) return -1;
+  if (a > b * (1.0 + kViolRel)) return 1;
+  return 0;
+}
+
+// Loop control, identical in every workgroup: one step from the reduced
+// values of the pass just done.  A sweep ranks the state it read against the
+// step's best and rotates the state buffers; the dual loop ends at its cap,
+// when the powers and every projected multiplier subgradient are below
+// tol_dual (and no user moved), or after `stall` sweeps without a better
+// state once the best is feasible.  The evaluation that follows reads the
+// best state; Dinkelbach's test (Sec. III) is the root condition
+// |R - E P| <= tol R on a feasible state, otherwise E <- R/P and the next
+// step starts from that state.  A warm start's first evaluation is of its
+// p^0, feasible or not: E^1 = R/P (F is strictly decreasing in E with its
+// root at the optimum, so the iteration converges from either side).
+__device__ void advance(const Sched& sc, Ctrl& c, const Eval& e) {
   if (c.mode == kSweep) {
     c.v += 1;
     c.total += 1;
     c.reset = 0;
-    const double delta = changes > 0 ? INFINITY : dm;
+    const double V = e.Vq + e.Vp, V2 = e.Vs, f = e.R - c.E * e.P;
+    bool replace = true, progress = true;
+    if (c.have_best) {
+      int r = cmp_viol(V, c.bV);
+      if (r == 0) r = cmp_viol(V2, c.bV2);
+      if (r != 0) {
+        replace = progress = r < 0;
+      } else {
+        replace = f > c.bf;
+        progress = f - c.bf > sc.tol_d * fabs(c.bR);
+      }
+    }
+    const int rd = c.rd, wr = c.wr;
+    if (replace) {
+      c.wr = c.have_best ? c.best : 3 - rd - wr;
+      c.best = rd;
+      c.have_best = 1;
+      c.bV = V;
+      c.bV2 = V2;
+      c.bf = f;
+      c.bR = e.R;
+    } else {
+      c.wr = rd;
+    }
+    c.rd = wr;
+    c.stall = progress ? 0 : c.stall + 1;
+    const double delta = e.changes > 0 ? INFINITY : fmax(fmax(e.dm, e.xres), e.zres);
     bool end = c.v >= sc.sweeps;
     if (isnan(delta)) {
       c.flags |= ALLOC_NONFINITE;
       end = true;
     }
-    if (!sc.fixed && delta < sc.tol_dual) end = true;
-    if (end) c.mode = kEval;
+    if (!sc.fixed) {
+      if (delta < sc.tol_dual) end = true;
+      if (sc.stall > 0 && c.stall >= sc.stall && c.bV == 0.0 && c.bV2 == 0.0) end = true;
+    }
+    if (end) {
+      c.mode = kEval;
+      if (c.have_best) c.rd = c.best;
+      c.wr = c.rd == 2 ? 0 : c.rd + 1;
+    }
   } else if (c.mode == kEval) {
-    c.R = R;
-    c.P = P;
-    const double F = R - c.E * P;
+    c.R = e.R;
+    c.P = e.P;
+    c.Vq = e.Vq;
+    c.Vp = e.Vp;
+    c.Vs = e.Vs;
+    const bool feasible = e.Vq == 0.0 && e.Vp == 0.0 && e.Vs == 0.0;
+    const double F = e.R - c.E * e.P;
     c.i += 1;
-    if (c.flags & ALLOC_NONFINITE) {
+    bool next = false;
+    if (c.first_eval) {
+      c.first_eval = 0;
+      if (c.i >= sc.max_d) {
+        c.flags |= ALLOC_NOT_CONVERGED;
+        c.mode = kDone;
+      } else {
+        c.E = e.R / e.P;
+        next = true;
+      }
+    } else if (c.flags & ALLOC_NONFINITE) {
       c.mode = kDone;
-    } else if (F <= sc.tol_d * R) {
+    } else if (feasible && fabs(F) <= sc.tol_d * e.R) {
       c.mode = kDone;
     } else if (c.i >= sc.max_d) {
       c.flags |= ALLOC_NOT_CONVERGED;
       c.mode = kDone;
     } else {
-      c.E = R / P;
+      c.E = e.R / e.P;
+      next = true;
+    }
+    if (next) {
       c.v = 0;
       c.reset = 1;
+      c.have_best = 0;
+      c.stall = 0;
       c.mode = kSweep;
     }
   }
@@ -1141,40 +1335,64 @@ __device__ void advance(const Sched& sc, Ctrl& c, double R, double P, double dm,
 }
 
 // Loop control of the grid solver, identical in every workgroup: the reduced
-// values are read with device-scope atomics after the grid barrier.
-__device__ void control(const Drop& d, const Sched& sc, Ctrl& c) {
-  const double R = load_shared(&d.red[0]), P = load_shared(&d.red[1]), dm = load_shared(&d.red[2]);
-  const int changes = c.mode == kSweep ? load_shared(&d.chg_count[c.pass & 1]) : 0;
-  advance(sc, c, R, P, dm, changes);
+// values are read with device-scope atomics after the grid barrier, the
+// per-workgroup C13 violations and zeta' steps by fixed-order trees.  The
+// workgroup's copy c sits in LDS; thread 0 advances it.
+__device__ void control(const Drop& d, const Sched& sc, Ctrl& c, Lds& s, int G) {
+  reduce_groups<false>(s, d.vq_part, G, 1, 1, 0, s.tmp);
+  reduce_groups<true>(s, d.zr_part, G, 1, 1, 0, s.tmp + 1);
+  Eval e;
+  e.R = load_shared(&d.red[0]);
+  e.P = load_shared(&d.red[1]);
+  e.dm = load_shared(&d.red[2]);
+  e.xres = load_shared(&d.red[3]);
+  e.Vp = load_shared(&d.red[4]);
+  e.Vs = load_shared(&d.red[5]);
+  e.Vq = s.tmp[0];
+  e.zres = s.tmp[1];
+  e.changes = c.mode == kSweep ? load_shared(&d.chg_count[c.pass & 1]) : 0;
+  __syncthreads();
+  if (threadIdx.x == 0) advance(sc, c, e);
+  __syncthreads();
+}
+
+__device__ inline PassConst pass_const(const Sched& sc, const Ctrl& c) {
+  const bool update = c.mode == kSweep;
+  PassConst pc;
+  pc.E = c.E;
+  pc.delta_v = sc.step0 / sqrt(1.0 + (double)c.v);
+  pc.refit = update && sc.refit_period > 0 && (c.v % sc.refit_period) == 0;
+  pc.reset = update && c.reset;
+  pc.update = update;
+  pc.write_out = !update;
+  pc.rd = c.rd;
+  pc.wr = c.wr;
+  return pc;
 }
 
 __global__ void __launch_bounds__(kGridBlock) solve_kernel(Drop d, Sched sc) {
   extern __shared__ __align__(16) char smem[];
   __shared__ Lds s_tab;
-  if (threadIdx.x == 0) carve_lds((LDS char*)smem, d.M, d.K, d.L, sc.tile, blockDim.x, &s_tab);
+  __shared__ Ctrl c;
+  if (threadIdx.x == 0) {
+    carve_lds((LDS char*)smem, d.M, d.K, d.L, sc.tile, blockDim.x, &s_tab);
+    c = *d.ctrl;
+  }
   __syncthreads();
   Lds& s = s_tab;
   cg::grid_group grid = cg::this_grid();
   const int b = blockIdx.x, G = gridDim.x;
-  Ctrl c = *d.ctrl;
   while (c.mode != kDone) {
-    const bool update = c.mode == kSweep;
-    PassConst pc;
-    pc.E = c.E;
-    pc.delta_v = sc.step0 / sqrt(1.0 + (double)c.v);
-    pc.refit = update && sc.refit_period > 0 && (c.v % sc.refit_period) == 0;
-    pc.reset = update && c.reset;
-    pc.update = update;
-    pc.write_out = !update;
-    begin_pass(d, s);
+    const PassConst pc = pass_const(sc, c);
+    begin_pass(d, s, c.rd);
     const int nb = (d.N - b + G - 1) / G;  // my subcarriers: b, b+G, ...
     for (int j = 0; j < nb; j += sc.tile) tile<false>(BlockTeam{(int)threadIdx.x, (int)blockDim.x}, d, sc, pc, s, b + j * G, G,
                                                    min(sc.tile, nb - j));
     write_partials(d, s, b);
     grid.sync();
-    reduce_pass(d, sc, c, s, b, G, update, pc.delta_v);
+    reduce_pass(d, sc, c, s, b, G, pc.update, pc.delta_v);
     grid.sync();
-    control(d, sc, c);
+    control(d, sc, c, s, G);
     if (b == 0 && threadIdx.x == 0) *d.ctrl = c;
   }
 }
@@ -1221,8 +1439,7 @@ __device__ void block_start(const Drop& d, Lds& s) {
         }
       if (wb >= 0) best = wb;
     }
-    gl(d.A)[k] = best;
-    gl(d.churn_A)[k] = 0;
+    gl(d.A)[k] = best;  // state buffer 0
     gl(d.zeta)[k] = gl(d.elastic)[k] ? 0.0 : (d.zeta0 ? fmax(gl(d.zeta0)[k], 0.0) : 1.0);
   }
   for (int m = tid; m < M; m += nth) gl(d.xi)[m] = d.xi0 ? fmax(gl(d.xi0)[m], 0.0) : 0.0;
@@ -1264,52 +1481,76 @@ __device__ void block_start(const Drop& d, Lds& s) {
       gl(d.be)[base + a] = 0.0;
       for (int b = 0; b < L; ++b) gl(d.zs)[(base + a) * L + b] = 0.0;
     }
-    gl(d.churn_sel)[i] = 0;
   }
   __syncthreads();
 }
 
+// Sum over the workgroup of one value per thread, by a fixed tree (wave
+// shuffles, then the waves in order); the total is returned to thread 0.
+__device__ double block_sum(double v, Lds& s) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  __syncthreads();  // s.red may still be read by the caller's previous use
+  if (lane == 0) s.red[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < nw; ++w) t += s.red[w];
+  return t;
+}
+
 // Reductions and multiplier steps of one pass from the workgroup's own
-// accumulators (it holds every subcarrier of the drop).
-__device__ void block_reduce(const Drop& d, const Sched& sc, const Ctrl& c, Lds& s, bool update,
-                             double delta_v, int* changes) {
+// accumulators (it holds every subcarrier of the drop); the pass's reduced
+// values go to thread 0's *e.
+__device__ void block_reduce(const Drop& d, const Sched& sc, int wr, Lds& s, bool update,
+                             double delta_v, int* changes, unsigned long long* zres, Eval* e) {
   const int M = d.M, K = d.K, tid = threadIdx.x, nth = blockDim.x;
+  double vq = 0.0;
   for (int k = tid; k < K; k += nth) {
     gl(d.user_rate)[k] = s.racc[k];
+    const bool el = gl(d.elastic)[k];
+    if (!el) vq += qos_viol(s.racc[k], gl(d.psi)[k]);
     if (!update) continue;
-    double best = -INFINITY;
-    int bm = 0;
-    for (int m = 0; m < M; ++m)
-      if (s.Sacc[m * K + k] > best) {
-        best = s.Sacc[m * K + k];
-        bm = m;
-      }
-    int ch_A = c.reset ? 0 : gl(d.churn_A)[k];
-    const int before = gl(d.A)[k];
-    if (!(sc.churn > 0 && ch_A >= sc.churn)) {
-      int after = before;
-      if (best > 0.0)
-        after = bm;
-      else if (gl(d.elastic)[k])
-        after = -1;
-      if (after != before) {
-        gl(d.A)[k] = after;
-        ++ch_A;
-        atomicAdd(changes, 1);
-      }
-    }
-    gl(d.churn_A)[k] = ch_A;
-    if (!gl(d.elastic)[k]) {
-      const double viol = fmin(fmax((gl(d.psi)[k] - s.rhacc[k]) / gl(d.psi)[k], -1.0), 1.0);
-      gl(d.zeta)[k] = fmax(gl(d.zeta)[k] + delta_v * viol, 0.0);
+    const int before = s.Al[k];
+    const int after = assoc_of(M, before, el, [&](int m) { return s.Sacc[m * K + k]; });
+    gl(d.A)[(size_t)wr * K + k] = after;
+    if (after != before) atomicAdd(changes, 1);
+    if (!el) {
+      double res;
+      gl(d.zeta)[k] = zeta_step(gl(d.zeta)[k], gl(d.psi)[k], s.rhacc[k], delta_v, sc.qos_down, &res);
+      if (res == res)
+        __hip_atomic_fetch_max((LDS unsigned long long*)zres, (unsigned long long)__double_as_longlong(res),
+                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
   }
-  if (update)
-    for (int m = tid; m < M; m += nth) {
-      const double ps = s.psacc[m];
-      const double scale = (double)d.N * d.L / (kLn2 * gl(d.pmax)[m]);
-      gl(d.xi)[m] = fmax(gl(d.xi)[m] + delta_v * scale * (ps - gl(d.pmax)[m]) / gl(d.pmax)[m], 0.0);
+  vq = block_sum(vq, s);
+  if (tid == 0) {
+    double R = 0.0, P = d.pstatic, dm = 0.0, Vp = 0.0, Vs = 0.0, xr = 0.0;
+    for (int m = 0; m < M; ++m) {
+      const double ps = s.psacc[m], pmax = gl(d.pmax)[m];
+      R += s.Racc[m];
+      P += gl(d.eta)[m] * s.peacc[m];
+      dm = fmax(dm, s.dmax[m]);
+      Vs += s.svacc[m];
+      const double y = ps / pmax;
+      if (y > 1.0 + kBudgetTol) Vp += y - (1.0 + kBudgetTol);
+      if (update) {
+        double res;
+        gl(d.xi)[m] = xi_step(gl(d.xi)[m], ps, pmax, d.N, d.L, delta_v, &res);
+        xr = fmax(xr, res);
+      }
     }
+    e->R = R;
+    e->P = P;
+    e->dm = dm;
+    e->Vq = vq;
+    e->Vp = Vp;
+    e->Vs = Vs;
+    e->xres = xr;
+    e->zres = __longlong_as_double((long long)*zres);
+    e->changes = *changes;
+  }
   __syncthreads();
 }
 
@@ -1354,18 +1595,18 @@ __device__ bool group_sync(unsigned* bar, int G) {
   return s_ok != 0;
 }
 
-__device__ inline Ctrl initial_ctrl(const Drop& d) {
+// Initial loop control: the initial state is in buffer 0; a warm start's
+// allocation (start_eval) is evaluated first.
+__host__ __device__ inline Ctrl initial_ctrl(double pstatic, int start_eval) {
   Ctrl c0;
-  c0.E = 0.0;
-  c0.R = 0.0;
-  c0.P = d.pstatic;
-  c0.i = 0;
-  c0.v = 0;
-  c0.mode = d.start_eval ? kEval : kSweep;
-  c0.total = 0;
+  memset(&c0, 0, sizeof c0);
+  c0.P = pstatic;
+  c0.mode = start_eval ? kEval : kSweep;
   c0.reset = 1;
-  c0.pass = 0;
-  c0.flags = 0;
+  c0.rd = 0;
+  c0.wr = 1;
+  c0.best = 2;
+  c0.first_eval = start_eval;
   return c0;
 }
 
@@ -1386,6 +1627,7 @@ __device__ __attribute__((always_inline)) void wave_pass(const Drop& d, const Sc
     v.peacc[m] = 0.0;
     v.Racc[m] = 0.0;
     v.dmax[m] = 0.0;
+    v.svacc[m] = 0.0;
   }
   tm.sync();
   const int nb = (d.N - w + W - 1) / W;  // subcarriers of this wave
@@ -1407,56 +1649,43 @@ __device__ __attribute__((always_inline)) void wave_pass(const Drop& d, const Sc
     s.rhacc[k] = rh;
   }
   for (int m = tid; m < M; m += nth) {
-    double ps = 0.0, pe = 0.0, R = 0.0, dm = 0.0;
+    double ps = 0.0, pe = 0.0, R = 0.0, dm = 0.0, sv = 0.0;
     for (int u = 0; u < W; ++u) {
       ps += sw[u].psacc[m];
       pe += sw[u].peacc[m];
       R += sw[u].Racc[m];
       dm = fmax(dm, sw[u].dmax[m]);
+      sv += sw[u].svacc[m];
     }
     s.psacc[m] = ps;
     s.peacc[m] = pe;
     s.Racc[m] = R;
     s.dmax[m] = dm;
+    s.svacc[m] = sv;
   }
   __syncthreads();
 }
 
 // A drop solved by one workgroup, every reduction inside it.
 __device__ __attribute__((always_inline)) void solve_single(const Drop& d, const Sched& sd, Lds& s, Lds* sw, Ctrl& s_c, int& s_changes,
-                             Ctrl* out) {
+                                                            unsigned long long& s_zres, Eval& s_e, Ctrl* out) {
   block_start(d, s);
-  if (threadIdx.x == 0) s_c = initial_ctrl(d);
+  if (threadIdx.x == 0) s_c = initial_ctrl(d.pstatic, d.start_eval);
   __syncthreads();
   while (s_c.mode != kDone) {
-    const Ctrl c = s_c;
-    const bool update = c.mode == kSweep;
-    PassConst pc;
-    pc.E = c.E;
-    pc.delta_v = sd.step0 / sqrt(1.0 + (double)c.v);
-    pc.refit = update && sd.refit_period > 0 && (c.v % sd.refit_period) == 0;
-    pc.reset = update && c.reset;
-    pc.update = update;
-    pc.write_out = !update;
-    if (threadIdx.x == 0) s_changes = 0;
-    begin_pass(d, s);
+    const PassConst pc = pass_const(sd, s_c);
+    if (threadIdx.x == 0) {
+      s_changes = 0;
+      s_zres = 0ull;
+    }
+    begin_pass(d, s, pc.rd);
     if (d.wave > 0)
       wave_pass(d, sd, pc, s, sw);
     else
       for (int n0 = 0; n0 < d.N; n0 += sd.tile)
         tile<true>(BlockTeam{(int)threadIdx.x, (int)blockDim.x}, d, sd, pc, s, n0, 1, min(sd.tile, d.N - n0));
-    block_reduce(d, sd, c, s, update, pc.delta_v, &s_changes);
-    if (threadIdx.x == 0) {
-      double R = 0.0, P = d.pstatic, dm = 0.0;
-      for (int m = 0; m < d.M; ++m) {
-        R += s.Racc[m];
-        P += gl(d.eta)[m] * s.peacc[m];
-        dm = fmax(dm, s.dmax[m]);
-      }
-      Ctrl cn = c;
-      advance(sd, cn, R, P, dm, s_changes);
-      s_c = cn;
-    }
+    block_reduce(d, sd, pc.wr, s, pc.update, pc.delta_v, &s_changes, &s_zres, &s_e);
+    if (threadIdx.x == 0) advance(sd, s_c, s_e);
     __syncthreads();
   }
   if (threadIdx.x == 0) *out = s_c;
@@ -1466,7 +1695,8 @@ __device__ __attribute__((always_inline)) void solve_single(const Drop& d, const
 // A drop solved by G workgroups together, this one of rank r: the grid
 // solver's pass (subcarriers r, r+G, ..., partials, fixed-order reductions)
 // with the group barrier in place of the grid barrier.
-__device__ __attribute__((always_inline)) void solve_group(const Drop& d, const Sched& sd, Lds& s, int r, int G, Ctrl* out) {
+__device__ __attribute__((always_inline)) void solve_group(const Drop& d, const Sched& sd, Lds& s, int r, int G, Ctrl& c,
+                                                           Ctrl* out) {
   if (r == 0) {
     if (threadIdx.x == 0) {
       store_shared(&d.chg_count[0], 0);
@@ -1474,32 +1704,28 @@ __device__ __attribute__((always_inline)) void solve_group(const Drop& d, const 
     }
     block_start(d, s);
   }
-  Ctrl c = initial_ctrl(d);
+  if (threadIdx.x == 0) c = initial_ctrl(d.pstatic, d.start_eval);
   bool ok = group_sync(d.bar, G);
   while (ok && c.mode != kDone) {
-    const bool update = c.mode == kSweep;
-    PassConst pc;
-    pc.E = c.E;
-    pc.delta_v = sd.step0 / sqrt(1.0 + (double)c.v);
-    pc.refit = update && sd.refit_period > 0 && (c.v % sd.refit_period) == 0;
-    pc.reset = update && c.reset;
-    pc.update = update;
-    pc.write_out = !update;
-    begin_pass(d, s);
+    const PassConst pc = pass_const(sd, c);
+    begin_pass(d, s, c.rd);
     const int nb = (d.N - r + G - 1) / G;
     for (int j = 0; j < nb; j += sd.tile) tile<false>(BlockTeam{(int)threadIdx.x, (int)blockDim.x}, d, sd, pc, s, r + j * G, G,
                                                    min(sd.tile, nb - j));
     write_partials(d, s, r);
     if (!(ok = group_sync(d.bar, G))) break;
-    reduce_pass(d, sd, c, s, r, G, update, pc.delta_v);
+    reduce_pass(d, sd, c, s, r, G, pc.update, pc.delta_v);
     if (!(ok = group_sync(d.bar, G))) break;
-    control(d, sd, c);
+    control(d, sd, c, s, G);
   }
-  if (!ok) {
-    c.flags |= ALLOC_GROUP_TIMEOUT;
-    c.mode = kDone;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (!ok) {
+      c.flags |= ALLOC_GROUP_TIMEOUT;
+      c.mode = kDone;
+    }
+    if (r == 0 || !ok) *out = c;
   }
-  if ((r == 0 || !ok) && threadIdx.x == 0) *out = c;
   __syncthreads();
 }
 
@@ -1513,6 +1739,8 @@ __global__ void __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(4))
 batch_kernel(const Drop* __restrict__ drops, const int2* __restrict__ slots, int S, Sched sc, int* queue, Ctrl* ctrls) {
   extern __shared__ __align__(16) char smem[];
   __shared__ int s_idx, s_changes;
+  __shared__ unsigned long long s_zres;
+  __shared__ Eval s_e;
   __shared__ Ctrl s_c;
   __shared__ Lds s_tab;
   __shared__ Lds s_wtab[kBlock / 64];
@@ -1534,9 +1762,9 @@ batch_kernel(const Drop* __restrict__ drops, const int2* __restrict__ slots, int
     }
     __syncthreads();
     if (d.group <= 1)
-      solve_single(d, sd, s_tab, s_wtab, s_c, s_changes, ctrls + sl.x);
+      solve_single(d, sd, s_tab, s_wtab, s_c, s_changes, s_zres, s_e, ctrls + sl.x);
     else
-      solve_group(d, sd, s_tab, sl.y, d.group, ctrls + sl.x);
+      solve_group(d, sd, s_tab, sl.y, d.group, s_c, ctrls + sl.x);
   }
 }
 
@@ -1578,8 +1806,7 @@ __global__ void cold_pick_kernel(Drop d, const double* snr, const double* p0sum)
     }
     if (wb >= 0) best = wb;
   }
-  gl(d.A)[k] = best;
-  gl(d.churn_A)[k] = 0;
+  gl(d.A)[k] = best;  // state buffer 0
   gl(d.zeta)[k] = gl(d.elastic)[k] ? 0.0 : 1.0;
 }
 
@@ -1624,7 +1851,6 @@ __global__ void cold_select_kernel(Drop d, const double* p0) {
     gl(d.be)[base + a] = 0.0;
     for (int b = 0; b < L; ++b) gl(d.zs)[(base + a) * L + b] = 0.0;
   }
-  gl(d.churn_sel)[i] = 0;
 }
 
 __global__ void p0_sum_kernel(Drop d, const double* p0, double* out) {
@@ -1650,6 +1876,24 @@ __global__ void dense_kernel(Drop d, float* out) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total;
        i += (size_t)gridDim.x * blockDim.x)
     out[i] = 0.0f;
+}
+
+// The RRH that serves each user in the returned selection (-1 unserved):
+// cleared, then written by the (m,n) whose slots hold the user (one RRH per
+// user, since one sweep's selection follows one association).
+__global__ void rrh_clear_kernel(int K, int* rrh) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < K) rrh[k] = -1;
+}
+
+__global__ void rrh_from_sel_kernel(Drop d, int* rrh) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= d.M * d.N) return;
+  const int m = i / d.N;
+  for (int a = 0; a < d.L; ++a) {
+    const int k = gl(d.out_sel)[(size_t)i * d.L + a];
+    if (k >= 0) rrh[k] = m;
+  }
 }
 
 __global__ void scatter_kernel(Drop d, float* out) {
@@ -1740,10 +1984,11 @@ void alloc_params_default(alloc_params* p) {
   p->sweeps_per_dinkelbach = 200;
   p->refit_period = 1;
   p->fixed_count = 1;
-  p->churn_limit = 8;
+  p->stall_sweeps = 30;
   p->tol_dinkelbach = 1e-6;
   p->tol_dual = 1e-7;
   p->step0 = 0.1;
+  p->qos_down = 0.2;
   p->flags = 0;
   p->max_groups = 0;
   p->tile = 0;
@@ -1785,6 +2030,8 @@ int alloc_ctx_create(int device, void* hip_stream, alloc_ctx** out) {
   c->lds_max = prop.sharedMemPerBlock;
   c->timing = 0;
   c->last_ms = -1.0;
+  c->refs = 0;
+  c->closed = 0;
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
     delete c;
     return ALLOC_EDEVICE;
@@ -1799,7 +2046,11 @@ int alloc_ctx_create(int device, void* hip_stream, alloc_ctx** out) {
 }
 
 void alloc_ctx_destroy(alloc_ctx* c) {
-  if (!c) return;
+  if (!c || c->closed) return;
+  if (c->refs > 0) {  // batches or networks still use it: freed with the last of them
+    c->closed = 1;
+    return;
+  }
   (void)hipSetDevice(c->device);
   if (c->ws) (void)hipFree(c->ws);
   (void)hipEventDestroy(c->ev0);
@@ -1810,6 +2061,38 @@ void alloc_ctx_destroy(alloc_ctx* c) {
 }  // extern "C"
 
 namespace alloc_internal {
+
+void ctx_retain(alloc_ctx* c) { ++c->refs; }
+
+void ctx_release(alloc_ctx* c) {
+  if (--c->refs == 0 && c->closed) {
+    c->closed = 0;
+    alloc_ctx_destroy(c);
+  }
+}
+
+}  // namespace alloc_internal
+
+namespace alloc_internal {
+
+// Scalars and flags of a result from the final loop control and rates.
+void finish_result(const Ctrl& cf, const double* ur, int K, alloc_result* res) {
+  uint32_t flags = cf.flags;
+  if (cf.Vq > 0.0) flags |= ALLOC_QOS_INFEASIBLE;
+  if (cf.Vp > 0.0) flags |= ALLOC_BUDGET_INFEASIBLE;
+  if (cf.Vs > 0.0) flags |= ALLOC_SIC_INFEASIBLE;
+  for (int k = 0; k < K; ++k)
+    if (!std::isfinite(ur[k])) flags |= ALLOC_NONFINITE;
+  res->ee = cf.P > 0.0 ? cf.R / cf.P : 0.0;
+  res->rate_sum = cf.R;
+  res->power_sum = cf.P;
+  res->viol_qos = cf.Vq;
+  res->viol_budget = cf.Vp;
+  res->viol_sic = cf.Vs;
+  res->dinkelbach_iters = cf.i;
+  res->sweeps = cf.total;
+  res->status_flags = flags;
+}
 
 int solve_one(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, const alloc_warm* warm,
               const DevWarm* dev, alloc_result* res) {
@@ -1870,16 +2153,17 @@ int solve_one(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, 
   const size_t oEta = lay.add(sizeof(double) * M);
   const size_t oPmask = lay.add(sizeof(double) * M);
   const size_t oW = lay.add(pb->weight ? sizeof(double) * M * K : 0);
-  const size_t oA = lay.add(sizeof(int) * K);
-  const size_t oSel = lay.add(sizeof(int) * ns);
-  const size_t oP = lay.add(sizeof(double) * ns);
-  const size_t oAl = lay.add(sizeof(double) * ns);
-  const size_t oBe = lay.add(sizeof(double) * ns);
-  const size_t oZs = lay.add(sizeof(double) * ns * L);
+  const size_t oA = lay.add(sizeof(int) * 3 * K);  // three state buffers
+  const size_t oSel = lay.add(sizeof(int) * 3 * ns);
+  const size_t oP = lay.add(sizeof(double) * 3 * ns);
+  const size_t oAl = lay.add(sizeof(double) * 3 * ns);
+  const size_t oBe = lay.add(sizeof(double) * 3 * ns);
+  const size_t oZs = lay.add(sizeof(double) * 3 * ns * L);
   const size_t oXi = lay.add(sizeof(double) * M);
   const size_t oZeta = lay.add(sizeof(double) * K);
-  const size_t oChS = lay.add(sizeof(int) * M * N);
-  const size_t oChA = lay.add(sizeof(int) * K);
+  const size_t oSvp = lay.add(sizeof(double) * G);
+  const size_t oVqp = lay.add(sizeof(double) * G);
+  const size_t oZrp = lay.add(sizeof(double) * G);
   const size_t oSp = lay.add(sizeof(double) * G * M * K);
   const size_t oRp = lay.add(sizeof(double) * G * K);
   const size_t oRhp = lay.add(sizeof(double) * G * K);
@@ -1888,8 +2172,9 @@ int solve_one(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, 
   const size_t oRP = lay.add(sizeof(double) * G);
   const size_t oDp = lay.add(sizeof(double) * G);
   const size_t oChg = lay.add(sizeof(int) * 2);
-  const size_t oRed = lay.add(sizeof(double) * 4);
+  const size_t oRed = lay.add(sizeof(double) * 8);
   const size_t oUr = lay.add(sizeof(double) * K);
+  const size_t oRrh = lay.add(sizeof(int) * K);
   const size_t oOs = lay.add(sizeof(int) * ns);
   const size_t oOp = lay.add(sizeof(double) * ns);
   const size_t oOz = lay.add(sizeof(double) * (size_t)M * N * (NP > 0 ? NP : 1));
@@ -1922,11 +2207,8 @@ int solve_one(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, 
   if (h_p0) ok = ok && h2d(oP0, warm->p0, sizeof(double) * n3);
   if (h_xi) ok = ok && h2d(oXi0, warm->xi0, sizeof(double) * M);
   if (h_z) ok = ok && h2d(oZ0, warm->zeta0, sizeof(double) * K);
-  Ctrl c0;
-  memset(&c0, 0, sizeof c0);
   // a warm initial allocation is Dinkelbach's p^0: evaluate it first
-  c0.mode = has_p0 ? kEval : kSweep;
-  c0.reset = 1;
+  const Ctrl c0 = initial_ctrl(pstatic, has_p0);
   ok = ok && h2d(oCtrl, &c0, sizeof c0);
   static const int zeros2[2] = {0, 0};
   ok = ok && h2d(oChg, zeros2, sizeof zeros2);
@@ -1954,8 +2236,9 @@ int solve_one(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, 
   d.zs = (double*)(ws + oZs);
   d.xi = (double*)(ws + oXi);
   d.zeta = (double*)(ws + oZeta);
-  d.churn_sel = (int*)(ws + oChS);
-  d.churn_A = (int*)(ws + oChA);
+  d.sv_part = (double*)(ws + oSvp);
+  d.vq_part = (double*)(ws + oVqp);
+  d.zr_part = (double*)(ws + oZrp);
   d.S_part = (double*)(ws + oSp);
   d.r_part = (double*)(ws + oRp);
   d.rh_part = (double*)(ws + oRhp);
@@ -1992,10 +2275,11 @@ int solve_one(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, 
   sc.sweeps = prm->sweeps_per_dinkelbach;
   sc.refit_period = prm->refit_period;
   sc.fixed = prm->fixed_count;
-  sc.churn = prm->churn_limit;
+  sc.stall = prm->stall_sweeps;
   sc.tol_d = prm->tol_dinkelbach;
   sc.tol_dual = prm->tol_dual;
   sc.step0 = prm->step0;
+  sc.qos_down = prm->qos_down;
   sc.tile = T;
   void* args[] = {(void*)&d, (void*)&sc};
   if (ctx->timing && hipEventRecord(ctx->ev0, st) != hipSuccess) return ALLOC_EDEVICE;
@@ -2005,12 +2289,16 @@ int solve_one(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, 
   if (ctx->timing && hipEventRecord(ctx->ev1, st) != hipSuccess) return ALLOC_EDEVICE;
 
   // outputs
+  int* rrh = (int*)(ws + oRrh);
+  hipLaunchKernelGGL(rrh_clear_kernel, dim3((K + tb - 1) / tb), dim3(tb), 0, st, K, rrh);
+  hipLaunchKernelGGL(rrh_from_sel_kernel, dim3((M * N + tb - 1) / tb), dim3(tb), 0, st, d, rrh);
+  if (hipGetLastError() != hipSuccess) return ALLOC_EDEVICE;
   const hipMemcpyKind kind = out_dev ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
   auto d2o = [&](void* dst, const void* src, size_t bytes) {
     return !dst || hipMemcpyAsync(dst, src, bytes, kind, st) == hipSuccess;
   };
   ok = d2o(res->sel, d.out_sel, sizeof(int) * ns) && d2o(res->slot_power, d.out_p, sizeof(double) * ns) &&
-       d2o(res->rrh_of_user, d.A, sizeof(int) * K) && d2o(res->xi, d.xi, sizeof(double) * M) &&
+       d2o(res->rrh_of_user, rrh, sizeof(int) * K) && d2o(res->xi, d.xi, sizeof(double) * M) &&
        d2o(res->zeta, d.zeta, sizeof(double) * K) && d2o(res->user_rate, d.user_rate, sizeof(double) * K);
   if (NP > 0) ok = ok && d2o(res->zeta_sic, d.out_zs, sizeof(double) * M * N * NP);
   if (!ok) return ALLOC_EDEVICE;
@@ -2042,25 +2330,15 @@ int solve_one(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, 
     if (hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1) != hipSuccess) return ALLOC_EDEVICE;
     ctx->last_ms = ms;
   }
-  uint32_t flags = cf.flags;
-  for (int k = 0; k < K; ++k) {
-    if (!el[k] && ur[k] < psi[k] * (1.0 - 1e-6)) flags |= ALLOC_QOS_INFEASIBLE;
-    if (!std::isfinite(ur[k])) flags |= ALLOC_NONFINITE;
-  }
-  res->ee = cf.P > 0.0 ? cf.R / cf.P : 0.0;
-  res->rate_sum = cf.R;
-  res->power_sum = cf.P;
-  res->dinkelbach_iters = cf.i;
-  res->sweeps = cf.total;
-  res->status_flags = flags;
+  finish_result(cf, ur.data(), K, res);
   return ALLOC_OK;
 }
 
 // Host side of one batched solve: the packed device layout of every drop's
 // inputs, state and outputs, the drop descriptors and the launch shape.
 struct BatchOff {
-  size_t G, psi, el, pmax, eta, pmask, w, A, sel, p, al, be, zs, xi, zeta, chs, cha, ur, os, op, oz;
-  size_t Sp, rp, rhp, psp, pep, Rp, dp, chg, red, bar;  // group drops only
+  size_t G, psi, el, pmax, eta, pmask, w, A, sel, p, al, be, zs, xi, zeta, ur, os, op, oz;
+  size_t Sp, rp, rhp, psp, pep, Rp, dp, svp, vqp, zrp, chg, red, bar;  // group drops only
   size_t wp0, wxi, wz;                                  // host warm starts, staged
 };
 
@@ -2083,8 +2361,12 @@ struct BatchPlan {
   size_t lds = 0;
 };
 
-__global__ void reset_queue_kernel(int* q) {
-  if (threadIdx.x == 0) *q = 0;
+// Start of a batched solve: the work queue and every group barrier (arrival
+// count, generation, broken flag) cleared by a kernel, so a captured graph
+// holds no memset node and a replay after a timed-out group starts clean.
+__global__ void reset_queue_kernel(int* q, unsigned* bars, int nbar) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *q = 0;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nbar; i += gridDim.x * blockDim.x) bars[i] = 0u;
 }
 
 // Validates, lays out and uploads the drops' inputs into *buf (grown to fit,
@@ -2188,7 +2470,6 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
     P.off[b].os = add(sizeof(int) * M * N * L);
     P.off[b].op = add(sizeof(double) * M * N * L);
     P.off[b].oz = add(sizeof(double) * M * N * (NP > 0 ? NP : 1));
-    P.off[b].A = add(sizeof(int) * K);
     P.off[b].xi = add(sizeof(double) * M);
     P.off[b].zeta = add(sizeof(double) * K);
     P.off[b].ur = add(sizeof(double) * K);
@@ -2204,13 +2485,12 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
   for (int b = 0; b < B; ++b) {
     const alloc_problem& pb = probs[b];
     const size_t M = pb.M, N = pb.N, K = pb.K, L = pb.l;
-    P.off[b].sel = add(sizeof(int) * M * N * L);
-    P.off[b].p = add(sizeof(double) * M * N * L);
-    P.off[b].al = add(sizeof(double) * M * N * L);
-    P.off[b].be = add(sizeof(double) * M * N * L);
-    P.off[b].zs = add(sizeof(double) * M * N * L * L);
-    P.off[b].chs = add(sizeof(int) * M * N);
-    P.off[b].cha = add(sizeof(int) * K);
+    P.off[b].A = add(sizeof(int) * 3 * K);  // three state buffers
+    P.off[b].sel = add(sizeof(int) * 3 * M * N * L);
+    P.off[b].p = add(sizeof(double) * 3 * M * N * L);
+    P.off[b].al = add(sizeof(double) * 3 * M * N * L);
+    P.off[b].be = add(sizeof(double) * 3 * M * N * L);
+    P.off[b].zs = add(sizeof(double) * 3 * M * N * L * L);
     P.off[b].G = add(gain_dev ? 0 : sizeof(float) * M * N * K);
     const size_t g = P.group[b];
     if (g > 1) {
@@ -2221,8 +2501,11 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
       P.off[b].pep = add(sizeof(double) * g * M);
       P.off[b].Rp = add(sizeof(double) * g);
       P.off[b].dp = add(sizeof(double) * g);
+      P.off[b].svp = add(sizeof(double) * g);
+      P.off[b].vqp = add(sizeof(double) * g);
+      P.off[b].zrp = add(sizeof(double) * g);
       P.off[b].chg = add(sizeof(int) * 2);
-      P.off[b].red = add(sizeof(double) * 4);
+      P.off[b].red = add(sizeof(double) * 8);
     }
   }
   P.bar_begin = tot;
@@ -2294,8 +2577,6 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
     d.zs = (double*)(ws + o.zs);
     d.xi = (double*)(ws + o.xi);
     d.zeta = (double*)(ws + o.zeta);
-    d.churn_sel = (int*)(ws + o.chs);
-    d.churn_A = (int*)(ws + o.cha);
     d.user_rate = (double*)(ws + o.ur);
     d.out_sel = (int*)(ws + o.os);
     d.out_p = (double*)(ws + o.op);
@@ -2310,6 +2591,9 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
       d.pel_part = (double*)(ws + o.pep);
       d.R_part = (double*)(ws + o.Rp);
       d.d_part = (double*)(ws + o.dp);
+      d.sv_part = (double*)(ws + o.svp);
+      d.vq_part = (double*)(ws + o.vqp);
+      d.zr_part = (double*)(ws + o.zrp);
       d.chg_count = (int*)(ws + o.chg);
       d.red = (double*)(ws + o.red);
       d.bar = (unsigned*)(ws + o.bar);
@@ -2336,9 +2620,6 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
     for (int b = 0; b < B && ok; ++b)
       ok = hipMemcpyAsync(ws + P.off[b].G, probs[b].gain, sizeof(float) * probs[b].M * probs[b].N * probs[b].K,
                           hipMemcpyHostToDevice, st) == hipSuccess;
-  // group barriers start at zero (each solve leaves its arrival count at zero)
-  if (ok && P.bar_end > P.bar_begin)
-    ok = hipMemsetAsync(ws + P.bar_begin, 0, P.bar_end - P.bar_begin, st) == hipSuccess;
   if (!ok) return ALLOC_EDEVICE;
 
   Sched& sc = P.sc;
@@ -2346,10 +2627,11 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
   sc.sweeps = prm->sweeps_per_dinkelbach;
   sc.refit_period = prm->refit_period;
   sc.fixed = prm->fixed_count;
-  sc.churn = prm->churn_limit;
+  sc.stall = prm->stall_sweeps;
   sc.tol_d = prm->tol_dinkelbach;
   sc.tol_dual = prm->tol_dual;
   sc.step0 = prm->step0;
+  sc.qos_down = prm->qos_down;
   sc.tile = 1;
   P.lds = budget;
   P.grid = std::min(S, cap);
@@ -2408,7 +2690,9 @@ int batch_upload(hipStream_t st, const BatchPlan& P) {
 // The batched solve proper: queue reset and the persistent kernel (no host
 // copies or memsets, so the pair can be captured into a graph).
 int batch_enqueue(hipStream_t st, const BatchPlan& P) {
-  hipLaunchKernelGGL(reset_queue_kernel, dim3(1), dim3(64), 0, st, (int*)(P.ws + P.oQueue));
+  const int nbar = (int)((P.bar_end - P.bar_begin) / sizeof(unsigned));
+  hipLaunchKernelGGL(reset_queue_kernel, dim3(std::max(1, std::min(1024, (nbar + 255) / 256))), dim3(256), 0, st,
+                     (int*)(P.ws + P.oQueue), (unsigned*)(P.ws + P.bar_begin), nbar);
   hipLaunchKernelGGL(batch_kernel, dim3(P.grid), dim3(P.threads), P.lds, st, (const Drop*)(P.ws + P.oDrops),
                      (const int2*)(P.ws + P.oSlots), (int)P.slots.size(), P.sc, (int*)(P.ws + P.oQueue),
                      (Ctrl*)(P.ws + P.oCtrls));
@@ -2431,7 +2715,13 @@ int batch_collect(hipStream_t st, const BatchPlan& P, alloc_result* results) {
     if (r.sel) memcpy(r.sel, src(o.os), sizeof(int) * M * N * L);
     if (r.slot_power) memcpy(r.slot_power, src(o.op), sizeof(double) * M * N * L);
     if (r.zeta_sic && NP > 0) memcpy(r.zeta_sic, src(o.oz), sizeof(double) * M * N * NP);
-    if (r.rrh_of_user) memcpy(r.rrh_of_user, src(o.A), sizeof(int) * K);
+    if (r.rrh_of_user) {  // the RRH whose slots hold each user, -1 unserved
+      const int* os = (const int*)src(o.os);
+      for (size_t k = 0; k < K; ++k) r.rrh_of_user[k] = -1;
+      for (size_t i = 0; i < M * N; ++i)
+        for (size_t a = 0; a < L; ++a)
+          if (os[i * L + a] >= 0) r.rrh_of_user[os[i * L + a]] = (int)(i / N);
+    }
     if (r.xi) memcpy(r.xi, src(o.xi), sizeof(double) * M);
     if (r.zeta) memcpy(r.zeta, src(o.zeta), sizeof(double) * K);
     const double* ur = (const double*)src(o.ur);
@@ -2444,18 +2734,7 @@ int batch_collect(hipStream_t st, const BatchPlan& P, alloc_result* results) {
         for (size_t a = 0; a < L; ++a)
           if (os[i * L + a] >= 0) r.power[i * K + os[i * L + a]] = (float)op[i * L + a];
     }
-    const Ctrl& cf = ctrls[b];
-    uint32_t flags = cf.flags;
-    for (size_t k = 0; k < K; ++k) {
-      if (!P.els[b][k] && ur[k] < P.psis[b][k] * (1.0 - 1e-6)) flags |= ALLOC_QOS_INFEASIBLE;
-      if (!std::isfinite(ur[k])) flags |= ALLOC_NONFINITE;
-    }
-    r.ee = cf.P > 0.0 ? cf.R / cf.P : 0.0;
-    r.rate_sum = cf.R;
-    r.power_sum = cf.P;
-    r.dinkelbach_iters = cf.i;
-    r.sweeps = cf.total;
-    r.status_flags = flags;
+    finish_result(ctrls[b], ur, (int)K, &r);
   }
   return ALLOC_OK;
 }
@@ -2489,7 +2768,7 @@ extern "C" {
 
 int alloc_solve(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, const alloc_warm* warm,
                 alloc_result* res) {
-  if (!prm) return ALLOC_EINVAL;
+  if (!prm || (ctx && ctx->closed)) return ALLOC_EINVAL;
   if (warm && (prm->flags & ALLOC_WARM_ON_DEVICE)) {
     const alloc_internal::DevWarm dw{warm->p0, warm->xi0, warm->zeta0};
     return alloc_internal::solve_one(ctx, pb, prm, nullptr, &dw, res);
@@ -2515,14 +2794,16 @@ void alloc_batch_destroy(alloc_batch* b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   if (b->cap) (void)hipStreamDestroy(b->cap);
   if (b->buf) (void)hipFree(b->buf);
+  alloc_internal::ctx_release(b->ctx);
   delete b;
 }
 
 int alloc_batch_create(alloc_ctx* ctx, int32_t B, const alloc_problem* probs, const alloc_params* prm,
                        alloc_batch** out) {
-  if (!ctx || !out) return ALLOC_EINVAL;
+  if (!ctx || !out || ctx->closed) return ALLOC_EINVAL;
   alloc_batch* b = new alloc_batch();
   b->ctx = ctx;
+  alloc_internal::ctx_retain(ctx);
   b->last_ms = -1.0;
   int rc = alloc_internal::batch_prepare(ctx, B, probs, prm, nullptr, &b->buf, &b->bytes, b->plan);
   if (rc == ALLOC_OK) rc = alloc_internal::batch_upload(ctx->stream, b->plan);
@@ -2572,7 +2853,7 @@ double alloc_batch_last_ms(alloc_batch* b) { return b ? b->last_ms : -1.0; }
 
 int alloc_solve_batch(alloc_ctx* ctx, int32_t B, const alloc_problem* probs, const alloc_params* prm,
                       const alloc_warm* warms, alloc_result* results) {
-  if (!prm) return ALLOC_EINVAL;
+  if (!prm || (ctx && ctx->closed)) return ALLOC_EINVAL;
   if (warms && (prm->flags & ALLOC_WARM_ON_DEVICE)) {
     const alloc_internal::WarmFn fn = [warms](int b, alloc_internal::DevWarm* w) {
       w->p0 = warms[b].p0;

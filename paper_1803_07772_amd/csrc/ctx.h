@@ -18,9 +18,16 @@ struct alloc_ctx {
   int timing;
   hipEvent_t ev0, ev1;
   double last_ms;
+  int refs;    // live batches and networks made on this context
+  int closed;  // alloc_ctx_destroy was called while refs > 0: freed with the last of them
 };
 
 namespace alloc_internal {
+
+// A batch or network made on the context holds it; the context is freed when
+// it was destroyed and its last holder goes.
+void ctx_retain(alloc_ctx* c);
+void ctx_release(alloc_ctx* c);
 
 // A warm start held in device memory (float64); any pointer may be null.
 struct DevWarm {

@@ -1123,15 +1123,20 @@ WarmArrays warm_arrays(int64_t n3, int M, int K) {
 }
 
 // The warm-started solve is replaced by the cold one when it ended
-// non-finite or with no allocation at all (EE not positive).
-bool needs_fallback(const alloc_result& r) { return (r.status_flags & ALLOC_NONFINITE) || !(r.ee > 0.0); }
+// non-finite, with no allocation at all (EE not positive), or infeasible: a
+// streaming user below its minimum rate (C13), an RRH over its budget (C12)
+// or a co-scheduled pair that breaks SIC decodability (C14).
+bool needs_fallback(const alloc_result& r) {
+  return (r.status_flags & (ALLOC_NONFINITE | ALLOC_QOS_INFEASIBLE | ALLOC_BUDGET_INFEASIBLE | ALLOC_SIC_INFEASIBLE)) ||
+         !(r.ee > 0.0);
+}
 
 }  // namespace
 
 extern "C" {
 
 int alloc_mlp_create(alloc_ctx* ctx, alloc_mlp** out) {
-  if (!ctx || !out) return ALLOC_EINVAL;
+  if (!ctx || !out || ctx->closed) return ALLOC_EINVAL;
   if (hipSetDevice(ctx->device) != hipSuccess) return ALLOC_EDEVICE;
   alloc_mlp* n = new alloc_mlp;
   memset(n, 0, sizeof *n);
@@ -1155,6 +1160,7 @@ int alloc_mlp_create(alloc_ctx* ctx, alloc_mlp** out) {
     delete n;
     return ALLOC_EDEVICE;
   }
+  alloc_internal::ctx_retain(ctx);
   *out = n;
   return ALLOC_OK;
 }
@@ -1164,6 +1170,7 @@ void alloc_mlp_destroy(alloc_mlp* net) {
   (void)hipSetDevice(net->ctx->device);
   (void)hipFree(net->master);
   if (net->ws) (void)hipFree(net->ws);
+  alloc_internal::ctx_release(net->ctx);
   delete net;
 }
 

@@ -17,7 +17,7 @@ from . import (AllocError, Context, Params, _Params, _Problem, _Result, _check, 
 
 NIN, HID, NOUT = 4, 256, 3
 N_PARAMS = 133635
-WARM_FALLBACK = 16
+WARM_FALLBACK = 128
 SHAPES = (("W1", (HID, NIN)), ("b1", (HID,)), ("W2", (HID, HID)), ("b2", (HID,)),
           ("W3", (HID, HID)), ("b3", (HID,)), ("W4", (NOUT, HID)), ("b4", (NOUT,)))
 
@@ -224,7 +224,8 @@ class MLP:
 
     def solve(self, drop, params: Params | None = None, gain=None, dense_power=False):
         """Network inference, then the solve from that warm start (cold-start
-        fallback when the warm solve ends non-finite or QoS-infeasible)."""
+        fallback when the warm solve ends non-finite, empty, or infeasible
+        for C12, C13 or C14)."""
         keep = []
         pb, flags = problem_struct(drop, keep, gain)
         res, out, dense = result_struct(drop, dense_power)

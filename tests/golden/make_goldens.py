@@ -26,10 +26,14 @@ def cfg3(seed=0):
         gain_sha256=np.frombuffer(hashlib.sha256(d.gain.tobytes()).digest(), np.uint8),
         sel=r.sel.astype(np.int16), slot_power=r.slot_power, rrh_of_user=r.rrh_of_user,
         xi=r.xi, zeta=r.zeta, zeta_sic=r.zeta_sic, user_rate=r.user_rate,
+        tie_mn=r.tie_mn, tie_user=r.tie_user,
         scalars=np.array([r.ee, r.rate_sum, r.power_sum, r.min_margin]),
-        ints=np.array([r.dinkelbach_iters, r.sweeps, r.status_flags, r.near_ties]))
-    print("cfg3 seed", seed, "ee", r.ee, "iters", r.dinkelbach_iters, "ties", r.near_ties,
-          "min margin", r.min_margin)
+        viol=np.array([r.viol_qos, r.viol_budget, r.viol_sic]),
+        ints=np.array([r.dinkelbach_iters, r.sweeps, r.status_flags, r.near_ties, r.first_tie_sweep]))
+    print("cfg3 seed", seed, "ee", r.ee, "iters", r.dinkelbach_iters, "flags", r.status_flags,
+          "ties", r.near_ties, "first tie sweep", r.first_tie_sweep, "min margin", r.min_margin,
+          "violations (C13, C12, C14)", r.viol_qos, r.viol_budget, r.viol_sic,
+          "flagged (m,n)", int((r.tie_mn > 0).sum()), "flagged users", int((r.tie_user > 0).sum()))
 
 
 if __name__ == "__main__":

@@ -7,6 +7,7 @@ import pytest
 import oracle
 import synth
 from tests import parity
+from tests.gpu_util import gpu_params
 
 pytestmark = pytest.mark.gpu
 
@@ -45,18 +46,15 @@ def test_batch_matches_oracle_per_drop(ctx):
     print(f"[gpu case] batch of {len(drops)} mixed drops", flush=True)
     gains = [torch.from_numpy(d.gain).cuda() for d in drops]
     res = ctx.solve_batch(drops, p, gains=gains)
-    chaotic = 0
+    diverged = 0
     for d, r in zip(drops, res):
         o = oracle.solve(d, op)
-
-        def rerun(scale, d=d):
-            return oracle.solve(dataclasses.replace(d, noise_w=d.noise_w * scale), op)
-
         info = parity.compare(d, r, o, label=f"batch drop {d.index} {d.M}x{d.N}x{d.K} l={d.l}",
-                              rerun=rerun)
+                              allow_diverged=True)
+        parity.check_structure(d, r)
         print(info, flush=True)
-        chaotic += bool(info.get("skipped"))
-    assert chaotic <= 3
+        diverged += bool(info.get("diverged"))
+    assert diverged <= 1
 
 
 def test_batch_host_gains_and_dense(ctx):
@@ -90,26 +88,28 @@ def test_batch_agrees_with_plain_solver(ctx):
 
 
 def test_batch_cfg4_generator_subset(ctx):
-    """Drops of the ragged 4096-drop configuration (a seeded subset of sizes
-    the oracle finishes quickly), solved in one batch with larger ones."""
+    """Drops of the ragged 4096-drop configuration's generator, the smallest
+    and the largest of 64 among them, solved in one batch: every drop
+    against the oracle."""
     import torch
 
     import paper_1803_07772_amd as pa
     M, N, K = synth.batch_sizes(64, seed=0)
-    idx = [b for b in range(64) if M[b] * N[b] * K[b] <= 60000][:6] + [int(np.argmax(M * N * K))]
+    work = M * N * K
+    idx = sorted(set([b for b in range(64) if work[b] <= 60000][:5] + [int(np.argmax(work))]))
     drops = synth.make_batch(64, seed=0, indices=idx)
     print(f"[gpu case] cfg4 subset sizes {[(d.M, d.N, d.K) for d in drops]}", flush=True)
     gains = [torch.from_numpy(d.gain).cuda() for d in drops]
-    res = ctx.solve_batch(drops, pa.Params(fixed_count=0, sweeps_per_dinkelbach=60), gains=gains)
     op = oracle.Params(fixed_count=0, sweeps_per_dinkelbach=60)
-    for d, r in list(zip(drops, res))[:-1]:
+    res = ctx.solve_batch(drops, gpu_params(op), gains=gains)
+    diverged = 0
+    for d, r in zip(drops, res):
         o = oracle.solve(d, op)
-
-        def rerun(scale, d=d):
-            return oracle.solve(dataclasses.replace(d, noise_w=d.noise_w * scale), op)
-
-        print(parity.compare(d, r, o, label=f"cfg4 drop {d.index}", rerun=rerun), flush=True)
-    assert np.isfinite(res[-1].ee) and res[-1].sweeps > 0
+        info = parity.compare(d, r, o, label=f"cfg4 drop {d.index} {d.M}x{d.N}x{d.K}", allow_diverged=True)
+        parity.check_structure(d, r)
+        print(info, flush=True)
+        diverged += bool(info.get("diverged"))
+    assert diverged <= 1
 
 
 def test_batch_rejects_bad_drop(ctx):
@@ -142,18 +142,14 @@ def test_batch_warm_starts_match_oracle(ctx):
     p = pa.Params(fixed_count=0, sweeps_per_dinkelbach=80)
     print(f"[gpu case] batch of {len(drops)} drops with warm starts", flush=True)
     res = ctx.solve_batch(drops, p, warms=warms)
-    chaotic = 0
+    diverged = 0
     for d, w, r in zip(drops, warms, res):
         o = oracle.solve(d, op, warm=w)
-
-        def rerun(scale, d=d, w=w):
-            return oracle.solve(dataclasses.replace(d, noise_w=d.noise_w * scale), op, warm=w)
-
         info = parity.compare(d, r, o, label=f"warm batch drop {d.index} warm={sorted(w or {})}",
-                              rerun=rerun)
+                              allow_diverged=True)
         print(info, flush=True)
-        chaotic += bool(info.get("skipped"))
-    assert chaotic <= 2
+        diverged += bool(info.get("diverged"))
+    assert diverged <= 1
 
 
 def _same(a, b):
@@ -237,21 +233,17 @@ def test_wave_tiles_match_oracle(ctx):
     # three workgroups in all: no drop is split over several
     p = pa.Params(fixed_count=0, sweeps_per_dinkelbach=120, max_groups=3)
     gains = [torch.from_numpy(d.gain).cuda() for d in drops]
+    orcs = [oracle.solve(d, op) for d in drops]
     for wave, blk in ((1, 0), (2, 256)):
         print(f"[gpu case] wave tiles: wave={wave} block={blk}, {len(drops)} mixed drops", flush=True)
         res = ctx.solve_batch(drops, dataclasses.replace(p, wave=wave, block=blk), gains=gains)
-        chaotic = 0
-        for d, r in zip(drops, res):
-            o = oracle.solve(d, op)
-
-            def rerun(scale, d=d):
-                return oracle.solve(dataclasses.replace(d, noise_w=d.noise_w * scale), op)
-
+        diverged = 0
+        for d, r, o in zip(drops, res, orcs):
             info = parity.compare(d, r, o, label=f"wave={wave} drop {d.index} {d.M}x{d.N}x{d.K} l={d.l}",
-                                  rerun=rerun)
+                                  allow_diverged=True)
             print(info, flush=True)
-            chaotic += bool(info.get("skipped"))
-        assert chaotic <= 3
+            diverged += bool(info.get("diverged"))
+        assert diverged <= 1
 
 
 def test_wave_tiles_agree_with_workgroup_tiles(ctx):
@@ -313,17 +305,11 @@ def test_group_scheduled_large_drop_matches_oracle(ctx):
     p = pa.Params(fixed_count=0, sweeps_per_dinkelbach=60)
     print("[gpu case] group-scheduled drop 6x256x64 l=3 among 5 small drops", flush=True)
     res = ctx.solve_batch(drops, p, gains=[torch.from_numpy(d.gain).cuda() for d in drops])
-    chaotic = 0
     for d, r in zip(drops, res):
         o = oracle.solve(d, op)
-
-        def rerun(scale, d=d):
-            return oracle.solve(dataclasses.replace(d, noise_w=d.noise_w * scale), op)
-
-        info = parity.compare(d, r, o, label=f"group batch {d.M}x{d.N}x{d.K}", rerun=rerun)
+        info = parity.compare(d, r, o, label=f"group batch {d.M}x{d.N}x{d.K}")
+        parity.check_structure(d, r)
         print(info, flush=True)
-        chaotic += bool(info.get("skipped"))
-    assert chaotic <= 1
     # the same drop alone (one drop: as many ranks as fit), with a small cap on
     # the grid, and through the plain solver: the same allocation
     alone = ctx.solve_batch([big], p)[0]
@@ -352,29 +338,6 @@ def test_group_scheduled_graph_replays(ctx):
     bt.close()
 
 
-def _check_structure(d, r):
-    """What holds for any correct allocation of the drop: distinct users per
-    subcarrier, each user served by one RRH at most (C5/C6), powers within
-    the mask and zero on empty slots, EE = rate / power.  (rrh_of_user is
-    the association the last sweep computed for the next one, so a served
-    user may already show another RRH there.)"""
-    sel, sp = r.sel, r.slot_power
-    assert sel.shape == (d.M, d.N, d.l)
-    assert ((sel >= -1) & (sel < d.K)).all()
-    assert ((r.rrh_of_user >= -1) & (r.rrh_of_user < d.M)).all()
-    mask = d.pmax_w / d.N
-    assert (sp >= 0).all() and (sp <= mask[:, None, None] * (1 + 1e-12)).all()
-    assert (sp[sel < 0] == 0).all()
-    served_by = np.full(d.K, -1)
-    for m in range(d.M):
-        for n in range(d.N):
-            users = sel[m, n][sel[m, n] >= 0]
-            assert len(set(users.tolist())) == len(users)
-            assert ((served_by[users] == -1) | (served_by[users] == m)).all()
-            served_by[users] = m
-    assert np.isfinite(r.ee) and r.ee == pytest.approx(r.rate_sum / r.power_sum, rel=1e-12)
-
-
 def test_benchmark_batch_full_size(ctx):
     """The benchmark's workload at full size and in its launch shape: 4096
     drops of 5 RRHs x 64 subcarriers x 32 users, one graph replay in the
@@ -393,18 +356,42 @@ def test_benchmark_batch_full_size(ctx):
     res = bt.results()
     bt.close()
     for d, r in zip(drops, res):
-        _check_structure(d, r)
+        parity.check_structure(d, r)
     op = oracle.Params(fixed_count=0)
     sample = np.random.default_rng(20240).choice(len(drops), 16, replace=False)
-    skipped = 0
+    diverged = 0
     for b in sample:
         d, r = drops[b], res[b]
         o = oracle.solve(d, op)
-
-        def rerun(scale, d=d):
-            return oracle.solve(dataclasses.replace(d, noise_w=d.noise_w * scale), op)
-
-        info = parity.compare(d, r, o, label=f"benchmark drop {b}", rerun=rerun)
+        info = parity.compare(d, r, o, label=f"benchmark drop {b}", allow_diverged=True)
         print(info, flush=True)
-        skipped += bool(info.get("skipped"))
-    assert skipped <= 4
+        diverged += bool(info.get("diverged"))
+    assert diverged <= 1
+
+
+def test_context_outlives_its_batches_and_networks():
+    """Destroying a context while a batch and a network made on it are alive
+    only closes it: they keep working, direct calls on the context are
+    refused, and it is freed with the last of them."""
+    import paper_1803_07772_amd as pa
+    from paper_1803_07772_amd.mlp import MLP, init_params
+    drops = _mixed_batch()[:3]
+    p = pa.Params(fixed_count=0, sweeps_per_dinkelbach=20)
+    print("[gpu case] context closed before its batch and network", flush=True)
+    c = pa.Context(0)
+    ref = c.solve_batch(drops, p)
+    bt = pa.Batch(c, drops, p)
+    net = MLP(c, init_params(3))
+    h = c._h
+    c.close()
+    held = pa.Context.__new__(pa.Context)  # a caller still holding the closed handle
+    held._h = h
+    with pytest.raises(pa.AllocError, match="-22"):
+        held.solve(drops[0], p)
+    held._h = None
+    bt.run()
+    for a, b in zip(bt.results(), ref):
+        _same(a, b)
+    net.solve(drops[0], p)
+    bt.close()
+    net.close()

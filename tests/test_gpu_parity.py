@@ -4,7 +4,6 @@ Every case prints its name before the GPU call so that a failing run names
 it.  Inputs come from the seeded generator; expected values from the oracle
 (run here, or stored by tests/golden/make_goldens.py for the full-size case).
 """
-import dataclasses
 import hashlib
 import os
 import sys
@@ -16,6 +15,7 @@ import oracle
 import synth
 from tests import parity, refeval
 from tests.drops_util import custom_drop
+from tests.gpu_util import gpu_params
 
 pytestmark = pytest.mark.gpu
 GOLD = os.path.join(os.path.dirname(__file__), "golden")
@@ -32,16 +32,7 @@ def ctx():
     c.close()
 
 
-def _gpu_params(op):
-    import paper_1803_07772_amd as pa
-    return pa.Params(max_dinkelbach=op.max_dinkelbach,
-                     sweeps_per_dinkelbach=op.sweeps_per_dinkelbach,
-                     refit_period=op.refit_period, fixed_count=op.fixed_count,
-                     churn_limit=op.churn_limit, tol_dinkelbach=op.tol_dinkelbach,
-                     tol_dual=op.tol_dual, step0=op.step0)
-
-
-def _run(ctx, d, op, label, device_gain=False, **kw):
+def _run(ctx, d, op, label, device_gain=False, allow_diverged=False, **kw):
     print(f"[gpu case] {label} M={d.M} N={d.N} K={d.K} l={d.l}", flush=True)
     okw = {k: v for k, v in kw.items() if k in ("pmask", "weight", "warm")}
     orc = oracle.solve(d, op, **okw)
@@ -49,12 +40,9 @@ def _run(ctx, d, op, label, device_gain=False, **kw):
     if device_gain:
         import torch
         gain = torch.from_numpy(d.gain).cuda()
-    gpu = ctx.solve(d, _gpu_params(op), gain=gain, **kw)
-
-    def rerun(scale):
-        return oracle.solve(dataclasses.replace(d, noise_w=d.noise_w * scale), op, **okw)
-
-    info = parity.compare(d, gpu, orc, pmask=kw.get("pmask"), label=label, rerun=rerun)
+    gpu = ctx.solve(d, gpu_params(op), gain=gain, **kw)
+    info = parity.compare(d, gpu, orc, pmask=kw.get("pmask"), label=label, allow_diverged=allow_diverged)
+    parity.check_structure(d, gpu, kw.get("pmask"))
     print(info, flush=True)
     return gpu, orc, info
 
@@ -63,20 +51,23 @@ def test_cfg1_converge(ctx):
     d = synth.make_drop(synth.CFG1, 0, 0)
     op = oracle.Params(fixed_count=0, sweeps_per_dinkelbach=2000, tol_dinkelbach=1e-6)
     gpu, orc, info = _run(ctx, d, op, "cfg1 seed0 converge")
-    assert "skipped" not in info
+    assert info["near_ties"] == 0 and gpu.status_flags == 0
 
 
 def test_cfg2_converge_with_caps(ctx):
-    """Seeds 0-15 of the 5-RRH / 64-subcarrier / 32-user configuration; at most
-    a quarter may be rounding-chaotic (compared on EE and structure only)."""
-    chaotic = []
+    """Seeds 0-15 of the 5-RRH / 64-subcarrier / 32-user configuration: every
+    drop at the bars on every element the oracle did not flag; at most one
+    drop may take a flagged decision the other way."""
+    diverged, flagged = [], 0
     for seed in range(16):
         d = synth.make_drop(synth.CFG2, seed, 0)
-        _, _, info = _run(ctx, d, oracle.Params(fixed_count=0), f"cfg2 seed{seed}", device_gain=True)
-        if info.get("skipped"):
-            chaotic.append(seed)
-    print("cfg2 drops compared on EE only:", chaotic, flush=True)
-    assert len(chaotic) <= 4
+        _, _, info = _run(ctx, d, oracle.Params(fixed_count=0), f"cfg2 seed{seed}", device_gain=True,
+                          allow_diverged=True)
+        flagged += info["flagged_mn"] + info["flagged_users"]
+        if info.get("diverged"):
+            diverged.append(seed)
+    print("cfg2: flagged elements", flagged, "diverged drops", diverged, flush=True)
+    assert len(diverged) <= 1
 
 
 @pytest.mark.parametrize("seed", range(3))
@@ -155,13 +146,17 @@ def test_cfg3_full_size_against_stored_oracle(ctx):
         pass
     orc = O()
     orc.sel = g["sel"].astype(np.int32)
-    for k in ("slot_power", "rrh_of_user", "xi", "zeta", "zeta_sic", "user_rate"):
+    for k in ("slot_power", "rrh_of_user", "xi", "zeta", "zeta_sic", "user_rate", "tie_mn", "tie_user"):
         setattr(orc, k, g[k])
     orc.ee, orc.rate_sum, orc.power_sum, _ = g["scalars"]
-    orc.dinkelbach_iters, orc.sweeps, orc.status_flags, orc.near_ties = (int(x) for x in g["ints"])
+    orc.dinkelbach_iters, orc.sweeps, orc.status_flags, orc.near_ties, _ = (int(x) for x in g["ints"])
     info = parity.compare(d, gpu, orc, label="cfg3 seed0")
-    print(info, flush=True)
-    assert "skipped" not in info
+    parity.check_structure(d, gpu)
+    print(info, gpu.status_flags, orc.status_flags, flush=True)
+    # the violations of C12-C14 at exit (flags compared by compare() when nothing is flagged)
+    vq, vp, vs = g["viol"]
+    for x, y in ((gpu.viol_qos, vq), (gpu.viol_budget, vp), (gpu.viol_sic, vs)):
+        assert (x == 0) == (y == 0) and abs(x - y) <= 1e-6 * max(abs(y), 1e-300)
 
 
 def test_deterministic_and_dense_output(ctx):
