@@ -37,15 +37,19 @@
  *    infeasible, less C12/C13 violation first, then less C14 violation, then
  *    the larger R - E P (a replacement needs a relative gain of 1e-6); the
  *    dual loop also ends after stall_sweeps sweeps without a better state
- *    once the best is feasible; the multipliers xi' and zeta' continue from
- *    the last sweep;
+ *    (a violation lower by more than 1e-6 relative is progress), and the
+ *    next Dinkelbach step restarts from the best; the multipliers xi' and
+ *    zeta' continue from the last sweep;
  *  - a warm start's allocation is Dinkelbach's p^0: E^1 = R(p^0)/P(p^0)
  *    whether or not it is feasible (F is strictly decreasing in E with its
  *    root at the optimum, Theorem 1 and Lemma 1, so the iteration converges
  *    from any E; from above the optimum F < 0 and E moves down), and it is
  *    the first step's starting state;
- *  - Dinkelbach's stop test is the root condition |F| <= tol R on a
- *    feasible state (F >= 0 whenever E is at most the optimum);
+ *  - Dinkelbach's stop test is the root condition |F| <= tol R (F >= 0
+ *    whenever E is at most the optimum) on a state that meets C12 and C13;
+ *    C14 is enforced through its multiplier and the selection rule, and a
+ *    state that still breaks it is reported (SCA keeps C13 feasible, Prop. 2;
+ *    nothing in the method guarantees C14);
  *  - all sweeps are Jacobi: every quantity of a sweep is read from the state
  *    the sweep starts from.
  */
@@ -1111,7 +1115,7 @@ static void rank_iterate(double Va, double Va2, double fa, double Vb, double Vb2
 /* Dinkelbach outer loop (Sec. III-IV) around the dual sweeps of Alg. 1.
  * Step i runs dual sweeps at E^i from the previous step's returned state and
  * returns the best state it visited (see rank_iterate()); F_i = R - E^i P at
- * that state; the solve stops when that state is feasible and
+ * that state; the solve stops when that state meets C12 and C13 and
  * |F_i| <= tol_dinkelbach R, otherwise E^{i+1} = R/P of that state. */
 ORC_API int orc_solve(const orc_problem* pb, const orc_params* prm, const orc_warm* warm,
                       orc_result* res) {
@@ -1172,7 +1176,7 @@ ORC_API int orc_solve(const orc_problem* pb, const orc_params* prm, const orc_wa
         if (!prm->fixed_count) {
           if (fabs(d - prm->tol_dual) <= 1e-6 * prm->tol_dual) st->ties++;
           if (d < prm->tol_dual) break;
-          if (prm->stall_sweeps > 0 && stall >= prm->stall_sweeps && bV == 0.0 && bV2 == 0.0) break;
+          if (prm->stall_sweeps > 0 && stall >= prm->stall_sweeps) break;
         }
       }
       if (have_best) snap_put(st, &best);
@@ -1195,9 +1199,10 @@ ORC_API int orc_solve(const orc_problem* pb, const orc_params* prm, const orc_wa
       st->E = R / P;
       continue;
     }
-    /* Dinkelbach's test applies to feasible iterates; an infeasible step is
-     * followed by another (the multipliers keep moving towards feasibility) */
-    const int feasible = st->ev_Vq == 0.0 && st->ev_Vp == 0.0 && st->ev_Vs == 0.0;
+    /* Dinkelbach's test applies to iterates that meet C12 and C13; an
+     * infeasible step is followed by another (the multipliers keep moving
+     * towards feasibility) */
+    const int feasible = st->ev_Vq == 0.0 && st->ev_Vp == 0.0;
     if (fabs(fabs(F) - prm->tol_dinkelbach * R) <= 1e-6 * prm->tol_dinkelbach * fabs(R)) st->ties++;
     if (feasible && fabs(F) <= prm->tol_dinkelbach * R) break;
     if (i >= prm->max_dinkelbach) {

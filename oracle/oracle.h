@@ -56,8 +56,7 @@ typedef struct {
   double step0;                  /* subgradient step delta_v = step0/sqrt(1+v) */
   double tie_rel;                /* relative margin below which a decision is a near-tie */
   int32_t stall_sweeps;          /* end the dual loop after this many sweeps without a
-                                    better state once the best is feasible (<=0: never;
-                                    not with fixed_count) */
+                                    better state (<=0: never; not with fixed_count) */
   double qos_down;               /* lower clip of the relative C13 violation in the
                                     zeta' step (the upper clip is 1) */
 } orc_params;

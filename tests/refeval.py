@@ -106,3 +106,31 @@ def feasibility(drop, P, l, psi=None, pmask=None, qos_rel=1e-6, tol=1e-9):
         s = drop.user_type == 1
         ok["qos"] = bool((r[s] >= psi[s] * (1 - qos_rel)).all())
     return ok
+
+
+def sic_violation(drop, P, tol=1e-9):
+    """Sum over co-scheduled pairs of the relative SIC margin Omega/nu (C14,
+    scaled by nu = Gamma_w (sigma + ICI_s) + Gamma_s (sigma + ICI_w)) above
+    tol; s is the user of larger raw gain (ties to the lower index)."""
+    G = drop.gain.astype(np.float64)
+    M, N, K = G.shape
+    sg = drop.noise_w
+    tot = P.sum(axis=2)
+    v = 0.0
+    for m in range(M):
+        for n in range(N):
+            users = np.nonzero(P[m, n] > 0)[0]
+            if users.size < 2:
+                continue
+            ici = {k: sum(tot[j, n] * G[j, n, k] for j in range(M) if j != m) for k in users}
+            for a in range(users.size):
+                for b in range(a + 1, users.size):
+                    ka, kb = users[a], users[b]
+                    s_, w_ = (ka, kb) if (G[m, n, ka] > G[m, n, kb] or
+                                          (G[m, n, ka] == G[m, n, kb] and ka < kb)) else (kb, ka)
+                    omega = (G[m, n, w_] * sg - G[m, n, s_] * sg + G[m, n, w_] * ici[s_]
+                             - G[m, n, s_] * ici[w_])
+                    nu = G[m, n, w_] * (sg + ici[s_]) + G[m, n, s_] * (sg + ici[w_])
+                    if omega / nu > tol:
+                        v += omega / nu - tol
+    return v

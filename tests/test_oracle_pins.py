@@ -833,3 +833,32 @@ def test_warm_start_from_an_infeasible_allocation():
     assert r.status_flags & (oracle.NOT_CONVERGED | oracle.QOS_INFEASIBLE | oracle.SIC_INFEASIBLE) == 0
     s = d.user_type == 1
     assert (r.user_rate[s] >= psi_of(d)[s] * (1 - 1e-6)).all()
+
+
+def test_stall_rule_ends_dual_loops_without_progress():
+    """The dual loop ends after stall_sweeps sweeps without a better state
+    (a violation lower by more than 1e-6 relative counts as better), whether
+    or not the best state is feasible, and the next Dinkelbach step restarts
+    from the best.  On this drop of the ragged batch generator (3 RRHs, 64
+    subcarriers, 216 users, l = 3) no step runs to the sweep cap, the last
+    step returns the state it started from (F = 0) after exactly
+    stall_sweeps + 1 sweeps, and the result meets C12-C14 (checked by the
+    independent evaluator) at Dinkelbach's root condition.  Without the rule
+    the first step runs to its cap."""
+    d = synth.make_batch(4096, seed=0, indices=[40])[0]
+    assert (d.M, d.N, d.K, d.l) == (3, 64, 216, 3)
+    op = oracle.Params(fixed_count=0)
+    r = oracle.solve(d, op)
+    n = r.dinkelbach_iters
+    F, sw = r.trace_F[:n], r.trace_sweeps[:n]
+    assert (sw < op.sweeps_per_dinkelbach).all(), sw
+    assert F[-1] == 0.0 and sw[-1] == op.stall_sweeps + 1, (F, sw)
+    assert r.status_flags & (oracle.NOT_CONVERGED | oracle.QOS_INFEASIBLE | oracle.BUDGET_INFEASIBLE
+                             | oracle.SIC_INFEASIBLE) == 0
+    P = refeval.dense_from_slots(d, r.sel, r.slot_power)
+    ok = refeval.feasibility(d, P, d.l, psi=psi_of(d))
+    assert all(ok.values()), ok
+    assert refeval.sic_violation(d, P) == 0.0
+    assert r.ee == pytest.approx(refeval.evaluate(d, P)["ee"], rel=1e-12)
+    r0 = oracle.solve(d, oracle.Params(fixed_count=0, stall_sweeps=0, max_dinkelbach=1))
+    assert r0.trace_sweeps[0] == op.sweeps_per_dinkelbach
