@@ -103,10 +103,11 @@ typedef struct {
   int32_t refit_period;          /* 1: SCALE refit every this many sweeps (<=0 never) */
   int32_t fixed_count;           /* 1: run exactly sweeps_per_dinkelbach sweeps */
   int32_t stall_sweeps;          /* 30: with fixed_count = 0, the dual loop also ends
-                                    after this many sweeps without a better state once
-                                    the best state is feasible (<= 0: never) */
-  double tol_dinkelbach;         /* 1e-6: stop when the returned state is feasible and
-                                    R - E P <= tol * R; also the relative gain of
+                                    after this many sweeps without a better state (a
+                                    violation of C12-C14 lower by more than 1e-6
+                                    relative counts as better; <= 0: never) */
+  double tol_dinkelbach;         /* 1e-6: stop when the returned state meets C12 and C13
+                                    and |R - E P| <= tol * R; also the relative gain of
                                     R - E P that counts as progress of the dual loop */
   double tol_dual;               /* 1e-7: dual loop stops when max|dp|/pmask and every
                                     projected multiplier subgradient are below tol and
@@ -137,6 +138,12 @@ typedef struct {
                                     wave tiles do not fit the LDS share keeps
                                     workgroup tiles); 0 = workgroup tiles.  With
                                     lds_kb = 0 the share is what the wave tiles need. */
+  int32_t group_triples;         /* 0: batched solver only: a drop of more than this many
+                                    (RRH, subcarrier, user) triples is solved by about
+                                    triples/group_triples workgroups together (at most
+                                    one per subcarrier and the resident number); 0 = a
+                                    drop above 1.5 times the average triples per
+                                    resident workgroup, by about triples/average */
 } alloc_params;
 
 ALLOC_API void alloc_params_default(alloc_params* p);

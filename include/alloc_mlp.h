@@ -55,9 +55,8 @@ extern "C" {
 #define ALLOC_MLP_NPARAMS 133635
 
 /* alloc_result.status_flags: the warm-started solve ended non-finite, with no
- * allocation (EE <= 0) or infeasible (ALLOC_QOS_INFEASIBLE,
- * ALLOC_BUDGET_INFEASIBLE, ALLOC_SIC_INFEASIBLE), and the returned result is
- * the cold-started solve's */
+ * allocation (EE <= 0) or infeasible for C12 or C13 (ALLOC_BUDGET_INFEASIBLE,
+ * ALLOC_QOS_INFEASIBLE), and the returned result is the cold-started solve's */
 #define ALLOC_WARM_FALLBACK 128u
 
 typedef struct alloc_mlp alloc_mlp;
@@ -119,8 +118,9 @@ ALLOC_API int alloc_mlp_warm(alloc_mlp* net, const alloc_problem* prob, uint32_t
 
 /* Network inference, then alloc_solve from that warm start.  Falls back to
  * the cold start (and sets ALLOC_WARM_FALLBACK) when the warm-started solve
- * ends non-finite, with EE <= 0 (nothing allocated) or infeasible (C12, C13
- * or C14 flagged): the cold-started solve is then returned, whatever its own
+ * ends non-finite, with EE <= 0 (nothing allocated) or infeasible for C12 or
+ * C13 (the constraints the method meets when it converges; C14 is reported
+ * on both paths): the cold-started solve is then returned, whatever its own
  * flags. */
 ALLOC_API int alloc_solve_mlp(alloc_mlp* net, const alloc_problem* prob, const alloc_params* prm,
                               alloc_result* res);

@@ -1241,10 +1241,11 @@ __device__ inline int cmp_viol(double a, double b) {
 // step's best and rotates the state buffers; the dual loop ends at its cap,
 // when the powers and every projected multiplier subgradient are below
 // tol_dual (and no user moved), or after `stall` sweeps without a better
-// state once the best is feasible.  The evaluation that follows reads the
+// state (a violation lower by more than kViolRel counts as better).  The evaluation that follows reads the
 // best state; Dinkelbach's test (Sec. III) is the root condition
-// |R - E P| <= tol R on a feasible state, otherwise E <- R/P and the next
-// step starts from that state.  A warm start's first evaluation is of its
+// |R - E P| <= tol R on a state that meets C12 and C13 (C14 is enforced
+// through its multiplier and the selection and reported when still broken),
+// otherwise E <- R/P and the next step starts from that state.  A warm start's first evaluation is of its
 // p^0, feasible or not: E^1 = R/P (F is strictly decreasing in E with its
 // root at the optimum, so the iteration converges from either side).
 __device__ void advance(const Sched& sc, Ctrl& c, const Eval& e) {
@@ -1286,7 +1287,7 @@ __device__ void advance(const Sched& sc, Ctrl& c, const Eval& e) {
     }
     if (!sc.fixed) {
       if (delta < sc.tol_dual) end = true;
-      if (sc.stall > 0 && c.stall >= sc.stall && c.bV == 0.0 && c.bV2 == 0.0) end = true;
+      if (sc.stall > 0 && c.stall >= sc.stall) end = true;
     }
     if (end) {
       c.mode = kEval;
@@ -1299,7 +1300,7 @@ __device__ void advance(const Sched& sc, Ctrl& c, const Eval& e) {
     c.Vq = e.Vq;
     c.Vp = e.Vp;
     c.Vs = e.Vs;
-    const bool feasible = e.Vq == 0.0 && e.Vp == 0.0 && e.Vs == 0.0;
+    const bool feasible = e.Vq == 0.0 && e.Vp == 0.0;  // C14 is reported, not required
     const double F = e.R - c.E * e.P;
     c.i += 1;
     bool next = false;
@@ -1928,6 +1929,7 @@ int validate(const alloc_problem* pb, const alloc_params* prm) {
   if (!std::isfinite(pb->noise_w)) return ALLOC_EINVAL;
   if (pb->M > kMaxM || pb->l > kMaxL || pb->K > kMaxK || pb->M * pb->K > kMaxMK) return ALLOC_ETOOBIG;
   if (prm->sweeps_per_dinkelbach < 1 || prm->max_dinkelbach < 1 || prm->max_groups < 0 || prm->tile < 0 ||
+      prm->group_triples < 0 ||
       prm->lds_kb < 0 || !(prm->block == 0 || prm->block == 256 || prm->block == 512 || prm->block == 1024) || prm->wave < 0 ||
       prm->wave > 16)
     return ALLOC_EINVAL;
@@ -1995,6 +1997,7 @@ void alloc_params_default(alloc_params* p) {
   p->lds_kb = 0;
   p->block = 0;
   p->wave = 0;
+  p->group_triples = 0;
 }
 
 int alloc_ctx_set_timing(alloc_ctx* ctx, int enable) {
@@ -2423,16 +2426,20 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
   int cap = per_cu * ctx->cus;  // workgroups resident at once
   if (prm->max_groups > 0) cap = std::min(cap, prm->max_groups);
 
-  // workgroups per drop: a drop with more work than the average share of a
-  // resident workgroup is split over about work/average of them (at most
-  // one per subcarrier), so no slot holds much more than the average
+  // workgroups per drop: with group_triples, a drop of more triples is
+  // split over about triples/group_triples of them; otherwise a drop with
+  // more work than 1.5 times the average share of a resident workgroup is
+  // split over about work/average of them.  At most one per subcarrier and
+  // no more than are resident.
   P.group.assign(B, 1);
   double wsum = 0.0;
   for (int b = 0; b < B; ++b) wsum += (double)probs[b].M * probs[b].N * probs[b].K;
-  const double avg = wsum / cap;
+  const double avg = prm->group_triples > 0 ? (double)prm->group_triples : wsum / cap;
+  const double above = prm->group_triples > 0 ? 1.0 : 1.5;
   for (int b = 0; b < B; ++b) {
     const double w = (double)probs[b].M * probs[b].N * probs[b].K;
-    if (w > 1.5 * avg) P.group[b] = (int)std::min<double>({std::floor(w / avg + 0.5), (double)cap, (double)probs[b].N});
+    if (w > above * avg)
+      P.group[b] = (int)std::min<double>({std::floor(w / avg + 0.5), (double)cap, (double)probs[b].N});
     P.group[b] = std::max(1, P.group[b]);
   }
 

@@ -1123,12 +1123,12 @@ WarmArrays warm_arrays(int64_t n3, int M, int K) {
 }
 
 // The warm-started solve is replaced by the cold one when it ended
-// non-finite, with no allocation at all (EE not positive), or infeasible: a
-// streaming user below its minimum rate (C13), an RRH over its budget (C12)
-// or a co-scheduled pair that breaks SIC decodability (C14).
+// non-finite, with no allocation at all (EE not positive), or infeasible for
+// the constraints the method meets when it converges: a streaming user below
+// its minimum rate (C13) or an RRH over its budget (C12).  C14 is enforced
+// through its multiplier and reported, as on the cold path.
 bool needs_fallback(const alloc_result& r) {
-  return (r.status_flags & (ALLOC_NONFINITE | ALLOC_QOS_INFEASIBLE | ALLOC_BUDGET_INFEASIBLE | ALLOC_SIC_INFEASIBLE)) ||
-         !(r.ee > 0.0);
+  return (r.status_flags & (ALLOC_NONFINITE | ALLOC_QOS_INFEASIBLE | ALLOC_BUDGET_INFEASIBLE)) || !(r.ee > 0.0);
 }
 
 }  // namespace

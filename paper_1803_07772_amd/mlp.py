@@ -225,7 +225,7 @@ class MLP:
     def solve(self, drop, params: Params | None = None, gain=None, dense_power=False):
         """Network inference, then the solve from that warm start (cold-start
         fallback when the warm solve ends non-finite, empty, or infeasible
-        for C12, C13 or C14)."""
+        for C12 or C13)."""
         keep = []
         pb, flags = problem_struct(drop, keep, gain)
         res, out, dense = result_struct(drop, dense_power)

@@ -6,12 +6,19 @@ the cap on subcarriers per LDS tile (``tile``) and the threads per workgroup
 (``block``: 512, 256 for more and smaller workgroups per compute unit, or
 1024 for one workgroup per compute unit with all of its LDS) and
 whether each wave runs its own subcarriers (``wave``: subcarriers per wave
-tile, 0 = tiles of the whole workgroup).  They change only the order of
-floating-point sums inside a drop, not the method.  Candidates are timed on
-the GPU (the batched kernel's HIP-event duration) on the whole batch, so the
-load per workgroup (and which drops are split over several workgroups) is the
-real one, but with a short fixed schedule (a few sweeps, every drop the same
-count) to keep tuning cheap; the fastest per size bucket is kept in a JSON
+tile, 0 = tiles of the whole workgroup), and the schedule: how many
+workgroups solve a large drop together (``group_triples``: a drop of more
+triples is split over about triples/group_triples workgroups; 0 = the
+library's rule by the average load).  They change only the order of
+floating-point sums inside a drop, not the method.
+
+Candidates are timed on the GPU (the batched kernel's HIP-event duration) on
+the whole batch, so the load per workgroup is the real one.  The launch
+shapes are first timed with a short fixed schedule (a few sweeps, every drop
+the same count), which ranks the per-sweep cost; the leading shapes are then
+timed with the real schedule, each with every group_triples candidate,
+because the end of a launch is set by the drops that need the most sweeps,
+which only full solves show.  The fastest per size bucket is kept in a JSON
 cache that later batches of the same bucket reuse.
 """
 from __future__ import annotations
@@ -84,14 +91,28 @@ def tuned(drops, params: Params, cache: dict | None = None) -> Params:
     if not e:
         return params
     return dataclasses.replace(params, lds_kb=int(e["lds_kb"]), tile=int(e["tile"]),
-                               block=int(e.get("block", 0)), wave=int(e.get("wave", 0)))
+                               block=int(e.get("block", 0)), wave=int(e.get("wave", 0)),
+                               group_triples=int(e.get("group_triples", 0)))
+
+
+SHAPE_FIELDS = ("lds_kb", "tile", "block", "wave")
+
+
+def group_candidates(drops) -> list:
+    """Schedules to try: the library's rule (0), and splitting every drop
+    above a half, a quarter and an eighth of the largest drop's triples."""
+    big = max(d.M * d.N * d.K for d in drops)
+    return [0] + sorted({max(1, big // f) for f in (2, 4, 8)}, reverse=True)
 
 
 def tune(ctx, drops, params: Params, gains=None, sweeps: int = 12,
-         candidates=CANDIDATES, cache: dict | None = None):
-    """Times every candidate on the batch with a fixed schedule of ``sweeps``
-    sweeps in each of two Dinkelbach steps; returns (best, timings) and
-    records the best under the batch's bucket in ``cache`` if given."""
+         candidates=CANDIDATES, cache: dict | None = None, full: int = 3, groups=None):
+    """Times every launch shape on the batch with a fixed schedule of
+    ``sweeps`` sweeps in each of two Dinkelbach steps, then the ``full``
+    fastest of them with the real schedule ``params`` under every schedule of
+    ``groups`` (default group_candidates(drops)); ``full`` = 0 keeps the
+    short ranking alone.  Returns (best, timings) and records the best under
+    the batch's bucket in ``cache`` if given."""
     short = dataclasses.replace(params, fixed_count=1, sweeps_per_dinkelbach=sweeps, max_dinkelbach=2)
     was = ctx.timing
     ctx.set_timing(True)
@@ -101,13 +122,24 @@ def tune(ctx, drops, params: Params, gains=None, sweeps: int = 12,
         ctx.solve_batch(drops, dataclasses.replace(p, sweeps_per_dinkelbach=1, max_dinkelbach=1), gains=gains)
         ctx.solve_batch(drops, p, gains=gains)
         times.append((ctx.last_kernel_ms(), cand))
-    ctx.set_timing(was)
     # candidates are in order of preference: keep the first within 2% of the
     # fastest (the short schedule cannot separate closer ones)
     fastest = min(t for t, _ in times)
-    best = next(c for t, c in times if t <= 1.02 * fastest)
+    best = dict(next(c for t, c in times if t <= 1.02 * fastest), group_triples=0)
+    full_times = []
+    if full > 0:
+        lead = [c for _, c in sorted(times, key=lambda x: x[0])[:full]]
+        for cand in lead:
+            for g in (group_candidates(drops) if groups is None else groups):
+                p = dataclasses.replace(params, **cand, group_triples=g)
+                ctx.solve_batch(drops, p, gains=gains)
+                full_times.append((ctx.last_kernel_ms(), dict(cand, group_triples=g)))
+        best = min(full_times, key=lambda x: x[0])[1]
+    ctx.set_timing(was)
     if cache is not None:
-        cache[batch_key(drops)] = dict(best, ms={"/".join(str(c[f]) for f in ("lds_kb", "tile", "block", "wave")): round(t, 3)
-                                                 for t, c in times},
-                                      drops=len(drops), sweeps=sweeps)
-    return best, times
+        key = lambda c: "/".join(str(c[f]) for f in SHAPE_FIELDS)  # noqa: E731
+        cache[batch_key(drops)] = dict(
+            best, ms={key(c): round(t, 3) for t, c in times},
+            full_ms={key(c) + f"/g{c['group_triples']}": round(t, 3) for t, c in full_times},
+            drops=len(drops), sweeps=sweeps)
+    return best, times + full_times

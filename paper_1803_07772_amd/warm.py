@@ -80,12 +80,13 @@ def train(net: MLP, feat, target, weight, cfg: TrainConfig):
 
 
 def fit(ctx: Context, drops, params: Params, cfg: TrainConfig | None = None, init=None,
-        gains=None) -> tuple[MLP, dict]:
-    """Solve the training drops cold, build rows, train a network."""
+        gains=None, chunk: int = 512) -> tuple[MLP, dict]:
+    """Solve the training drops cold (``chunk`` drops per batched solve),
+    build rows, train a network."""
     from .mlp import init_params
     cfg = cfg or TrainConfig()
     t0 = time.perf_counter()
-    results = solve_cold(ctx, drops, params, gains)
+    results = solve_cold(ctx, drops, params, gains, chunk)
     t1 = time.perf_counter()
     net = MLP(ctx, init_params(cfg.seed) if init is None else init)
     feat, target, weight = training_rows(net, drops, results, cfg, gains)

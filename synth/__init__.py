@@ -263,9 +263,19 @@ def batch_sizes(B: int, seed: int = 0, cfg_id: int = 4, mf=(2, 16), n_choices=CF
     return M, N, K
 
 
-def make_batch(B: int, seed: int = 0, recipe: Recipe = CFG4, indices=None):
-    """A ragged batch of drops; drop b uses sizes from batch_sizes and index b."""
+def make_batch(B: int, seed: int = 0, recipe: Recipe = CFG4, indices=None, threads: int = 1):
+    """A ragged batch of drops; drop b uses sizes from batch_sizes and index b.
+    With threads > 1 the drops are generated by that many threads (the
+    generator releases the interpreter lock; every drop is keyed by its own
+    index, so the result does not depend on the thread count)."""
     M, N, K = batch_sizes(B, seed=seed, cfg_id=recipe.cfg_id)
-    idx = range(B) if indices is None else indices
-    return [make_drop(recipe.with_sizes(int(M[b]), int(N[b]), int(K[b])), seed=seed, index=b)
-            for b in idx]
+    idx = list(range(B) if indices is None else indices)
+
+    def one(b):
+        return make_drop(recipe.with_sizes(int(M[b]), int(N[b]), int(K[b])), seed=seed, index=b)
+
+    if threads <= 1:
+        return [one(b) for b in idx]
+    from concurrent.futures import ThreadPoolExecutor
+    with ThreadPoolExecutor(threads) as ex:
+        return list(ex.map(one, idx))

@@ -132,3 +132,27 @@ def compare(drop, gpu, orc, pmask=None, label="", allow_diverged=False):
     assert info["ee_rel"] <= EE_RTOL_DIVERGED, info
     check_structure(drop, gpu, pmask)
     return info
+
+
+class Stored:
+    """An oracle result read back from a stored .npz (tests/golden)."""
+
+
+def load_stored(g, prefix, drop):
+    """The stored oracle result of ``drop`` under ``prefix`` in the loaded
+    archive g (as tests/golden/make_cfg4_goldens.py writes it); checks that
+    the drop's gains are the ones the oracle solved."""
+    import hashlib
+    if hashlib.sha256(drop.gain.tobytes()).digest() != g[prefix + "gain_sha256"].tobytes():
+        raise ValueError(f"{prefix}: gains differ from the stored oracle run")
+    o = Stored()
+    o.sel = g[prefix + "sel"].astype(np.int32)
+    o.slot_power = g[prefix + "slot_power"].astype(np.float64)
+    o.rrh_of_user = g[prefix + "rrh_of_user"].astype(np.int32)
+    o.user_rate, o.xi, o.zeta = g[prefix + "user_rate"], g[prefix + "xi"], g[prefix + "zeta"]
+    o.zeta_sic = np.zeros((drop.M, drop.N, 0))
+    o.tie_mn, o.tie_user = g[prefix + "tie_mn"], g[prefix + "tie_user"]
+    o.ee, o.rate_sum, o.power_sum, o.viol_qos, o.viol_budget, o.viol_sic = (
+        float(x) for x in g[prefix + "scalars"])
+    o.dinkelbach_iters, o.sweeps, o.status_flags, o.near_ties = (int(x) for x in g[prefix + "ints"])
+    return o

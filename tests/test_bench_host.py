@@ -28,15 +28,26 @@ def test_roofline_arithmetic():
     assert r["traffic"] is None and "valu_issue" not in r
 
 
-def test_counter_record_needs_matching_sources_and_size(tmp_path, monkeypatch):
+def test_counter_record_needs_matching_sources_and_workload(tmp_path, monkeypatch):
     rec = json.load(open(os.path.join(ROOT, "profiles", "traffic.json")))["batch_kernel"]
-    drops = rec["drops_per_step"]
+    wl = rec["workload"]
     if rec["src_sha256"] == bench.solver_source_sha():
-        assert bench.traffic_for("batch_kernel", drops) == rec["hbm_bytes_per_launch"]
-        assert bench.traffic_for("batch_kernel", drops + 1) is None
-        v = bench.valu_issue("batch_kernel", drops, 500.0)
+        assert bench.traffic_for("batch_kernel", wl) == rec["hbm_bytes_per_launch"]
+        assert bench.traffic_for("batch_kernel", wl + "x") is None
+        v = bench.valu_issue("batch_kernel", wl, 500.0)
         assert v["frac"] == pytest.approx(rec["valu_wave_insts_per_launch"] / 0.5 / bench.VALU_WAVE_INSTS_PEAK)
     # a record taken on other sources is ignored
     monkeypatch.setattr(bench, "solver_source_sha", lambda: "0" * 64)
-    assert bench.traffic_for("batch_kernel", drops) is None
-    assert bench.valu_issue("batch_kernel", drops, 500.0) is None
+    assert bench.traffic_for("batch_kernel", wl) is None
+    assert bench.valu_issue("batch_kernel", wl, 500.0) is None
+
+
+def test_gate_reads_the_stored_subset():
+    """The gate's stored oracle results hold the seeded 1% of the ragged
+    batch, as the script that writes them selects it."""
+    import numpy as np
+    from tests.golden import make_cfg4_goldens as mk
+    g = np.load(bench.GATE_PATH)
+    assert np.array_equal(g["indices"], mk.subset_indices()) and len(g["indices"]) == 41
+    for b in g["indices"][:3]:
+        assert f"d{b}_sel" in g and f"d{b}_scalars" in g

@@ -267,9 +267,9 @@ def test_solve_mlp_equals_solve_from_its_warm_start(ctx):
 
 def needs_fallback(r):
     """The warm-started result is replaced by the cold one: non-finite, empty
-    (EE <= 0), or infeasible for C12, C13 or C14."""
+    (EE <= 0), or infeasible for C12 or C13."""
     import paper_1803_07772_amd as pa
-    bad = pa.NONFINITE | pa.QOS_INFEASIBLE | pa.BUDGET_INFEASIBLE | pa.SIC_INFEASIBLE
+    bad = pa.NONFINITE | pa.QOS_INFEASIBLE | pa.BUDGET_INFEASIBLE
     return bool(r.status_flags & bad) or not r.ee > 0
 
 

@@ -32,3 +32,12 @@ def test_tuned_params_from_cache(tmp_path):
     tune.save_cache(cache, str(path))
     assert tune.load_cache(str(path)) == cache
     assert json.loads(path.read_text()) == cache
+
+
+def test_schedule_from_cache_and_group_candidates():
+    drops = [synth.make_drop(synth.CFG2, s, 0) for s in range(3)]
+    cache = {"M8-N64-K32-l2": {"lds_kb": 0, "tile": 0, "block": 1024, "wave": 0, "group_triples": 4000}}
+    assert tune.tuned(drops, Params(), cache) == dataclasses.replace(Params(), block=1024, group_triples=4000)
+    big = synth.make_drop(synth.CFG2.with_sizes(9, 512, 100), 0, 0)
+    g = tune.group_candidates(drops + [big])
+    assert g[0] == 0 and g[1:] == [9 * 512 * 100 // 2, 9 * 512 * 100 // 4, 9 * 512 * 100 // 8]
