@@ -90,6 +90,7 @@ def _load():
         lib.orc_state_sweep.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]
         lib.orc_state_sweep.restype = ctypes.c_double
         lib.orc_state_eval.argtypes = [ctypes.c_void_p] + [ctypes.c_void_p] * 4
+        lib.orc_state_repair_sic.argtypes = [ctypes.c_void_p]
         lib.orc_state_export.argtypes = [ctypes.c_void_p, R]
         lib.orc_state_get_slots.argtypes = [ctypes.c_void_p] * 6
         lib.orc_state_set_powers.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
@@ -252,6 +253,11 @@ class State:
 
     def reset_scale(self):
         self._lib.orc_state_reset_scale(self._h)
+
+    def repair_sic(self):
+        """Dissolve the pairs that break C14 at the state (as a solve does
+        before it returns)."""
+        self._lib.orc_state_repair_sic(self._h)
 
     def sweep(self, v: int, refit: bool) -> float:
         return self._lib.orc_state_sweep(self._h, v, int(refit))

@@ -47,9 +47,10 @@
  *    the first step's starting state;
  *  - Dinkelbach's stop test is the root condition |F| <= tol R (F >= 0
  *    whenever E is at most the optimum) on a state that meets C12 and C13;
- *    C14 is enforced through its multiplier and the selection rule, and a
- *    state that still breaks it is reported (SCA keeps C13 feasible, Prop. 2;
- *    nothing in the method guarantees C14);
+ *    C14 is enforced through its multiplier and the selection rule (SCA keeps
+ *    C13 feasible, Prop. 2; nothing in the method guarantees C14), and the
+ *    pairs that still break it when the solve ends are dissolved (see
+ *    repair_subcarrier());
  *  - all sweeps are Jacobi: every quantity of a sweep is read from the state
  *    the sweep starts from.
  */
@@ -1011,6 +1012,89 @@ ORC_API void orc_state_set_powers(orc_state* st, const double* power) {
     if (st->sel[i] >= 0) st->p[i] = power[i];
 }
 
+/* ---------------------------------------------------------- C14 repair */
+
+/* Makes subcarrier n of the state meet C14 (Sec. II-B, C8/C14: a
+ * co-scheduled pair is SIC-decodable only when its raw-gain and
+ * normalised-gain orders agree).  While a pair breaks it at the state's
+ * interference, the pair of largest margin (RRHs in increasing order, then
+ * pairs in decoding order, the first of equal margins) loses one user: the
+ * elastic one when exactly one is elastic (streaming users keep the rates
+ * C13 asks for), otherwise the one of lower rate on the subcarrier (the
+ * higher user index on equal rates).  Its slot is emptied with its C14
+ * multipliers.  Every round removes a user, so the loop ends. */
+static void repair_subcarrier(orc_state* st, int n, double* ici, mview* vw) {
+  const int M = st->M, K = st->K, L = st->L;
+  const double sg = st->sigma;
+  for (;;) {
+    double sv, best = SIC_TOL;
+    int bm = -1, ba = 0, bb = 0;
+    eval_subcarrier(st, n, 0, ici, vw, NULL, NULL, &sv);
+    for (int m = 0; m < M; ++m) {
+      const mview* v = &vw[m];
+      for (int a = 0; a < v->cnt; ++a)
+        for (int b = a + 1; b < v->cnt; ++b) {
+          const int ka = v->user[a], kb = v->user[b];
+          const double ga = st->G[IDX3(st, m, n, ka)], gb = st->G[IDX3(st, m, n, kb)];
+          const double om = pair_margin(ga, (sg + ici[(size_t)m * K + ka]) / ga, ka, gb,
+                                        (sg + ici[(size_t)m * K + kb]) / gb, kb);
+          note_mn(st, m, n, fabs(om - best) / fmax(fabs(best), SIC_TOL), &st->part_ties[n], &st->part_margin[n]);
+          if (om > best) {
+            best = om;
+            bm = m;
+            ba = a;
+            bb = b;
+          }
+        }
+    }
+    if (bm < 0) return;
+    const mview* v = &vw[bm];
+    const int ea = st->elastic[v->user[ba]], eb = st->elastic[v->user[bb]];
+    int drop;
+    if (ea != eb) {
+      drop = ea ? ba : bb;
+    } else {
+      const double ra = v->r[ba], rb = v->r[bb];
+      note_mn(st, bm, n, fabs(ra - rb) / fmax(fmax(ra, rb), DBL_MIN), &st->part_ties[n],
+              &st->part_margin[n]);
+      if (ra != rb)
+        drop = ra < rb ? ba : bb;
+      else
+        drop = v->user[ba] > v->user[bb] ? ba : bb;
+    }
+    const int s = v->slot[drop];
+    const size_t si = SLOT(st, bm, n, s);
+    st->sel[si] = -1;
+    st->p[si] = 0.0;
+    st->al[si] = 1.0;
+    st->be[si] = 0.0;
+    for (int b = 0; b < L; ++b) {
+      st->zs[PAIR(st, bm, n, s, b)] = 0.0;
+      st->zs[PAIR(st, bm, n, b, s)] = 0.0;
+    }
+  }
+}
+
+static void repair_sic(orc_state* st) {
+  const int M = st->M, N = st->N, K = st->K;
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int n = 0; n < N; ++n) {
+    double* ici = (double*)malloc(sizeof(double) * (size_t)M * K);
+    mview* vw = (mview*)malloc(sizeof(mview) * M);
+    st->part_ties[n] = 0;
+    st->part_margin[n] = INFINITY;
+    repair_subcarrier(st, n, ici, vw);
+    free(ici);
+    free(vw);
+  }
+  for (int n = 0; n < N; ++n) {
+    st->ties += st->part_ties[n];
+    if (st->part_margin[n] < st->min_margin) st->min_margin = st->part_margin[n];
+  }
+}
+
+ORC_API void orc_state_repair_sic(orc_state* st) { repair_sic(st); }
+
 /* ---------------------------------------------------------- full solve */
 
 /* Primal state of an iterate: association, selection, powers, SCALE
@@ -1213,6 +1297,12 @@ ORC_API int orc_solve(const orc_problem* pb, const orc_params* prm, const orc_wa
   }
   snap_free(&cur);
   snap_free(&best);
+  /* the returned allocation meets C14: pairs that still break it are
+   * dissolved, and the allocation is evaluated again */
+  if (st->ev_Vs > 0.0 && !(flags & ORC_NONFINITE)) {
+    repair_sic(st);
+    orc_state_eval(st, &R, &P, NULL, rate);
+  }
   orc_state_export(st, res);
   if (st->ev_Vq > 0.0) flags |= ORC_QOS_INFEASIBLE;
   if (st->ev_Vp > 0.0) flags |= ORC_BUDGET_INFEASIBLE;

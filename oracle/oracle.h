@@ -133,6 +133,9 @@ void orc_state_set_multipliers(orc_state* st, const double* xi, const double* ze
                                const double* zs);
 /* Per-triple Lagrangian maximum H [M][N][K] computed by the last sweep. */
 void orc_state_get_H(orc_state* st, double* H);
+/* Dissolves the co-scheduled pairs that break C14 at the state, as a solve
+ * does before it returns (see repair_subcarrier in oracle.c). */
+void orc_state_repair_sic(orc_state* st);
 
 /* Minimum-rate requirement Psi (bits/s/Hz) of a streaming user (Sec. II-B). */
 double orc_min_rate(double arrival_bps, double delay_s, double packet_bits, double bw_hz);

@@ -52,7 +52,9 @@ constexpr double kBudgetTol = 1e-6;
 constexpr double kSicTol = 1e-9;
 constexpr double kViolRel = 1e-6;
 
-enum Mode : int { kSweep = 0, kEval = 1, kDone = 2 };
+// kRepair: dissolve the C14 pairs the returned state still breaks; kFinal:
+// evaluate the repaired state.
+enum Mode : int { kSweep = 0, kEval = 1, kDone = 2, kRepair = 3, kFinal = 4 };
 
 // Loop-control state.  Every workgroup holds an identical copy.
 //
@@ -1225,6 +1227,113 @@ __device__ void reduce_pass(const Drop& d, const Sched& sc, const Ctrl& c, Lds& 
   }
 }
 
+// Makes subcarrier n of state buffer rd meet C14 (Sec. II-B, C8/C14: a
+// co-scheduled pair is SIC-decodable only when its raw-gain and
+// normalised-gain orders agree).  While a pair breaks it at the state's
+// interference, the pair of largest margin (RRHs in increasing order, then
+// pairs in decoding order, the first of equal margins) loses one user: the
+// elastic one when exactly one is elastic, otherwise the one of lower rate on
+// the subcarrier (the higher user index on equal rates); its slot is emptied
+// with its C14 multipliers.  Every round removes a user, so the loop ends.
+// One thread per subcarrier, on the state in device memory: it runs once, at
+// the end of a solve, and only when the returned state breaks C14.
+__device__ void repair_subcarrier(const Drop& d, int rd, int n) {
+  const int M = d.M, N = d.N, K = d.K, L = d.L;
+  const size_t nsl = (size_t)M * N * L;
+  GLB int* sel = gl(d.sel) + rd * nsl;
+  GLB double* p = gl(d.p) + rd * nsl;
+  GLB double* al = gl(d.al) + rd * nsl;
+  GLB double* be = gl(d.be) + rd * nsl;
+  GLB double* zs = gl(d.zs) + rd * nsl * L;
+  GLB const float* G = gl(d.G);
+  const double sg = d.sigma;
+  auto ici_of = [&](int m, int k) {  // sum over the other RRHs, in increasing order
+    double acc = 0.0;
+    for (int j = 0; j < M; ++j) {
+      if (j == m) continue;
+      double pj = 0.0;
+      for (int q = 0; q < L; ++q)
+        if (sel[((size_t)j * N + n) * L + q] >= 0) pj += p[((size_t)j * N + n) * L + q];
+      acc += pj * (double)G[((size_t)j * N + n) * K + k];
+    }
+    return acc;
+  };
+  for (;;) {
+    double best = kSicTol;
+    int bm = -1, bq[2] = {0, 0};
+    for (int m = 0; m < M; ++m) {
+      // the selected users of (m,n) in decoding order: u ascending, ties to
+      // the lower user
+      int cnt = 0, uk[kMaxL], uq[kMaxL];
+      double uu[kMaxL];
+      for (int q = 0; q < L; ++q) {
+        const int k = sel[((size_t)m * N + n) * L + q];
+        if (k < 0) continue;
+        const double u = (sg + ici_of(m, k)) / (double)G[((size_t)m * N + n) * K + k];
+        int t = cnt++;
+        while (t > 0 && (uu[t - 1] > u || (uu[t - 1] == u && uk[t - 1] > k))) {
+          uu[t] = uu[t - 1];
+          uk[t] = uk[t - 1];
+          uq[t] = uq[t - 1];
+          --t;
+        }
+        uu[t] = u;
+        uk[t] = k;
+        uq[t] = q;
+      }
+      for (int a = 0; a < cnt; ++a)
+        for (int b = a + 1; b < cnt; ++b) {
+          const float ga = G[((size_t)m * N + n) * K + uk[a]], gb = G[((size_t)m * N + n) * K + uk[b]];
+          const bool a_strong = ga > gb || (ga == gb && uk[a] < uk[b]);
+          const double us = a_strong ? uu[a] : uu[b], uw = a_strong ? uu[b] : uu[a];
+          const double om = (us - uw) / (us + uw);
+          if (om > best) {
+            best = om;
+            bm = m;
+            bq[0] = uq[a];
+            bq[1] = uq[b];
+          }
+        }
+    }
+    if (bm < 0) return;
+    const size_t base = ((size_t)bm * N + n) * L;
+    int ks[2];
+    double r[2];
+    for (int x = 0; x < 2; ++x) {
+      const int k = sel[base + bq[x]];
+      ks[x] = k;
+      // rate on the subcarrier: interference of the users decoded before k
+      const double g = (double)G[((size_t)bm * N + n) * K + k];
+      const double ici = ici_of(bm, k), u = (sg + ici) / g;
+      double pre = 0.0;
+      for (int q = 0; q < L; ++q) {
+        const int k2 = sel[base + q];
+        if (k2 < 0 || k2 == k) continue;
+        const double u2 = (sg + ici_of(bm, k2)) / (double)G[((size_t)bm * N + n) * K + k2];
+        if (u2 < u || (u2 == u && k2 < k)) pre += p[base + q];
+      }
+      r[x] = log2_1p(p[base + bq[x]] * g / (sg + ici + g * pre));
+    }
+    const bool e0 = gl(d.elastic)[ks[0]], e1 = gl(d.elastic)[ks[1]];
+    int drop;
+    if (e0 != e1)
+      drop = e0 ? 0 : 1;
+    else if (r[0] != r[1])
+      drop = r[0] < r[1] ? 0 : 1;
+    else
+      drop = ks[0] > ks[1] ? 0 : 1;
+    const int q = bq[drop];
+    sel[base + q] = -1;
+    p[base + q] = 0.0;
+    al[base + q] = 1.0;
+    be[base + q] = 0.0;
+    for (int b = 0; b < L; ++b) {
+      zs[(base + q) * L + b] = 0.0;
+      zs[(base + b) * L + q] = 0.0;
+    }
+  }
+}
+
 // Two violations a (new) and b (best): -1 when a is lower by more than
 // kViolRel (relative), 1 when higher, 0 otherwise (zero equals only zero).
 __device__ inline int cmp_viol(double a, double b) {
@@ -1331,6 +1440,16 @@ __device__ void advance(const Sched& sc, Ctrl& c, const Eval& e) {
       c.stall = 0;
       c.mode = kSweep;
     }
+    // the returned allocation meets C14: pairs that still break it are
+    // dissolved and the allocation evaluated again
+    if (c.mode == kDone && e.Vs > 0.0 && !(c.flags & ALLOC_NONFINITE)) c.mode = kRepair;
+  } else if (c.mode == kFinal) {
+    c.R = e.R;
+    c.P = e.P;
+    c.Vq = e.Vq;
+    c.Vp = e.Vp;
+    c.Vs = e.Vs;
+    c.mode = kDone;
   }
   c.pass += 1;
 }
@@ -1365,7 +1484,7 @@ __device__ inline PassConst pass_const(const Sched& sc, const Ctrl& c) {
   pc.refit = update && sc.refit_period > 0 && (c.v % sc.refit_period) == 0;
   pc.reset = update && c.reset;
   pc.update = update;
-  pc.write_out = !update;
+  pc.write_out = c.mode == kEval || c.mode == kFinal;
   pc.rd = c.rd;
   pc.wr = c.wr;
   return pc;
@@ -1384,6 +1503,13 @@ __global__ void __launch_bounds__(kGridBlock) solve_kernel(Drop d, Sched sc) {
   cg::grid_group grid = cg::this_grid();
   const int b = blockIdx.x, G = gridDim.x;
   while (c.mode != kDone) {
+    if (c.mode == kRepair) {
+      for (int n = b * blockDim.x + threadIdx.x; n < d.N; n += G * blockDim.x) repair_subcarrier(d, c.rd, n);
+      grid.sync();
+      if (threadIdx.x == 0) c.mode = kFinal;
+      __syncthreads();
+      continue;
+    }
     const PassConst pc = pass_const(sc, c);
     begin_pass(d, s, c.rd);
     const int nb = (d.N - b + G - 1) / G;  // my subcarriers: b, b+G, ...
@@ -1674,6 +1800,13 @@ __device__ __attribute__((always_inline)) void solve_single(const Drop& d, const
   if (threadIdx.x == 0) s_c = initial_ctrl(d.pstatic, d.start_eval);
   __syncthreads();
   while (s_c.mode != kDone) {
+    if (s_c.mode == kRepair) {
+      for (int n = threadIdx.x; n < d.N; n += blockDim.x) repair_subcarrier(d, s_c.rd, n);
+      __syncthreads();
+      if (threadIdx.x == 0) s_c.mode = kFinal;
+      __syncthreads();
+      continue;
+    }
     const PassConst pc = pass_const(sd, s_c);
     if (threadIdx.x == 0) {
       s_changes = 0;
@@ -1708,6 +1841,13 @@ __device__ __attribute__((always_inline)) void solve_group(const Drop& d, const 
   if (threadIdx.x == 0) c = initial_ctrl(d.pstatic, d.start_eval);
   bool ok = group_sync(d.bar, G);
   while (ok && c.mode != kDone) {
+    if (c.mode == kRepair) {
+      for (int n = r * blockDim.x + threadIdx.x; n < d.N; n += G * blockDim.x) repair_subcarrier(d, c.rd, n);
+      if (!(ok = group_sync(d.bar, G))) break;
+      if (threadIdx.x == 0) c.mode = kFinal;
+      __syncthreads();
+      continue;
+    }
     const PassConst pc = pass_const(sd, c);
     begin_pass(d, s, c.rd);
     const int nb = (d.N - r + G - 1) / G;

@@ -862,3 +862,62 @@ def test_stall_rule_ends_dual_loops_without_progress():
     assert r.ee == pytest.approx(refeval.evaluate(d, P)["ee"], rel=1e-12)
     r0 = oracle.solve(d, oracle.Params(fixed_count=0, stall_sweeps=0, max_dinkelbach=1))
     assert r0.trace_sweeps[0] == op.sweeps_per_dinkelbach
+
+
+def _sic_broken_state(streaming_weak):
+    """Two RRHs, one subcarrier: RRH 0 serves users 0 and 1 together, RRH 1
+    serves user 2 at a power whose interference reaches user 0 ten thousand
+    times more than user 1.  User 0 has the larger raw gain but, under that
+    interference, the smaller normalised gain: the pair breaks C14."""
+    gain = np.zeros((2, 1, 3))
+    gain[0, 0] = [1e-10, 0.8e-10, 1e-14]
+    gain[1, 0] = [1e-9, 1e-13, 1e-10]
+    ut = [0, 1 if streaming_weak else 0, 0]
+    d = custom_drop(gain, user_type=ut, pmax=[1.0, 1.0], eta=[4.0, 2.0], noise=1e-15, l=2,
+                    arrival=[0.0, 64e3, 0.0], delay=[0.0, 0.05, 0.0])
+    p0 = np.zeros((2, 1, 3))
+    p0[0, 0, 0], p0[0, 0, 1], p0[1, 0, 2] = 0.01, 0.02, 0.1
+    return d, p0
+
+
+@pytest.mark.parametrize("streaming_weak", [True, False])
+def test_c14_repair_dissolves_the_breaking_pair(streaming_weak):
+    """The repair a solve applies before it returns (C8/C14): the breaking
+    pair loses its elastic user when the other is streaming, otherwise the
+    user of lower rate (the independent evaluator's rates); the result meets
+    C14 and nothing else changes."""
+    d, p0 = _sic_broken_state(streaming_weak)
+    assert refeval.sic_violation(d, p0) > 0.5
+    st = oracle.State(d, oracle.Params(fixed_count=0), warm=dict(p0=p0))
+    sel0, p_0, *_ = st.slots()
+    assert sorted(sel0[0, 0].tolist()) == [0, 1] and sel0[1, 0, 0] == 2
+    rates = refeval.evaluate(d, p0)["user_rate"]
+    st.repair_sic()
+    sel, p, *_ = st.slots()
+    st.close()
+    if streaming_weak:
+        gone = 0  # the elastic one of (elastic 0, streaming 1)
+    else:
+        gone = 0 if rates[0] < rates[1] else 1
+    kept = 1 - gone
+    assert sorted(k for k in sel[0, 0].tolist() if k >= 0) == [kept]
+    assert sel[1, 0, 0] == 2 and p[1, 0, 0] == p_0[1, 0, 0]
+    P = np.zeros_like(p0)
+    P[0, 0, kept], P[1, 0, 2] = p0[0, 0, kept], p0[1, 0, 2]
+    assert refeval.sic_violation(d, P) == 0.0
+
+
+def test_every_output_meets_c14():
+    """Drops of the ragged batch generator whose dual loop leaves C14 pairs
+    broken, and the 5-RRH configuration: every returned allocation meets
+    C12-C14 (the independent evaluator), and EE = R/P of it."""
+    drops = synth.make_batch(4096, seed=0, indices=[2061, 40, 1492, 2322, 56])
+    drops += [synth.make_drop(synth.CFG2, s, 0) for s in range(4)]
+    for d in drops:
+        r = oracle.solve(d, oracle.Params(fixed_count=0))
+        P = refeval.dense_from_slots(d, r.sel, r.slot_power)
+        ok = refeval.feasibility(d, P, d.l, psi=psi_of(d))
+        assert all(ok.values()), (d.index, ok)
+        assert refeval.sic_violation(d, P) == 0.0 and r.viol_sic == 0.0
+        assert r.status_flags & oracle.SIC_INFEASIBLE == 0
+        assert r.ee == pytest.approx(refeval.evaluate(d, P)["ee"], rel=1e-12)
