@@ -38,6 +38,7 @@
  */
 #ifndef ALLOC_H
 #define ALLOC_H
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -222,6 +223,22 @@ ALLOC_API int alloc_batch_results(alloc_batch* batch, alloc_result* results);
 /* Duration of the last run's graph in ms (HIP events on the context's stream). */
 ALLOC_API double alloc_batch_last_ms(alloc_batch* batch);
 ALLOC_API void alloc_batch_destroy(alloc_batch* batch);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * alloc_solve of one cold-started drop that calls no hipMalloc, hipFree or
+ * other allocating routine.  Its workspace (the drop's copied inputs, solver
+ * state, partials and outputs before they are copied out) is a fixed device
+ * array of alloc_noalloc_max_bytes() bytes (64 MiB) that the library holds on
+ * every device it runs on until the process ends; a drop whose workspace
+ * does not fit (with device gains, the 17 x 1024 x 256 configuration fits)
+ * returns ALLOC_ETOOBIG before any work.  Same arguments, method, results
+ * and errors as alloc_solve otherwise (no warm start).  Every call on one
+ * device shares that array: calls that overlap on one device, from any
+ * context or stream, race and must be serialised by the caller. */
+ALLOC_API int alloc_solve_noalloc(alloc_ctx* ctx, const alloc_problem* prob, const alloc_params* prm,
+                                  alloc_result* res);
+ALLOC_API size_t alloc_noalloc_max_bytes(void);
 
 ALLOC_API const char* alloc_strerror(int code);
 

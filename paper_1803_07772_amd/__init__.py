@@ -89,7 +89,8 @@ EXPORTS = ("alloc_ctx_create", "alloc_ctx_destroy", "alloc_params_default", "all
            "alloc_mlp_features", "alloc_mlp_forward", "alloc_mlp_grad", "alloc_mlp_train_step",
            "alloc_mlp_adamw", "alloc_mlp_rows", "alloc_mlp_warm", "alloc_solve_mlp",
            "alloc_solve_batch_mlp", "alloc_mlp_last_ms", "alloc_batch_create", "alloc_batch_run",
-           "alloc_batch_results", "alloc_batch_last_ms", "alloc_batch_destroy")
+           "alloc_batch_results", "alloc_batch_last_ms", "alloc_batch_destroy", "alloc_solve_noalloc",
+           "alloc_noalloc_max_bytes")
 
 
 def load():
@@ -131,6 +132,11 @@ def load():
         lib.alloc_batch_last_ms.restype = ctypes.c_double
         lib.alloc_batch_destroy.argtypes = [ctypes.c_void_p]
         lib.alloc_batch_destroy.restype = None
+        lib.alloc_solve_noalloc.argtypes = [ctypes.c_void_p, ctypes.POINTER(_Problem),
+                                            ctypes.POINTER(_Params), ctypes.POINTER(_Result)]
+        lib.alloc_solve_noalloc.restype = ctypes.c_int
+        lib.alloc_noalloc_max_bytes.argtypes = []
+        lib.alloc_noalloc_max_bytes.restype = ctypes.c_size_t
         _lib = lib
     return _lib
 
@@ -433,6 +439,23 @@ class Context:
         _check(load().alloc_solve(self._h, ctypes.byref(pb), ctypes.byref(pc),
                                   ctypes.byref(wm) if wm is not None else None, ctypes.byref(res)))
         return to_result(res, out, dense)
+
+    def solve_noalloc(self, drop, params: Params | None = None, gain=None, pmask=None, weight=None,
+                      dense_power: bool = False) -> Result:
+        """Solve one drop (cold start) in the library's fixed device
+        workspace: no device memory is allocated (alloc_solve_noalloc)."""
+        params = params or Params()
+        keep = []
+        pb, flags = problem_struct(drop, keep, gain, pmask, weight)
+        res, out, dense = result_struct(drop, dense_power)
+        pc = params._c(flags)
+        _check(load().alloc_solve_noalloc(self._h, ctypes.byref(pb), ctypes.byref(pc), ctypes.byref(res)))
+        return to_result(res, out, dense)
+
+
+def noalloc_max_bytes() -> int:
+    """Size of the fixed device workspace of Context.solve_noalloc."""
+    return int(load().alloc_noalloc_max_bytes())
 
 
 class Batch:

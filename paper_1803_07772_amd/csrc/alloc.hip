@@ -31,6 +31,14 @@
 
 namespace cg = cooperative_groups;
 
+// Fixed workspace of alloc_solve_noalloc (callers that cannot allocate):
+// every device the library runs on holds one copy, at its own address, until
+// the process ends.  Host code never uses this name as an address: each
+// context looks up its device's copy once (hipGetSymbolAddress, in
+// alloc_ctx_create) and passes that pointer to the kernels.
+constexpr size_t kScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
 namespace {
 
 constexpr double kLn2 = 0.69314718055994530942;
@@ -2175,6 +2183,11 @@ int alloc_ctx_create(int device, void* hip_stream, alloc_ctx** out) {
   c->last_ms = -1.0;
   c->refs = 0;
   c->closed = 0;
+  c->scratch = nullptr;
+  if (hipGetSymbolAddress((void**)&c->scratch, HIP_SYMBOL(scratch)) != hipSuccess || !c->scratch) {
+    delete c;
+    return ALLOC_EDEVICE;
+  }
   if (hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
     delete c;
     return ALLOC_EDEVICE;
@@ -2237,8 +2250,11 @@ void finish_result(const Ctrl& cf, const double* ur, int K, alloc_result* res) {
   res->status_flags = flags;
 }
 
-int solve_one(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, const alloc_warm* warm,
-              const DevWarm* dev, alloc_result* res) {
+// alloc_solve on the context's grow-only workspace, or on a fixed one
+// (fixed != nullptr: fixed_bytes of device memory; a problem whose layout
+// needs more is rejected with ALLOC_ETOOBIG and nothing is allocated).
+int solve_one_ws(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, const alloc_warm* warm,
+                 const DevWarm* dev, alloc_result* res, char* fixed, size_t fixed_bytes) {
   if (!ctx || !res) return ALLOC_EINVAL;
   if (warm && dev) return ALLOC_EINVAL;
   int rc = validate(pb, prm);
@@ -2329,14 +2345,21 @@ int solve_one(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, 
   const size_t oP0s = lay.add(has_p0 ? sizeof(double) * M * K : 0);
   const size_t oXi0 = lay.add(h_xi ? sizeof(double) * M : 0);
   const size_t oZ0 = lay.add(h_z ? sizeof(double) * K : 0);
-  if (lay.total > ctx->ws_bytes) {
-    if (ctx->ws) (void)hipFree(ctx->ws);
-    ctx->ws = nullptr;
-    ctx->ws_bytes = 0;
-    if (hipMalloc((void**)&ctx->ws, lay.total) != hipSuccess) return ALLOC_ENOMEM;
-    ctx->ws_bytes = lay.total;
+  const size_t oDense = lay.add(res->power && !out_dev ? sizeof(float) * n3 : 0);
+  char* ws;
+  if (fixed) {
+    if (lay.total > fixed_bytes) return ALLOC_ETOOBIG;
+    ws = fixed;
+  } else {
+    if (lay.total > ctx->ws_bytes) {
+      if (ctx->ws) (void)hipFree(ctx->ws);
+      ctx->ws = nullptr;
+      ctx->ws_bytes = 0;
+      if (hipMalloc((void**)&ctx->ws, lay.total) != hipSuccess) return ALLOC_ENOMEM;
+      ctx->ws_bytes = lay.total;
+    }
+    ws = ctx->ws;
   }
-  char* ws = ctx->ws;
   hipStream_t st = ctx->stream;
   auto h2d = [&](size_t off, const void* src, size_t bytes) {
     return bytes == 0 || hipMemcpyAsync(ws + off, src, bytes, hipMemcpyHostToDevice, st) == hipSuccess;
@@ -2445,21 +2468,14 @@ int solve_one(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, 
        d2o(res->zeta, d.zeta, sizeof(double) * K) && d2o(res->user_rate, d.user_rate, sizeof(double) * K);
   if (NP > 0) ok = ok && d2o(res->zeta_sic, d.out_zs, sizeof(double) * M * N * NP);
   if (!ok) return ALLOC_EDEVICE;
-  if (res->power) {
-    float* dense = res->power;
-    float* tmp = nullptr;
-    if (!out_dev) {
-      if (hipMallocAsync((void**)&tmp, sizeof(float) * n3, st) != hipSuccess) return ALLOC_ENOMEM;
-      dense = tmp;
-    }
+  if (res->power) {  // dense powers: written in place on the device, or staged in the workspace
+    float* dense = out_dev ? res->power : (float*)(ws + oDense);
     hipLaunchKernelGGL(dense_kernel, dim3(std::min<size_t>((n3 + tb - 1) / tb, 65535)), dim3(tb), 0, st, d,
                        dense);
     hipLaunchKernelGGL(scatter_kernel, dim3((M * N + tb - 1) / tb), dim3(tb), 0, st, d, dense);
-    if (tmp) {
-      if (hipMemcpyAsync(res->power, tmp, sizeof(float) * n3, hipMemcpyDeviceToHost, st) != hipSuccess)
-        return ALLOC_EDEVICE;
-      (void)hipFreeAsync(tmp, st);
-    }
+    if (!out_dev &&
+        hipMemcpyAsync(res->power, dense, sizeof(float) * n3, hipMemcpyDeviceToHost, st) != hipSuccess)
+      return ALLOC_EDEVICE;
   }
   Ctrl cf;
   if (hipMemcpyAsync(&cf, d.ctrl, sizeof cf, hipMemcpyDeviceToHost, st) != hipSuccess) return ALLOC_EDEVICE;
@@ -2475,6 +2491,11 @@ int solve_one(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, 
   }
   finish_result(cf, ur.data(), K, res);
   return ALLOC_OK;
+}
+
+int solve_one(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, const alloc_warm* warm,
+              const DevWarm* dev, alloc_result* res) {
+  return solve_one_ws(ctx, pb, prm, warm, dev, res, nullptr, 0);
 }
 
 // Host side of one batched solve: the packed device layout of every drop's
@@ -2997,6 +3018,13 @@ int alloc_batch_results(alloc_batch* b, alloc_result* results) {
 }
 
 double alloc_batch_last_ms(alloc_batch* b) { return b ? b->last_ms : -1.0; }
+
+int alloc_solve_noalloc(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, alloc_result* res) {
+  if (!ctx || !prm || ctx->closed) return ALLOC_EINVAL;
+  return alloc_internal::solve_one_ws(ctx, pb, prm, nullptr, nullptr, res, ctx->scratch, kScratchBytes);
+}
+
+size_t alloc_noalloc_max_bytes(void) { return kScratchBytes; }
 
 int alloc_solve_batch(alloc_ctx* ctx, int32_t B, const alloc_problem* probs, const alloc_params* prm,
                       const alloc_warm* warms, alloc_result* results) {

@@ -20,6 +20,7 @@ struct alloc_ctx {
   double last_ms;
   int refs;    // live batches and networks made on this context
   int closed;  // alloc_ctx_destroy was called while refs > 0: freed with the last of them
+  char* scratch;  // device address of the library's fixed workspace on this device
 };
 
 namespace alloc_internal {
@@ -43,6 +44,10 @@ using WarmFn = std::function<int(int b, DevWarm* out)>;
 // alloc_solve with the warm start in device memory (dev may be null).
 int solve_one(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, const alloc_warm* host,
               const DevWarm* dev, alloc_result* res);
+// The same on a fixed device workspace of fixed_bytes (fixed != null): a
+// layout that does not fit is rejected with ALLOC_ETOOBIG.
+int solve_one_ws(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, const alloc_warm* host,
+                 const DevWarm* dev, alloc_result* res, char* fixed, size_t fixed_bytes);
 
 // alloc_solve_batch with warm starts from host arrays (host, [B] or null) or
 // from a producer (fn, or null).
