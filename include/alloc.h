@@ -29,7 +29,8 @@
  *                    rate or delay target <= 0, NULL required pointer;
  *      ALLOC_ETOOBIG the problem exceeds a kernel limit (see below);
  *      ALLOC_ENOMEM  device allocation failed;
- *      ALLOC_EDEVICE a HIP runtime call failed.
+ *      ALLOC_EDEVICE a HIP runtime call failed;
+ *      ALLOC_EFILE   (network files only) a file could not be read or written.
  *    Non-fatal conditions are reported in alloc_result.status_flags.
  *  - Limits: M <= 32, l <= 4, K <= 1024, M*K <= 4608 (one subcarrier's gain
  *    slab and its state must fit one workgroup's LDS).
@@ -52,6 +53,7 @@ extern "C" {
 #define ALLOC_ENOMEM (-12)
 #define ALLOC_EDEVICE (-5)
 #define ALLOC_ETOOBIG (-27)
+#define ALLOC_EFILE (-2) /* a file could not be read or written, or has the wrong contents */
 
 /* alloc_params.flags */
 #define ALLOC_GAIN_ON_DEVICE 1u /* problem.gain is a device pointer */
@@ -61,6 +63,8 @@ extern "C" {
 /* alloc_result.status_flags */
 #define ALLOC_NOT_CONVERGED 1u  /* Dinkelbach stopped at max_dinkelbach */
 #define ALLOC_QOS_INFEASIBLE 2u /* C13: a streaming user ends below (1-1e-6) of its minimum rate */
+#define ALLOC_NEAR_TIE 4u       /* with tie_rel > 0: some discrete decision was within tie_rel
+                                   of going the other way (see alloc_params.tie_rel) */
 #define ALLOC_NONFINITE 8u      /* a non-finite rate or power appeared */
 #define ALLOC_SIC_INFEASIBLE 16u /* C14: a co-scheduled pair ends with SIC margin above 1e-9 */
 #define ALLOC_BUDGET_INFEASIBLE 64u /* C12: an RRH ends above (1+1e-6) of its power budget */
@@ -145,6 +149,18 @@ typedef struct {
                                     one per subcarrier and the resident number); 0 = a
                                     drop above 1.5 times the average triples per
                                     resident workgroup, by about triples/average */
+  double tie_rel;                /* 0: when positive, count the discrete decisions of the
+                                    solve whose relative margin is at most tie_rel (a
+                                    different summation order could have taken them the
+                                    other way): the SIC decoding order of two users of an
+                                    (m,n), and where a candidate would enter it (relative
+                                    difference of their normalised gains),
+                                    a candidate among the first l of its RRH's selection
+                                    order and the next one (relative difference of the
+                                    per-triple Lagrangian maxima H), and a user's best and
+                                    second-best RRH (relative difference of the sums of H);
+                                    the count is alloc_result.near_ties and a positive count
+                                    sets ALLOC_NEAR_TIE.  0: not counted (no cost) */
 } alloc_params;
 
 ALLOC_API void alloc_params_default(alloc_params* p);
@@ -187,6 +203,7 @@ typedef struct {
   double viol_sic;     /* C14: sum over co-scheduled pairs of margin - 1e-9 where positive */
   int32_t dinkelbach_iters, sweeps;
   uint32_t status_flags;
+  int32_t near_ties;   /* near-tie decisions over the solve (alloc_params.tie_rel > 0), else 0 */
 } alloc_result;
 
 /* Solve one drop on the context's stream; returns when the results are

@@ -78,6 +78,17 @@ ALLOC_API void alloc_mlp_destroy(alloc_mlp* net);
 ALLOC_API int alloc_mlp_set_params(alloc_mlp* net, const float* host, int64_t n);
 ALLOC_API int alloc_mlp_get_params(alloc_mlp* net, float* host, int64_t n);
 
+/* Save the FP32 master parameters to the file at `path` (created or
+ * replaced), or load them from it, in the safetensors layout: a little-endian
+ * uint64 header length, a JSON header with one tensor "params" (dtype F32,
+ * shape [ALLOC_MLP_NPARAMS]) and metadata naming the layer sizes, then the
+ * values.  The AdamW moments are not saved; loading resets them as
+ * alloc_mlp_set_params does.  Returns ALLOC_EFILE when the file cannot be
+ * written or read, or does not hold such a tensor; ALLOC_EINVAL for a NULL
+ * argument or a non-finite value; the network is unchanged on error. */
+ALLOC_API int alloc_mlp_save(alloc_mlp* net, const char* path);
+ALLOC_API int alloc_mlp_load(alloc_mlp* net, const char* path);
+
 /* Features [M*N*K][4] (float32, device) of every triple of a drop, in
  * [M][N][K] order.  The gain pointer follows ALLOC_GAIN_ON_DEVICE in flags. */
 ALLOC_API int alloc_mlp_features(alloc_mlp* net, const alloc_problem* prob, uint32_t flags,

@@ -21,6 +21,7 @@ ALLOC_OUT_ON_DEVICE = 2
 ALLOC_WARM_ON_DEVICE = 4
 NOT_CONVERGED = 1
 QOS_INFEASIBLE = 2
+NEAR_TIE = 4
 NONFINITE = 8
 SIC_INFEASIBLE = 16
 GROUP_TIMEOUT = 32
@@ -53,7 +54,7 @@ class _Params(ctypes.Structure):
                 ("tol_dual", ctypes.c_double), ("step0", ctypes.c_double),
                 ("qos_down", ctypes.c_double), ("flags", ctypes.c_uint32), ("max_groups", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("lds_kb", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("wave", ctypes.c_int32), ("group_triples", ctypes.c_int32)]
+                ("wave", ctypes.c_int32), ("group_triples", ctypes.c_int32), ("tie_rel", ctypes.c_double)]
 
 
 class _Warm(ctypes.Structure):
@@ -69,7 +70,7 @@ class _Result(ctypes.Structure):
                 ("power_sum", ctypes.c_double), ("viol_qos", ctypes.c_double),
                 ("viol_budget", ctypes.c_double), ("viol_sic", ctypes.c_double),
                 ("dinkelbach_iters", ctypes.c_int32),
-                ("sweeps", ctypes.c_int32), ("status_flags", ctypes.c_uint32)]
+                ("sweeps", ctypes.c_int32), ("status_flags", ctypes.c_uint32), ("near_ties", ctypes.c_int32)]
 
 
 # NumPy mirrors of the C structs (same field order, offsets and size), so
@@ -79,7 +80,7 @@ _PROBLEM_DTYPE = np.dtype({"names": [f for f, _ in _Problem._fields_],
                            "offsets": [getattr(_Problem, f).offset for f, _ in _Problem._fields_],
                            "itemsize": ctypes.sizeof(_Problem)})
 _RESULT_DTYPE = np.dtype({"names": [f for f, _ in _Result._fields_],
-                          "formats": ["<u8"] * 8 + ["<f8"] * 6 + ["<i4", "<i4", "<u4"],
+                          "formats": ["<u8"] * 8 + ["<f8"] * 6 + ["<i4", "<i4", "<u4", "<i4"],
                           "offsets": [getattr(_Result, f).offset for f, _ in _Result._fields_],
                           "itemsize": ctypes.sizeof(_Result)})
 
@@ -90,7 +91,7 @@ EXPORTS = ("alloc_ctx_create", "alloc_ctx_destroy", "alloc_params_default", "all
            "alloc_mlp_adamw", "alloc_mlp_rows", "alloc_mlp_warm", "alloc_solve_mlp",
            "alloc_solve_batch_mlp", "alloc_mlp_last_ms", "alloc_batch_create", "alloc_batch_run",
            "alloc_batch_results", "alloc_batch_last_ms", "alloc_batch_destroy", "alloc_solve_noalloc",
-           "alloc_noalloc_max_bytes")
+           "alloc_noalloc_max_bytes", "alloc_mlp_save", "alloc_mlp_load")
 
 
 def load():
@@ -163,12 +164,13 @@ class Params:
     block: int = 0
     wave: int = 0
     group_triples: int = 0
+    tie_rel: float = 0.0
 
     def _c(self, flags: int) -> _Params:
         return _Params(self.max_dinkelbach, self.sweeps_per_dinkelbach, self.refit_period,
                        self.fixed_count, self.stall_sweeps, self.tol_dinkelbach, self.tol_dual,
                        self.step0, self.qos_down, flags, self.max_groups, self.tile, self.lds_kb,
-                       self.block, self.wave, self.group_triples)
+                       self.block, self.wave, self.group_triples, self.tie_rel)
 
 
 def default_params() -> Params:
@@ -176,7 +178,7 @@ def default_params() -> Params:
     load().alloc_params_default(ctypes.byref(p))
     return Params(p.max_dinkelbach, p.sweeps_per_dinkelbach, p.refit_period, p.fixed_count,
                   p.stall_sweeps, p.tol_dinkelbach, p.tol_dual, p.step0, p.qos_down, p.max_groups,
-                  p.tile, p.lds_kb, p.block, p.wave, p.group_triples)
+                  p.tile, p.lds_kb, p.block, p.wave, p.group_triples, p.tie_rel)
 
 
 @dataclasses.dataclass
@@ -198,6 +200,7 @@ class Result:
     viol_budget: float = 0.0
     viol_sic: float = 0.0
     power: np.ndarray | None = None
+    near_ties: int = 0
 
 
 def _hp(keep, a, dtype):
@@ -245,7 +248,7 @@ def result_struct(drop, dense_power=False):
                   dense.ctypes.data if dense is not None else None,
                   out["rrh_of_user"].ctypes.data, out["xi"].ctypes.data,
                   out["zeta"].ctypes.data, out["zeta_sic"].ctypes.data if NP else None,
-                  out["user_rate"].ctypes.data, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0)
+                  out["user_rate"].ctypes.data, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0, 0, 0, 0)
     return res, out, dense
 
 
@@ -253,7 +256,8 @@ def to_result(res, out, dense) -> "Result":
     return Result(ee=res.ee, rate_sum=res.rate_sum, power_sum=res.power_sum,
                   dinkelbach_iters=res.dinkelbach_iters, sweeps=res.sweeps,
                   status_flags=res.status_flags, viol_qos=res.viol_qos,
-                  viol_budget=res.viol_budget, viol_sic=res.viol_sic, power=dense, **out)
+                  viol_budget=res.viol_budget, viol_sic=res.viol_sic, power=dense,
+                  near_ties=res.near_ties, **out)
 
 
 class Context:
@@ -416,7 +420,8 @@ class Context:
                              user_rate=ur[k0:k1], ee=r.ee, rate_sum=r.rate_sum,
                              power_sum=r.power_sum, dinkelbach_iters=r.dinkelbach_iters,
                              sweeps=r.sweeps, status_flags=r.status_flags, viol_qos=r.viol_qos,
-                             viol_budget=r.viol_budget, viol_sic=r.viol_sic, power=dense))
+                             viol_budget=r.viol_budget, viol_sic=r.viol_sic, power=dense,
+                             near_ties=int(r.near_ties)))
         return rs
 
     def solve(self, drop, params: Params | None = None, gain=None, warm=None, pmask=None,

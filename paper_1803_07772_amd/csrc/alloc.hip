@@ -96,6 +96,7 @@ struct Ctrl {
 struct Sched {
   int max_d, sweeps, refit_period, fixed, stall, tile;
   double tol_d, tol_dual, step0, qos_down;
+  double tie_rel;  // > 0: count near-tie decisions in Drop::ties
 };
 
 // Reduced values of one pass, the input of the loop control.
@@ -199,6 +200,7 @@ struct Drop {
   int start_eval;          // the initial allocation is Dinkelbach's p^0 (warm start)
   int group;               // batched solver: workgroups that solve the drop together
   unsigned* bar;           // [3] their barrier: arrivals, generation, broken
+  unsigned* ties;          // near-tie decisions (Sched::tie_rel > 0), zeroed before the solve
 };
 
 // Pointers into the workgroup's LDS: 32-bit addresses, direct LDS access.
@@ -210,6 +212,11 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 template <class T>
 __device__ __forceinline__ GLB T* gl(T* p) {
   return (GLB T*)p;
+}
+
+// One near-tie decision (rare: only where a margin is within tie_rel).
+__device__ __forceinline__ void note_tie(const Drop& d) {
+  __hip_atomic_fetch_add(gl(d.ties), 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // LDS carve-up for one workgroup.  The table of array pointers itself sits in
@@ -704,6 +711,7 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
       if (q2 == q || k2 < 0) continue;
       const double u2 = s.u[IX_MK(t, m, k2)];
       if (u2 < uq || (u2 == uq && k2 < k)) ++pos;
+      if (sc.tie_rel > 0.0 && k2 > k && fabs(u2 - uq) <= sc.tie_rel * fmax(u2, uq)) note_tie(d);
     }
     s.vslot[IX_ML(t, m, pos)] = q;
     s.vuser[IX_ML(t, m, pos)] = k;
@@ -898,6 +906,8 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
       const double ua = s.vu[IX_ML(t, m, a)];
       if (ka == k) q = a;
       if (ua < u || (ua == u && ka < k)) ++pos;
+      // where a candidate would enter the decoding order
+      if (sc.tie_rel > 0.0 && ka != k && fabs(ua - u) <= sc.tie_rel * fmax(ua, u)) note_tie(d);
     }
     const double Sb = s.vpre[IX_ML1(t, m, q >= 0 ? q : pos)];
     const double pin = s.vT[IX_ML1(t, m, q >= 0 ? q + 1 : pos)];
@@ -956,6 +966,15 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
       rank += (hj > h) || (hj == h && j < k);
     }
     s.ord[IX_SK(t, s.grp_off[m] + rank)] = k;
+    if (sc.tie_rel > 0.0 && rank < L) {  // k and the next candidate in H order
+      double gap = INFINITY;
+      for (int e = s.grp_off[m]; e < s.grp_off[m + 1]; ++e) {
+        const int j = s.grp[e];
+        const double hj = s.Hc[IX_SK(t, j)];
+        if (j != k && hj > 0.0 && (hj < h || (hj == h && j > k))) gap = fmin(gap, h - hj);
+      }
+      if (gap <= sc.tie_rel * h) note_tie(d);
+    }
   }
   tm.sync();
   // ... then, one item per slot, each (subcarrier, RRH)'s new selection
@@ -1166,6 +1185,23 @@ __device__ inline int assoc_of(int M, int before, bool elastic, F&& S) {
   return elastic ? -1 : before;
 }
 
+// Whether the best and second-best RRH of a user are within tie_rel of each
+// other (both with a positive sum of H).
+template <class F>
+__device__ inline bool assoc_near_tie(int M, double tie_rel, F&& S) {
+  double best = -INFINITY, second = -INFINITY;
+  for (int m = 0; m < M; ++m) {
+    const double v = S(m);
+    if (v > best) {
+      second = best;
+      best = v;
+    } else if (v > second) {
+      second = v;
+    }
+  }
+  return best > 0.0 && second > 0.0 && best - second <= tie_rel * best;
+}
+
 // Reductions across workgroups: users k = b, b+G, ... per workgroup (rates,
 // association into buffer wr, zeta' steps, partial C13 violation);
 // workgroup 0 also does the per-RRH and scalar sums.
@@ -1188,6 +1224,7 @@ __device__ void reduce_pass(const Drop& d, const Sched& sc, const Ctrl& c, Lds& 
       if (update) {
         const int before = gl(d.A)[(size_t)c.rd * K + k];
         const int after = assoc_of(M, before, el, [&](int m) { return s.tmp[2 + m]; });
+        if (sc.tie_rel > 0.0 && assoc_near_tie(M, sc.tie_rel, [&](int m) { return s.tmp[2 + m]; })) note_tie(d);
         gl(d.A)[(size_t)c.wr * K + k] = after;
         if (after != before) ++changes;
         if (!el) {
@@ -1649,6 +1686,7 @@ __device__ void block_reduce(const Drop& d, const Sched& sc, int wr, Lds& s, boo
     if (!update) continue;
     const int before = s.Al[k];
     const int after = assoc_of(M, before, el, [&](int m) { return s.Sacc[m * K + k]; });
+    if (sc.tie_rel > 0.0 && assoc_near_tie(M, sc.tie_rel, [&](int m) { return s.Sacc[m * K + k]; })) note_tie(d);
     gl(d.A)[(size_t)wr * K + k] = after;
     if (after != before) atomicAdd(changes, 1);
     if (!el) {
@@ -2077,7 +2115,7 @@ int validate(const alloc_problem* pb, const alloc_params* prm) {
   if (!std::isfinite(pb->noise_w)) return ALLOC_EINVAL;
   if (pb->M > kMaxM || pb->l > kMaxL || pb->K > kMaxK || pb->M * pb->K > kMaxMK) return ALLOC_ETOOBIG;
   if (prm->sweeps_per_dinkelbach < 1 || prm->max_dinkelbach < 1 || prm->max_groups < 0 || prm->tile < 0 ||
-      prm->group_triples < 0 ||
+      prm->group_triples < 0 || !(prm->tie_rel >= 0.0) || !std::isfinite(prm->tie_rel) ||
       prm->lds_kb < 0 || !(prm->block == 0 || prm->block == 256 || prm->block == 512 || prm->block == 1024) || prm->wave < 0 ||
       prm->wave > 16)
     return ALLOC_EINVAL;
@@ -2146,6 +2184,7 @@ void alloc_params_default(alloc_params* p) {
   p->block = 0;
   p->wave = 0;
   p->group_triples = 0;
+  p->tie_rel = 0.0;
 }
 
 int alloc_ctx_set_timing(alloc_ctx* ctx, int enable) {
@@ -2163,6 +2202,7 @@ const char* alloc_strerror(int code) {
     case ALLOC_ENOMEM: return "device memory allocation failed";
     case ALLOC_EDEVICE: return "HIP runtime error";
     case ALLOC_ETOOBIG: return "problem exceeds a kernel limit (M<=32, l<=4, K<=1024, M*K<=4608)";
+    case ALLOC_EFILE: return "file could not be read or written, or is not a saved network";
     default: return "unknown error";
   }
 }
@@ -2232,8 +2272,10 @@ void ctx_release(alloc_ctx* c) {
 namespace alloc_internal {
 
 // Scalars and flags of a result from the final loop control and rates.
-void finish_result(const Ctrl& cf, const double* ur, int K, alloc_result* res) {
+void finish_result(const Ctrl& cf, const double* ur, int K, unsigned ties, alloc_result* res) {
   uint32_t flags = cf.flags;
+  if (ties > 0) flags |= ALLOC_NEAR_TIE;
+  res->near_ties = (int32_t)std::min<unsigned>(ties, 0x7fffffffu);
   if (cf.Vq > 0.0) flags |= ALLOC_QOS_INFEASIBLE;
   if (cf.Vp > 0.0) flags |= ALLOC_BUDGET_INFEASIBLE;
   if (cf.Vs > 0.0) flags |= ALLOC_SIC_INFEASIBLE;
@@ -2330,7 +2372,7 @@ int solve_one_ws(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* pr
   const size_t oPep = lay.add(sizeof(double) * G * M);
   const size_t oRP = lay.add(sizeof(double) * G);
   const size_t oDp = lay.add(sizeof(double) * G);
-  const size_t oChg = lay.add(sizeof(int) * 2);
+  const size_t oChg = lay.add(sizeof(int) * 3);  // two change counters and the near-tie count
   const size_t oRed = lay.add(sizeof(double) * 8);
   const size_t oUr = lay.add(sizeof(double) * K);
   const size_t oRrh = lay.add(sizeof(int) * K);
@@ -2376,8 +2418,8 @@ int solve_one_ws(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* pr
   // a warm initial allocation is Dinkelbach's p^0: evaluate it first
   const Ctrl c0 = initial_ctrl(pstatic, has_p0);
   ok = ok && h2d(oCtrl, &c0, sizeof c0);
-  static const int zeros2[2] = {0, 0};
-  ok = ok && h2d(oChg, zeros2, sizeof zeros2);
+  static const int zeros3[3] = {0, 0, 0};
+  ok = ok && h2d(oChg, zeros3, sizeof zeros3);
   if (!ok) return ALLOC_EDEVICE;
 
   Drop d;
@@ -2413,6 +2455,7 @@ int solve_one_ws(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* pr
   d.R_part = (double*)(ws + oRP);
   d.d_part = (double*)(ws + oDp);
   d.chg_count = (int*)(ws + oChg);
+  d.ties = (unsigned*)(ws + oChg) + 2;
   d.red = (double*)(ws + oRed);
   d.user_rate = (double*)(ws + oUr);
   d.out_sel = (int*)(ws + oOs);
@@ -2446,6 +2489,7 @@ int solve_one_ws(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* pr
   sc.tol_dual = prm->tol_dual;
   sc.step0 = prm->step0;
   sc.qos_down = prm->qos_down;
+  sc.tie_rel = prm->tie_rel;
   sc.tile = T;
   void* args[] = {(void*)&d, (void*)&sc};
   if (ctx->timing && hipEventRecord(ctx->ev0, st) != hipSuccess) return ALLOC_EDEVICE;
@@ -2479,6 +2523,8 @@ int solve_one_ws(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* pr
   }
   Ctrl cf;
   if (hipMemcpyAsync(&cf, d.ctrl, sizeof cf, hipMemcpyDeviceToHost, st) != hipSuccess) return ALLOC_EDEVICE;
+  unsigned ties = 0;
+  if (hipMemcpyAsync(&ties, d.ties, sizeof ties, hipMemcpyDeviceToHost, st) != hipSuccess) return ALLOC_EDEVICE;
   std::vector<double> ur(K);
   if (hipMemcpyAsync(ur.data(), d.user_rate, sizeof(double) * K, hipMemcpyDeviceToHost, st) != hipSuccess)
     return ALLOC_EDEVICE;
@@ -2489,7 +2535,7 @@ int solve_one_ws(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* pr
     if (hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1) != hipSuccess) return ALLOC_EDEVICE;
     ctx->last_ms = ms;
   }
-  finish_result(cf, ur.data(), K, res);
+  finish_result(cf, ur.data(), K, ties, res);
   return ALLOC_OK;
 }
 
@@ -2503,6 +2549,7 @@ int solve_one(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, 
 struct BatchOff {
   size_t G, psi, el, pmax, eta, pmask, w, A, sel, p, al, be, zs, xi, zeta, ur, os, op, oz;
   size_t Sp, rp, rhp, psp, pep, Rp, dp, svp, vqp, zrp, chg, red, bar;  // group drops only
+  size_t ties;                                          // near-tie count (zeroed with the barriers)
   size_t wp0, wxi, wz;                                  // host warm starts, staged
 };
 
@@ -2677,6 +2724,7 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
     }
   }
   P.bar_begin = tot;
+  for (int b = 0; b < B; ++b) P.off[b].ties = add(sizeof(unsigned));
   for (int b = 0; b < B; ++b)
     if (P.group[b] > 1) P.off[b].bar = add(sizeof(unsigned) * 3);
   P.bar_end = tot;
@@ -2749,6 +2797,7 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
     d.out_sel = (int*)(ws + o.os);
     d.out_p = (double*)(ws + o.op);
     d.out_zs = (double*)(ws + o.oz);
+    d.ties = (unsigned*)(ws + o.ties);
     const int g = P.group[b];
     d.group = g;
     if (g > 1) {
@@ -2800,6 +2849,7 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
   sc.tol_dual = prm->tol_dual;
   sc.step0 = prm->step0;
   sc.qos_down = prm->qos_down;
+  sc.tie_rel = prm->tie_rel;
   sc.tile = 1;
   P.lds = budget;
   P.grid = std::min(S, cap);
@@ -2871,8 +2921,10 @@ int batch_enqueue(hipStream_t st, const BatchPlan& P) {
 int batch_collect(hipStream_t st, const BatchPlan& P, alloc_result* results) {
   std::vector<char> out(P.out_end - P.out_begin);
   std::vector<Ctrl> ctrls(P.B);
+  std::vector<char> bars(P.bar_end - P.bar_begin);  // near-tie counts and barrier words
   if (hipMemcpyAsync(out.data(), P.ws + P.out_begin, out.size(), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipMemcpyAsync(ctrls.data(), P.ws + P.oCtrls, sizeof(Ctrl) * P.B, hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipMemcpyAsync(bars.data(), P.ws + P.bar_begin, bars.size(), hipMemcpyDeviceToHost, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess)
     return ALLOC_EDEVICE;
   for (int b = 0; b < P.B; ++b) {
@@ -2902,7 +2954,9 @@ int batch_collect(hipStream_t st, const BatchPlan& P, alloc_result* results) {
         for (size_t a = 0; a < L; ++a)
           if (os[i * L + a] >= 0) r.power[i * K + os[i * L + a]] = (float)op[i * L + a];
     }
-    finish_result(ctrls[b], ur, (int)K, &r);
+    unsigned ties;
+    memcpy(&ties, bars.data() + (o.ties - P.bar_begin), sizeof ties);
+    finish_result(ctrls[b], ur, (int)K, ties, &r);
   }
   return ALLOC_OK;
 }

@@ -15,9 +15,11 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <string.h>
 
 #include <algorithm>
+#include <string>
 #include <vector>
 
 #include "alloc.h"
@@ -1133,6 +1135,53 @@ bool needs_fallback(const alloc_result& r) {
 
 }  // namespace
 
+namespace {
+
+// Finds `"key"` at object depth 1 of the header and returns the position after
+// its colon, or npos.
+size_t json_key(const std::string& h, const char* key) {
+  const std::string k = std::string("\"") + key + "\"";
+  int depth = 0;
+  bool str = false;
+  for (size_t i = 0; i < h.size(); ++i) {
+    const char c = h[i];
+    if (str) {
+      if (c == '\\') ++i;
+      else if (c == '"') str = false;
+      continue;
+    }
+    if (c == '{' || c == '[') ++depth;
+    else if (c == '}' || c == ']') --depth;
+    else if (c == '"') {
+      if (depth == 1 && h.compare(i, k.size(), k) == 0) {
+        size_t j = i + k.size();
+        while (j < h.size() && (h[j] == ' ' || h[j] == ':')) ++j;
+        return j;
+      }
+      str = true;
+    }
+  }
+  return std::string::npos;
+}
+
+// The integers of a JSON array starting at h[pos] == '['.
+bool json_ints(const std::string& h, size_t pos, std::vector<long long>* out) {
+  if (pos >= h.size() || h[pos] != '[') return false;
+  size_t i = pos + 1;
+  while (i < h.size()) {
+    while (i < h.size() && (h[i] == ' ' || h[i] == ',')) ++i;
+    if (i < h.size() && h[i] == ']') return true;
+    char* end = nullptr;
+    const long long v = strtoll(h.c_str() + i, &end, 10);
+    if (end == h.c_str() + i) return false;
+    out->push_back(v);
+    i = (size_t)(end - h.c_str());
+  }
+  return false;
+}
+
+}  // namespace
+
 extern "C" {
 
 int alloc_mlp_create(alloc_ctx* ctx, alloc_mlp** out) {
@@ -1195,6 +1244,70 @@ int alloc_mlp_get_params(alloc_mlp* net, float* host, int64_t n) {
       hipStreamSynchronize(st) != hipSuccess)
     return ALLOC_EDEVICE;
   return ALLOC_OK;
+}
+
+// The safetensors layout of a saved network: little-endian uint64 header
+// length, a JSON header (space-padded to a multiple of 8 bytes), the data.
+int alloc_mlp_save(alloc_mlp* net, const char* path) {
+  if (!net || !path) return ALLOC_EINVAL;
+  std::vector<float> w(kNP);
+  int rc = alloc_mlp_get_params(net, w.data(), kNP);
+  if (rc) return rc;
+  char buf[256];
+  snprintf(buf, sizeof buf,
+           "{\"__metadata__\":{\"n_params\":\"%lld\",\"layers\":\"4-256-256-256-3\"},"
+           "\"params\":{\"dtype\":\"F32\",\"shape\":[%lld],\"data_offsets\":[0,%lld]}}",
+           (long long)kNP, (long long)kNP, (long long)(kNP * sizeof(float)));
+  std::string hdr(buf);
+  while (hdr.size() % 8) hdr += ' ';
+  unsigned char len[8];
+  for (int i = 0; i < 8; ++i) len[i] = (unsigned char)(((uint64_t)hdr.size() >> (8 * i)) & 0xff);
+  FILE* f = fopen(path, "wb");
+  if (!f) return ALLOC_EFILE;
+  bool ok = fwrite(len, 1, 8, f) == 8 && fwrite(hdr.data(), 1, hdr.size(), f) == hdr.size() &&
+            fwrite(w.data(), sizeof(float), kNP, f) == (size_t)kNP;
+  // the data are written as the host holds them: little-endian IEEE floats
+  ok = (fclose(f) == 0) && ok;
+  return ok ? ALLOC_OK : ALLOC_EFILE;
+}
+
+int alloc_mlp_load(alloc_mlp* net, const char* path) {
+  if (!net || !path) return ALLOC_EINVAL;
+  FILE* f = fopen(path, "rb");
+  if (!f) return ALLOC_EFILE;
+  unsigned char len[8];
+  uint64_t n = 0;
+  std::string hdr;
+  std::vector<float> w;
+  bool ok = fread(len, 1, 8, f) == 8;
+  if (ok) {
+    for (int i = 0; i < 8; ++i) n |= (uint64_t)len[i] << (8 * i);
+    ok = n > 0 && n < (1u << 20);
+  }
+  if (ok) {
+    hdr.resize(n);
+    ok = fread(&hdr[0], 1, n, f) == n;
+  }
+  // the one tensor "params": F32 of shape [kNP] at the start of the data
+  size_t at = ok ? json_key(hdr, "params") : std::string::npos;
+  if (at == std::string::npos || hdr[at] != '{') ok = false;
+  std::vector<long long> shape, offs;
+  if (ok) {
+    const std::string t = hdr.substr(at, hdr.find('}', at) - at + 1);
+    const size_t dt = json_key(t, "dtype"), sh = json_key(t, "shape"), of = json_key(t, "data_offsets");
+    ok = dt != std::string::npos && t.compare(dt, 5, "\"F32\"") == 0 && sh != std::string::npos &&
+         of != std::string::npos && json_ints(t, sh, &shape) && json_ints(t, of, &offs) && shape.size() == 1 &&
+         shape[0] == kNP && offs.size() == 2 && offs[1] - offs[0] == (long long)(kNP * sizeof(float)) &&
+         offs[0] >= 0;
+  }
+  if (ok) ok = fseek(f, (long)(8 + n + offs[0]), SEEK_SET) == 0;
+  if (ok) {
+    w.resize(kNP);
+    ok = fread(w.data(), sizeof(float), kNP, f) == (size_t)kNP;
+  }
+  fclose(f);
+  if (!ok) return ALLOC_EFILE;
+  return alloc_mlp_set_params(net, w.data(), kNP);
 }
 
 int alloc_mlp_features(alloc_mlp* net, const alloc_problem* pb, uint32_t flags, float* feat) {

@@ -9,6 +9,7 @@ from __future__ import annotations
 import ctypes
 import dataclasses
 import math
+import os
 
 import numpy as np
 
@@ -64,6 +65,8 @@ def _lib():
             "alloc_solve_batch_mlp": ([vp, ctypes.c_int32, P(_Problem), P(_Params), P(_Result)],
                                       ctypes.c_int),
             "alloc_mlp_last_ms": ([vp], ctypes.c_double),
+            "alloc_mlp_save": ([vp, ctypes.c_char_p], ctypes.c_int),
+            "alloc_mlp_load": ([vp, ctypes.c_char_p], ctypes.c_int),
         }
         for name, (args, res) in sig.items():
             f = getattr(lib, name)
@@ -131,19 +134,20 @@ class MLP:
 
     def save(self, path: str):
         """Writes the FP32 master weights (the order alloc_mlp_get_params
-        returns) to a safetensors file; the optimizer's moments are not saved."""
-        from safetensors.numpy import save_file
-        save_file({"params": self.get_params()}, path,
-                  metadata={"n_params": str(N_PARAMS), "layers": "4-256-256-256-3"})
+        returns) to a safetensors file (alloc_mlp_save); the optimizer's
+        moments are not saved."""
+        _check(_lib().alloc_mlp_save(self._h, os.fsencode(path)))
 
     @classmethod
     def load(cls, ctx: Context, path: str) -> "MLP":
-        """A network on ``ctx`` with the weights save() wrote."""
-        from safetensors.numpy import load_file
-        t = load_file(path)
-        if set(t) != {"params"} or t["params"].dtype != np.float32 or t["params"].size != N_PARAMS:
-            raise ValueError(f"{path}: not a saved warm-start network")
-        return cls(ctx, t["params"])
+        """A network on ``ctx`` with the weights save() wrote (alloc_mlp_load)."""
+        net = cls(ctx)
+        try:
+            _check(_lib().alloc_mlp_load(net._h, os.fsencode(path)))
+        except Exception:
+            net.close()
+            raise
+        return net
 
     def features(self, drop, gain=None, pmask=None):
         import torch

@@ -31,6 +31,6 @@ def test_defaults_and_error_strings():
     p = pa.default_params()
     assert p == pa.Params()
     lib = pa.load()
-    for code in (0, -22, -12, -5, -27):
+    for code in (0, -22, -12, -5, -27, -2):
         assert lib.alloc_strerror(code)
     assert b"kernel limit" in lib.alloc_strerror(-27)

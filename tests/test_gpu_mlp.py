@@ -91,7 +91,14 @@ def test_get_set_params_roundtrip(ctx):
 
 
 def test_save_load_roundtrip(ctx, tmp_path):
+    """alloc_mlp_save / alloc_mlp_load: the weights come back bit for bit,
+    the file is a safetensors file that the safetensors library reads, a
+    file that library writes loads, and a file without the right tensor is
+    refused with the network unchanged."""
+    import paper_1803_07772_amd as pa
     from paper_1803_07772_amd.mlp import MLP
+    from safetensors.numpy import load_file, save_file
+    print("[gpu case] mlp save/load", flush=True)
     flat, _ = _weights(2)
     net = _net(ctx, flat)
     path = str(tmp_path / "net.safetensors")
@@ -100,11 +107,24 @@ def test_save_load_roundtrip(ctx, tmp_path):
     assert np.array_equal(back.get_params(), flat)
     X = _cuda(_feat(np.random.default_rng(9), 300))
     assert np.array_equal(back.forward(X).cpu().numpy(), net.forward(X).cpu().numpy())
-    from safetensors.numpy import save_file
+    t = load_file(path)
+    assert set(t) == {"params"} and np.array_equal(t["params"], flat)
+    other, _ = _weights(3)
+    ext = str(tmp_path / "ext.safetensors")
+    save_file({"params": other}, ext, metadata={"layers": "4-256-256-256-3"})
+    b2 = MLP.load(ctx, ext)
+    assert np.array_equal(b2.get_params(), other)
     bad = str(tmp_path / "bad.safetensors")
     save_file({"params": flat[:10]}, bad)
-    with pytest.raises(ValueError):
+    with pytest.raises(pa.AllocError):
         MLP.load(ctx, bad)
+    with pytest.raises(pa.AllocError):
+        MLP.load(ctx, str(tmp_path / "missing.safetensors"))
+    lib = pa.load()
+    assert lib.alloc_mlp_load(back._h, bad.encode()) == -2
+    assert np.array_equal(back.get_params(), flat)
+    for n in (net, back, b2):
+        n.close()
 
 
 def test_features_match_reference(ctx):

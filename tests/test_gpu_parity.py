@@ -195,3 +195,43 @@ def test_invalid_inputs_rejected(ctx):
     r = ctx.solve(d, pa.Params(sweeps_per_dinkelbach=5))
     assert np.isfinite(r.ee)
     sys.stdout.flush()
+
+
+def test_near_tie_reporting(ctx):
+    """alloc_params.tie_rel: the GPU counts its own near-tie decisions.  Two
+    identical users competing for one subcarrier (l = 1) tie exactly, and
+    gains 1e-12 apart are within 1e-9: both are flagged, by the plain and the
+    batched solver, as the oracle flags them; gains 1e-3 apart are not.  With
+    tie_rel = 0 nothing is counted.  On ordinary drops counting changes no
+    result bit, and every drop the GPU flags, the oracle flags too (the GPU
+    watches a subset of the oracle's decisions: decoding order and where a
+    candidate would enter it, the selection order around the l-th
+    candidate, the best two RRHs)."""
+    import paper_1803_07772_amd as pa
+    from tests.test_oracle_pins import _tie_drop
+    p = pa.Params(fixed_count=0, sweeps_per_dinkelbach=200)
+    pt = pa.Params(fixed_count=0, sweeps_per_dinkelbach=200, tie_rel=1e-9)
+    for delta, flagged in ((0.0, True), (1e-12, True), (1e-3, False)):
+        print(f"[gpu case] near-tie drop delta={delta}", flush=True)
+        d = _tie_drop(delta)
+        o = oracle.solve(d, oracle.Params(fixed_count=0, sweeps_per_dinkelbach=200), gain=d.gain)
+        assert (o.near_ties > 0) == flagged
+        for r in (ctx.solve(d, pt), ctx.solve_batch([d], pt)[0]):
+            assert (r.near_ties > 0) == flagged, (delta, r.near_ties)
+            assert bool(r.status_flags & pa.NEAR_TIE) == flagged
+        r0 = ctx.solve(d, p)
+        assert r0.near_ties == 0 and not r0.status_flags & pa.NEAR_TIE
+    op = oracle.Params(fixed_count=0)
+    drops = [synth.make_drop(synth.CFG2, s, 0) for s in range(8)]
+    print("[gpu case] near-tie counts on cfg2 seeds 0-7", flush=True)
+    a = ctx.solve_batch(drops, gpu_params(op))
+    b = ctx.solve_batch(drops, gpu_params(op, tie_rel=1e-9))
+    counts = []
+    for d, x, y in zip(drops, a, b):
+        assert x.ee == y.ee and np.array_equal(x.slot_power, y.slot_power) and x.sweeps == y.sweeps
+        assert x.near_ties == 0
+        o = oracle.solve(d, op)
+        if y.near_ties > 0:
+            assert o.near_ties > 0
+        counts.append((y.near_ties, o.near_ties))
+    print("near ties (gpu, oracle):", counts, flush=True)
