@@ -894,6 +894,20 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
   }
   tm.sync();
 
+  // near-ties of where each user would enter its RRH's decoding order (a
+  // separate loop, so that the sweep without counting carries none of it)
+  if (sc.tie_rel > 0.0) {
+    for (int i = tid; i < ns * M * K; i += nth) {
+      const int t = dv.MK.div(i), r = i - mul24(t, M * K), m = dv.K.div(r), k = r - mul24(m, K);
+      const double u = s.u[IX_MK(t, m, k)];
+      const int cnt = s.vcnt[IX_SM(t, m)];
+      for (int a = 0; a < cnt; ++a) {
+        const double ua = s.vu[IX_ML(t, m, a)];
+        if (s.vuser[IX_ML(t, m, a)] != k && fabs(ua - u) <= sc.tie_rel * fmax(ua, u)) note_tie(d);
+      }
+    }
+  }
+
   // 6. per-triple Lagrangian maximum H (the candidates' order starts empty:
   //    its storage held the price terms read after step 5)
   for (int i = tid; i < ns * K; i += nth) s.ord[i] = -1;
@@ -906,8 +920,6 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
       const double ua = s.vu[IX_ML(t, m, a)];
       if (ka == k) q = a;
       if (ua < u || (ua == u && ka < k)) ++pos;
-      // where a candidate would enter the decoding order
-      if (sc.tie_rel > 0.0 && ka != k && fabs(ua - u) <= sc.tie_rel * fmax(ua, u)) note_tie(d);
     }
     const double Sb = s.vpre[IX_ML1(t, m, q >= 0 ? q : pos)];
     const double pin = s.vT[IX_ML1(t, m, q >= 0 ? q + 1 : pos)];
