@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--eval-drops", type=int, default=64,
                     help="fresh drops of that generator the warm start is evaluated on")
     ap.add_argument("--train-steps", type=int, default=300)
+    ap.add_argument("--warm-cap", type=int, default=6,
+                    help="Dinkelbach steps of the warm-started attempt before it falls back to the cold solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-large", action="store_true")
@@ -424,13 +426,14 @@ def nn_warm(a, ctx, params, dev):
     print(f"[bench] trained: {info}", flush=True)
     edrops = [synth.make_drop(synth.CFG3, 1_000_000 + s, 0) for s in range(a.eval_drops)]
     eg = [torch.from_numpy(d.gain).to(dev) for d in edrops]
-    net.solve_batch(edrops[:2], params, gains=eg[:2])
+    wparams = dataclasses.replace(params, warm_max_dinkelbach=a.warm_cap)
+    net.solve_batch(edrops[:2], wparams, gains=eg[:2])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     cold = ctx.solve_batch(edrops, params, gains=eg)
     dtc = time.perf_counter() - t0
     t0 = time.perf_counter()
-    wr = net.solve_batch(edrops, params, gains=eg)
+    wr = net.solve_batch(edrops, wparams, gains=eg)
     dtw = time.perf_counter() - t0
     mlp_ms = net.last_ms()
     rows = sum(d.M * d.N * d.K for d in edrops)
@@ -442,7 +445,8 @@ def nn_warm(a, ctx, params, dev):
                     f"evaluated on {a.eval_drops} fresh drops (seeds 1000000..); a fraction of the "
                     "200k-drop training set and 4096 evaluation drops",
         "allocations_per_s": a.eval_drops / dtw, "cold_allocations_per_s": a.eval_drops / dtc,
-        "includes": "network inference + warm-started batched solve (one alloc_solve_batch_mlp call)",
+        "includes": "network inference + warm-started batched solve (one alloc_solve_batch_mlp call), "
+                    f"at most {a.warm_cap} Dinkelbach steps for the warm attempt, then the cold fallbacks",
         "train": info, "sweeps_mean_warm": float(np.mean([r.sweeps for r in wr])),
         "sweeps_mean_cold": float(np.mean([r.sweeps for r in cold])),
         "dinkelbach_mean_warm": float(np.mean([r.dinkelbach_iters for r in wr])),

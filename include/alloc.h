@@ -161,6 +161,13 @@ typedef struct {
                                     second-best RRH (relative difference of the sums of H);
                                     the count is alloc_result.near_ties and a positive count
                                     sets ALLOC_NEAR_TIE.  0: not counted (no cost) */
+  int32_t warm_max_dinkelbach;   /* 0: the network's solves (alloc_solve_mlp,
+                                    alloc_solve_batch_mlp) only: when positive and below
+                                    max_dinkelbach, the warm-started attempt runs at most
+                                    this many Dinkelbach steps, and one that has not met
+                                    the stopping test within them falls back to the cold
+                                    solve too (which runs max_dinkelbach); 0: the warm
+                                    attempt runs max_dinkelbach steps */
 } alloc_params;
 
 ALLOC_API void alloc_params_default(alloc_params* p);

@@ -130,9 +130,10 @@ ALLOC_API int alloc_mlp_warm(alloc_mlp* net, const alloc_problem* prob, uint32_t
 /* Network inference, then alloc_solve from that warm start.  Falls back to
  * the cold start (and sets ALLOC_WARM_FALLBACK) when the warm-started solve
  * ends non-finite, with EE <= 0 (nothing allocated) or infeasible for C12 or
- * C13 (the constraints the method meets when it converges; C14 is reported
- * on both paths): the cold-started solve is then returned, whatever its own
- * flags. */
+ * C13 (the constraints the method meets when it converges; every returned
+ * allocation meets C14), or, with alloc_params.warm_max_dinkelbach set, has
+ * not converged within that many Dinkelbach steps: the cold-started solve is
+ * then returned, whatever its own flags. */
 ALLOC_API int alloc_solve_mlp(alloc_mlp* net, const alloc_problem* prob, const alloc_params* prm,
                               alloc_result* res);
 

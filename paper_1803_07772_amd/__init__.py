@@ -54,7 +54,8 @@ class _Params(ctypes.Structure):
                 ("tol_dual", ctypes.c_double), ("step0", ctypes.c_double),
                 ("qos_down", ctypes.c_double), ("flags", ctypes.c_uint32), ("max_groups", ctypes.c_int32),
                 ("tile", ctypes.c_int32), ("lds_kb", ctypes.c_int32), ("block", ctypes.c_int32),
-                ("wave", ctypes.c_int32), ("group_triples", ctypes.c_int32), ("tie_rel", ctypes.c_double)]
+                ("wave", ctypes.c_int32), ("group_triples", ctypes.c_int32), ("tie_rel", ctypes.c_double),
+                ("warm_max_dinkelbach", ctypes.c_int32)]
 
 
 class _Warm(ctypes.Structure):
@@ -165,12 +166,14 @@ class Params:
     wave: int = 0
     group_triples: int = 0
     tie_rel: float = 0.0
+    warm_max_dinkelbach: int = 0
 
     def _c(self, flags: int) -> _Params:
         return _Params(self.max_dinkelbach, self.sweeps_per_dinkelbach, self.refit_period,
                        self.fixed_count, self.stall_sweeps, self.tol_dinkelbach, self.tol_dual,
                        self.step0, self.qos_down, flags, self.max_groups, self.tile, self.lds_kb,
-                       self.block, self.wave, self.group_triples, self.tie_rel)
+                       self.block, self.wave, self.group_triples, self.tie_rel,
+                       self.warm_max_dinkelbach)
 
 
 def default_params() -> Params:
@@ -178,7 +181,8 @@ def default_params() -> Params:
     load().alloc_params_default(ctypes.byref(p))
     return Params(p.max_dinkelbach, p.sweeps_per_dinkelbach, p.refit_period, p.fixed_count,
                   p.stall_sweeps, p.tol_dinkelbach, p.tol_dual, p.step0, p.qos_down, p.max_groups,
-                  p.tile, p.lds_kb, p.block, p.wave, p.group_triples, p.tie_rel)
+                  p.tile, p.lds_kb, p.block, p.wave, p.group_triples, p.tie_rel,
+                  p.warm_max_dinkelbach)
 
 
 @dataclasses.dataclass

@@ -2128,6 +2128,7 @@ int validate(const alloc_problem* pb, const alloc_params* prm) {
   if (pb->M > kMaxM || pb->l > kMaxL || pb->K > kMaxK || pb->M * pb->K > kMaxMK) return ALLOC_ETOOBIG;
   if (prm->sweeps_per_dinkelbach < 1 || prm->max_dinkelbach < 1 || prm->max_groups < 0 || prm->tile < 0 ||
       prm->group_triples < 0 || !(prm->tie_rel >= 0.0) || !std::isfinite(prm->tie_rel) ||
+      prm->warm_max_dinkelbach < 0 ||
       prm->lds_kb < 0 || !(prm->block == 0 || prm->block == 256 || prm->block == 512 || prm->block == 1024) || prm->wave < 0 ||
       prm->wave > 16)
     return ALLOC_EINVAL;
@@ -2197,6 +2198,7 @@ void alloc_params_default(alloc_params* p) {
   p->wave = 0;
   p->group_triples = 0;
   p->tie_rel = 0.0;
+  p->warm_max_dinkelbach = 0;
 }
 
 int alloc_ctx_set_timing(alloc_ctx* ctx, int enable) {

@@ -1129,8 +1129,19 @@ WarmArrays warm_arrays(int64_t n3, int M, int K) {
 // the constraints the method meets when it converges: a streaming user below
 // its minimum rate (C13) or an RRH over its budget (C12).  C14 is enforced
 // through its multiplier and reported, as on the cold path.
-bool needs_fallback(const alloc_result& r) {
-  return (r.status_flags & (ALLOC_NONFINITE | ALLOC_QOS_INFEASIBLE | ALLOC_BUDGET_INFEASIBLE)) || !(r.ee > 0.0);
+bool needs_fallback(const alloc_result& r, bool capped) {
+  const uint32_t bad = ALLOC_NONFINITE | ALLOC_QOS_INFEASIBLE | ALLOC_BUDGET_INFEASIBLE |
+                       (capped ? ALLOC_NOT_CONVERGED : 0u);
+  return (r.status_flags & bad) || !(r.ee > 0.0);
+}
+
+// The warm attempt's schedule: max_dinkelbach cut to warm_max_dinkelbach
+// when that is set and smaller (then *capped).
+alloc_params warm_params(const alloc_params& p, bool* capped) {
+  alloc_params w = p;
+  *capped = p.warm_max_dinkelbach > 0 && p.warm_max_dinkelbach < p.max_dinkelbach;
+  if (*capped) w.max_dinkelbach = p.warm_max_dinkelbach;
+  return w;
 }
 
 }  // namespace
@@ -1446,9 +1457,11 @@ int alloc_solve_mlp(alloc_mlp* net, const alloc_problem* pb, const alloc_params*
   net->last_ms = mlp_ms;
   const alloc_internal::DevWarm dw{(const double*)(net->ws + wa.p0), (const double*)(net->ws + wa.xi0),
                                    (const double*)(net->ws + wa.zeta0)};
-  rc = alloc_internal::solve_one(c, pb, prm, nullptr, &dw, res);
+  bool capped;
+  const alloc_params wp = warm_params(*prm, &capped);
+  rc = alloc_internal::solve_one(c, pb, &wp, nullptr, &dw, res);
   if (rc) return rc;
-  if (needs_fallback(*res)) {
+  if (needs_fallback(*res, capped)) {
     rc = alloc_internal::solve_one(c, pb, prm, nullptr, nullptr, res);
     if (rc) return rc;
     res->status_flags |= ALLOC_WARM_FALLBACK;
@@ -1484,11 +1497,13 @@ int alloc_solve_batch_mlp(alloc_mlp* net, int32_t B, const alloc_problem* probs,
     dw->zeta0 = (const double*)(w + wb.zeta) + wb.koff[b];
     return ALLOC_OK;
   };
-  rc = alloc_internal::solve_batch(c, B, probs, prm, nullptr, &fn, results);
+  bool capped;
+  const alloc_params wp = warm_params(*prm, &capped);
+  rc = alloc_internal::solve_batch(c, B, probs, &wp, nullptr, &fn, results);
   if (rc) return rc;
   std::vector<int> redo;
   for (int b = 0; b < B; ++b)
-    if (needs_fallback(results[b])) redo.push_back(b);
+    if (needs_fallback(results[b], capped)) redo.push_back(b);
   if (redo.empty()) return ALLOC_OK;
   std::vector<alloc_problem> rp;
   std::vector<alloc_result> rr;

@@ -342,3 +342,30 @@ def test_qos_infeasible_is_a_fallback(ctx):
     assert cold.status_flags & pa.QOS_INFEASIBLE
     assert r.status_flags == cold.status_flags | pa.WARM_FALLBACK
     assert r.ee == cold.ee and np.array_equal(r.sel, cold.sel)
+
+
+def test_warm_attempt_capped(ctx):
+    """alloc_params.warm_max_dinkelbach: a warm attempt that meets the
+    stopping test within the cap is the uncapped warm result, bit for bit; one
+    that needs more Dinkelbach steps than the cap is replaced by the cold
+    solve (which keeps the full max_dinkelbach), flagged."""
+    import paper_1803_07772_amd as pa
+    d = synth.make_drop(synth.CFG1, 2, 0)
+    print("[gpu case] capped warm attempt", flush=True)
+    flat, _ = _weights(8, gain=1.0)
+    net = _net(ctx, flat)
+    p = pa.Params(fixed_count=0, sweeps_per_dinkelbach=200, max_dinkelbach=20)
+    free = net.solve(d, p)
+    assert not free.status_flags & pa.WARM_FALLBACK
+    D = free.dinkelbach_iters
+    assert 2 <= D < 20
+    same = net.solve(d, dataclasses.replace(p, warm_max_dinkelbach=D))
+    assert same.ee == free.ee and np.array_equal(same.sel, free.sel) and same.status_flags == free.status_flags
+    cut = net.solve(d, dataclasses.replace(p, warm_max_dinkelbach=D - 1))
+    cold = ctx.solve(d, p)
+    assert cut.status_flags == cold.status_flags | pa.WARM_FALLBACK
+    assert cut.ee == cold.ee and np.array_equal(cut.sel, cold.sel)
+    rb = net.solve_batch([d], dataclasses.replace(p, warm_max_dinkelbach=D - 1))[0]
+    assert rb.status_flags & pa.WARM_FALLBACK or (rb.dinkelbach_iters <= D - 1 and
+                                                  not rb.status_flags & pa.NOT_CONVERGED)
+    net.close()
