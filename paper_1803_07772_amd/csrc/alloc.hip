@@ -1217,6 +1217,26 @@ __device__ inline bool assoc_near_tie(int M, double tie_rel, F&& S) {
 // Reductions across workgroups: users k = b, b+G, ... per workgroup (rates,
 // association into buffer wr, zeta' steps, partial C13 violation);
 // workgroup 0 also does the per-RRH and scalar sums.
+// Sum over the workgroup of one value per thread, by a fixed tree (wave
+// shuffles, then the waves in order); the total is returned to thread 0.
+__device__ double block_sum(double v, Lds& s) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  __syncthreads();  // s.red may still be read by the caller's previous use
+  if (lane == 0) s.red[wave] = v;
+  __syncthreads();
+  double t = 0.0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < nw; ++w) t += s.red[w];
+  return t;
+}
+
+// Groups of at most this many workgroups reduce a user's partials with one
+// thread per (user, quantity), in workgroup order; larger grids with a tree
+// over the workgroup's threads per user.
+constexpr int kSerialGroups = 32;
+
 __device__ void reduce_pass(const Drop& d, const Sched& sc, const Ctrl& c, Lds& s, int b, int G,
                             bool update, double delta_v) {
   const int M = d.M, K = d.K, tid = threadIdx.x;
@@ -1224,29 +1244,83 @@ __device__ void reduce_pass(const Drop& d, const Sched& sc, const Ctrl& c, Lds& 
   int changes = 0;
   double vq = 0.0, zr = 0.0;
   if (b == 0 && tid == 0) store_shared(&d.chg_count[par ^ 1], 0);  // next pass's counter
-  for (int k = b; k < K; k += G) {
-    reduce_groups<false>(s, d.r_part + k, G, 1, K, 0, s.tmp);
-    reduce_groups<false>(s, d.rh_part + k, G, 1, K, 0, s.tmp + 1);
-    if (update) reduce_groups<false>(s, d.S_part + k, G, M, (size_t)M * K, K, s.tmp + 2);
+  if (G <= kSerialGroups) {
+    // this workgroup's users k = b, b + G, ...: each sum of G partials in
+    // workgroup order, one item per (user, quantity), into the accumulators
+    // (the workgroup's own partials are in device memory already)
+    const int nth = blockDim.x;
+    const int nk = b < K ? (K - b + G - 1) / G : 0;
+    const int nq = update ? M + 2 : 2;
+    for (int i = tid; i < nk * nq; i += nth) {
+      const int j = i / nq, f = i - j * nq, k = b + j * G;
+      const int m = f - 2;
+      GLB const double* src = f == 0 ? gl(d.r_part) + k : f == 1 ? gl(d.rh_part) + k : gl(d.S_part) + (size_t)m * K + k;
+      const size_t gs = f < 2 ? (size_t)K : (size_t)M * K;
+      double acc = 0.0;
+      for (int g = 0; g < G; ++g) acc += src[(size_t)g * gs];
+      if (f == 0) s.racc[k] = acc;
+      else if (f == 1) s.rhacc[k] = acc;
+      else s.Sacc[(size_t)m * K + k] = acc;
+    }
     if (tid == 0) {
-      const double r = s.tmp[0], rh = s.tmp[1];
+      s.tmp[0] = 0.0;                // largest zeta' step (an integer maximum)
+      *(LDS int*)(s.tmp + 1) = 0;    // association changes
+    }
+    __syncthreads();
+    for (int j = tid; j < nk; j += nth) {
+      const int k = b + j * G;
+      const double r = s.racc[k], rh = s.rhacc[k];
       gl(d.user_rate)[k] = r;
       const bool el = gl(d.elastic)[k];
       if (!el) vq += qos_viol(r, gl(d.psi)[k]);
       if (update) {
         const int before = gl(d.A)[(size_t)c.rd * K + k];
-        const int after = assoc_of(M, before, el, [&](int m) { return s.tmp[2 + m]; });
-        if (sc.tie_rel > 0.0 && assoc_near_tie(M, sc.tie_rel, [&](int m) { return s.tmp[2 + m]; })) note_tie(d);
+        const int after = assoc_of(M, before, el, [&](int m) { return s.Sacc[(size_t)m * K + k]; });
+        if (sc.tie_rel > 0.0 && assoc_near_tie(M, sc.tie_rel, [&](int m) { return s.Sacc[(size_t)m * K + k]; }))
+          note_tie(d);
         gl(d.A)[(size_t)c.wr * K + k] = after;
-        if (after != before) ++changes;
+        if (after != before)
+          __hip_atomic_fetch_add((LDS int*)(s.tmp + 1), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (!el) {
           double res;
           gl(d.zeta)[k] = zeta_step(gl(d.zeta)[k], gl(d.psi)[k], rh, delta_v, sc.qos_down, &res);
-          zr = fmax(zr, res);
+          if (res == res)
+            __hip_atomic_fetch_max((LDS unsigned long long*)s.tmp, (unsigned long long)__double_as_longlong(res),
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         }
       }
     }
+    vq = block_sum(vq, s);  // in a fixed order; thread 0 holds the total
+    if (tid == 0) {
+      zr = s.tmp[0];
+      changes = *(LDS int*)(s.tmp + 1);
+    }
     __syncthreads();
+  } else {
+    for (int k = b; k < K; k += G) {
+      reduce_groups<false>(s, d.r_part + k, G, 1, K, 0, s.tmp);
+      reduce_groups<false>(s, d.rh_part + k, G, 1, K, 0, s.tmp + 1);
+      if (update) reduce_groups<false>(s, d.S_part + k, G, M, (size_t)M * K, K, s.tmp + 2);
+      if (tid == 0) {
+        const double r = s.tmp[0], rh = s.tmp[1];
+        gl(d.user_rate)[k] = r;
+        const bool el = gl(d.elastic)[k];
+        if (!el) vq += qos_viol(r, gl(d.psi)[k]);
+        if (update) {
+          const int before = gl(d.A)[(size_t)c.rd * K + k];
+          const int after = assoc_of(M, before, el, [&](int m) { return s.tmp[2 + m]; });
+          if (sc.tie_rel > 0.0 && assoc_near_tie(M, sc.tie_rel, [&](int m) { return s.tmp[2 + m]; })) note_tie(d);
+          gl(d.A)[(size_t)c.wr * K + k] = after;
+          if (after != before) ++changes;
+          if (!el) {
+            double res;
+            gl(d.zeta)[k] = zeta_step(gl(d.zeta)[k], gl(d.psi)[k], rh, delta_v, sc.qos_down, &res);
+            zr = fmax(zr, res);
+          }
+        }
+      }
+      __syncthreads();
+    }
   }
   if (tid == 0) {
     if (changes > 0) __hip_atomic_fetch_add(&d.chg_count[par], changes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -1255,12 +1329,36 @@ __device__ void reduce_pass(const Drop& d, const Sched& sc, const Ctrl& c, Lds& 
   }
   if (b == 0) {
     // per-RRH sums, xi' step, R, P, max delta, C12 and C14 violations
-    // (fixed-order trees)
-    reduce_groups<false>(s, d.psum_part, G, M, M, 1, s.psacc);
-    reduce_groups<false>(s, d.pel_part, G, M, M, 1, s.peacc);
-    reduce_groups<false>(s, d.R_part, G, 1, 1, 0, s.tmp);
-    reduce_groups<true>(s, d.d_part, G, 1, 1, 0, s.tmp + 1);
-    reduce_groups<false>(s, d.sv_part, G, 1, 1, 0, s.tmp + 2);
+    // (in workgroup order, or fixed-order trees for large grids)
+    if (G <= kSerialGroups) {
+      for (int i = tid; i < 2 * M + 3; i += (int)blockDim.x) {
+        GLB const double* src;
+        int stride;
+        LDS double* dst;
+        if (i < M) {
+          src = gl(d.psum_part) + i, stride = M, dst = s.psacc + i;
+        } else if (i < 2 * M) {
+          src = gl(d.pel_part) + (i - M), stride = M, dst = s.peacc + (i - M);
+        } else {
+          const int q = i - 2 * M;
+          src = q == 0 ? gl(d.R_part) : q == 1 ? gl(d.d_part) : gl(d.sv_part), stride = 1, dst = s.tmp + q;
+        }
+        const bool mx = i == 2 * M + 1;  // the largest power change
+        double acc = 0.0;
+        for (int g = 0; g < G; ++g) {
+          const double v = src[(size_t)g * stride];
+          acc = mx ? fmax(acc, v) : acc + v;
+        }
+        *dst = acc;
+      }
+      __syncthreads();
+    } else {
+      reduce_groups<false>(s, d.psum_part, G, M, M, 1, s.psacc);
+      reduce_groups<false>(s, d.pel_part, G, M, M, 1, s.peacc);
+      reduce_groups<false>(s, d.R_part, G, 1, 1, 0, s.tmp);
+      reduce_groups<true>(s, d.d_part, G, 1, 1, 0, s.tmp + 1);
+      reduce_groups<false>(s, d.sv_part, G, 1, 1, 0, s.tmp + 2);
+    }
     if (tid == 0) {
       double P = d.pstatic, Vp = 0.0, xr = 0.0;
       for (int m = 0; m < M; ++m) {
@@ -1516,8 +1614,21 @@ __device__ void advance(const Sched& sc, Ctrl& c, const Eval& e) {
 // per-workgroup C13 violations and zeta' steps by fixed-order trees.  The
 // workgroup's copy c sits in LDS; thread 0 advances it.
 __device__ void control(const Drop& d, const Sched& sc, Ctrl& c, Lds& s, int G) {
-  reduce_groups<false>(s, d.vq_part, G, 1, 1, 0, s.tmp);
-  reduce_groups<true>(s, d.zr_part, G, 1, 1, 0, s.tmp + 1);
+  if (G <= kSerialGroups) {  // the workgroups' values in workgroup order
+    if (threadIdx.x == 0) {
+      double vq = 0.0, zr = 0.0;
+      for (int g = 0; g < G; ++g) {
+        vq += load_shared(&d.vq_part[g]);
+        zr = fmax(zr, load_shared(&d.zr_part[g]));
+      }
+      s.tmp[0] = vq;
+      s.tmp[1] = zr;
+    }
+    __syncthreads();
+  } else {
+    reduce_groups<false>(s, d.vq_part, G, 1, 1, 0, s.tmp);
+    reduce_groups<true>(s, d.zr_part, G, 1, 1, 0, s.tmp + 1);
+  }
   Eval e;
   e.R = load_shared(&d.red[0]);
   e.P = load_shared(&d.red[1]);
@@ -1669,20 +1780,6 @@ __device__ void block_start(const Drop& d, Lds& s) {
   __syncthreads();
 }
 
-// Sum over the workgroup of one value per thread, by a fixed tree (wave
-// shuffles, then the waves in order); the total is returned to thread 0.
-__device__ double block_sum(double v, Lds& s) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  __syncthreads();  // s.red may still be read by the caller's previous use
-  if (lane == 0) s.red[wave] = v;
-  __syncthreads();
-  double t = 0.0;
-  if (threadIdx.x == 0)
-    for (int w = 0; w < nw; ++w) t += s.red[w];
-  return t;
-}
 
 // Reductions and multiplier steps of one pass from the workgroup's own
 // accumulators (it holds every subcarrier of the drop); the pass's reduced
