@@ -835,17 +835,19 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
       const int cj = s.vcnt[IX_SM(t, j)];
       for (int a = 0; a < cj; ++a)
         inter += s.vc[IX_ML(t, j, a)] * (double)s.g[IX_MK(t, m, s.vuser[IX_ML(t, j, a)])];
-      // pairs of RRH m: their margins move with the power of RRH j
+      // pairs of RRH m: their margins move with the power of RRH j (a pair
+      // whose multiplier is zero adds nothing: skipped)
       const int cnt = s.vcnt[IX_SM(t, m)];
       for (int a = 0; a < cnt; ++a)
         for (int b = a + 1; b < cnt; ++b) {
+          const double z = s.szs[IX_MLL(t, m, s.vslot[IX_ML(t, m, a)], s.vslot[IX_ML(t, m, b)])];
+          if (z == 0.0) continue;
           const int ka = s.vuser[IX_ML(t, m, a)], kb = s.vuser[IX_ML(t, m, b)];
           const double ga = s.g[IX_MK(t, m, ka)], gb = s.g[IX_MK(t, m, kb)];
           const bool swap = gb > ga || (gb == ga && kb < ka);  // strong = larger raw gain
           const int ks = swap ? kb : ka, kw = swap ? ka : kb;
           const double us = swap ? s.vu[IX_ML(t, m, b)] : s.vu[IX_ML(t, m, a)];
           const double uw = swap ? s.vu[IX_ML(t, m, a)] : s.vu[IX_ML(t, m, b)];
-          const double z = s.szs[IX_MLL(t, m, s.vslot[IX_ML(t, m, a)], s.vslot[IX_ML(t, m, b)])];
           const double gs = swap ? gb : ga, gw = swap ? ga : gb;
           const double dj = ((double)s.g[IX_MK(t, j, ks)] / gs - (double)s.g[IX_MK(t, j, kw)] / gw) / (us + uw);
           sic += z * dj;
