@@ -1026,7 +1026,9 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
           if (b < np) {
             const bool kstrong = gk > cgn[b] || (gk == cgn[b] && k < ch[b]);
             const double us = kstrong ? uk : cu[b], uw = kstrong ? cu[b] : uk;
-            if ((us - uw) / (us + uw) > 0.0) ok = false;
+            // the margin (us - uw)/(us + uw) is positive exactly when
+            // us > uw (both positive)
+            if (us > uw) ok = false;
           }
         if (ok) {
 #pragma unroll
