@@ -785,8 +785,10 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
         const bool swap = gb > ga || (gb == ga && kb < ka);
         const double us = swap ? s.vu[IX_ML(t, m, b)] : s.vu[IX_ML(t, m, a)];
         const double uw = swap ? s.vu[IX_ML(t, m, a)] : s.vu[IX_ML(t, m, b)];
-        const double om = (us - uw) / (us + uw);
-        if (om > kSicTol) sv += om - kSicTol;
+        if (us > uw) {  // a positive margin (the only kind counted)
+          const double om = (us - uw) / (us + uw);
+          if (om > kSicTol) sv += om - kSicTol;
+        }
       }
     s.tsv[i] = sv;
     if (pc.write_out) {
@@ -866,9 +868,14 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
     const bool swap = gb > ga || (gb == ga && kb < ka);
     const double us = swap ? s.vu[IX_ML(t, m, b)] : s.vu[IX_ML(t, m, a)];
     const double uw = swap ? s.vu[IX_ML(t, m, a)] : s.vu[IX_ML(t, m, b)];
-    const double om = (us - uw) / (us + uw);
     const int sa = s.vslot[IX_ML(t, m, a)], sb = s.vslot[IX_ML(t, m, b)];
     const double z = s.szs[IX_MLL(t, m, sa, sb)];
+    if (z == 0.0 && !(us > uw)) {  // a zero multiplier and a margin <= 0: it stays 0
+      s.szn[IX_MLL(t, m, sa, sb)] = 0.0;
+      s.szn[IX_MLL(t, m, sb, sa)] = 0.0;
+      continue;
+    }
+    const double om = (us - uw) / (us + uw);
     const double zn = fmax(z + pc.delta_v * om, 0.0);
     s.szn[IX_MLL(t, m, sa, sb)] = zn;
     s.szn[IX_MLL(t, m, sb, sa)] = zn;
@@ -939,8 +946,8 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
       }
       if (pt > 0.0) H = wmu * log2_1p(pt / ainv) - c * pt;
     }
-    if (s.Al[k] == m) {
-      s.Hc[IX_SK(t, k)] = H;
+    if (s.Al[k] == m) {  // H in the user's place within its RRH group
+      s.Hc[IX_SK(t, s.grp_off[m] + s.grpk[k])] = H;
       s.pic[IX_SK(t, k)] = pin;
     }
     return H;
@@ -966,26 +973,26 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
   }
 
   // 7. selection.  Each candidate (H > 0 on its own RRH) takes the place of
-  //    its rank within its RRH group (H desc, user asc) ...
+  //    its rank within its RRH group (H desc, user asc: a group holds its
+  //    users in increasing order, so positions order them as indices do) ...
   for (int i = tid; i < ns * K; i += nth) {
     const int t = dv.K.div(i), k = i - mul24(t, K);
     const int m = s.Al[k];
     if (m < 0) continue;
-    const double h = s.Hc[i];
+    const int e0 = s.grp_off[m], e1 = s.grp_off[m + 1], ek = e0 + s.grpk[k];
+    const double h = s.Hc[IX_SK(t, ek)];
     if (!(h > 0.0)) continue;
     int rank = 0;
-    for (int e = s.grp_off[m]; e < s.grp_off[m + 1]; ++e) {
-      const int j = s.grp[e];
-      const double hj = s.Hc[IX_SK(t, j)];
-      rank += (hj > h) || (hj == h && j < k);
+    for (int e = e0; e < e1; ++e) {
+      const double hj = s.Hc[IX_SK(t, e)];
+      rank += (hj > h) || (hj == h && e < ek);
     }
-    s.ord[IX_SK(t, s.grp_off[m] + rank)] = k;
+    s.ord[IX_SK(t, e0 + rank)] = k;
     if (sc.tie_rel > 0.0 && rank < L) {  // k and the next candidate in H order
       double gap = INFINITY;
-      for (int e = s.grp_off[m]; e < s.grp_off[m + 1]; ++e) {
-        const int j = s.grp[e];
-        const double hj = s.Hc[IX_SK(t, j)];
-        if (j != k && hj > 0.0 && (hj < h || (hj == h && j > k))) gap = fmin(gap, h - hj);
+      for (int e = e0; e < e1; ++e) {
+        const double hj = s.Hc[IX_SK(t, e)];
+        if (e != ek && hj > 0.0 && (hj < h || (hj == h && e > ek))) gap = fmin(gap, h - hj);
       }
       if (gap <= sc.tie_rel * h) note_tie(d);
     }
