@@ -128,7 +128,7 @@ class _Pattern:
                     continue
                 s_, w_ = (k, k2) if (G[m, n, k] > G[m, n, k2] or (G[m, n, k] == G[m, n, k2] and k < k2)) else (k2, k)
                 a = np.zeros(nt)
-                for q, (m3, n3, k3) in enumerate(trip):
+                for q, (m3, n3, _) in enumerate(trip):
                     if n3 == n and m3 != m:
                         a[q] = G[m, n, w_] * G[m3, n, s_] - G[m, n, s_] * G[m3, n, w_]
                 c0 = sg * (G[m, n, w_] - G[m, n, s_])
@@ -295,7 +295,6 @@ def polyblock(pat: _Pattern, best: float, eps: float, max_iter: int = 200000, ro
         if len(new):
             # drop vertices dominated by another vertex
             allv = np.concatenate([V, new])
-            alf = np.concatenate([fV, fn])
             nn = len(new)
             dom_new = np.zeros(nn, bool)
             for a in range(nn):
@@ -310,7 +309,7 @@ def polyblock(pat: _Pattern, best: float, eps: float, max_iter: int = 200000, ro
                 V, fV = V[~dom_old], fV[~dom_old]
             V = np.concatenate([V, new])
             fV = np.concatenate([fV, fn])
-            del allv, alf
+            del allv
         # prune vertices that cannot beat the new best
         keepv = fV > best + eps
         V, fV = V[keepv], fV[keepv]

@@ -126,7 +126,7 @@ def solve_relaxed(d, rho1: float, rho2: float, max_dinkelbach: int = 30, sweeps:
         return R, P
 
     trace = []
-    for it in range(max_dinkelbach):
+    for _ in range(max_dinkelbach):
         al[:] = 1.0
         be[:] = 0.0
         for s in range(sweeps):
