@@ -1134,37 +1134,6 @@ __device__ void write_partials(const Drop& d, const Lds& s, int b) {
   }
 }
 
-// Sums (or maxima) over workgroups g of v(g, m) = base[g*gs + m*ms] for
-// m < M, in a fixed order: strided partial sums per (m, chunk), then a tree
-// over chunks.  Result in out[m] (LDS), visible to all threads on return.
-template <bool kMax>
-__device__ void reduce_groups(Lds& s, const double* base, int G, int M, size_t gs, size_t ms,
-                              LDS double* out) {
-  const int tid = threadIdx.x, nth = blockDim.x;
-  const int chunks = nth / M;
-  if (tid < M * chunks) {
-    const int m = tid % M, c = tid / M;
-    double acc = 0.0;
-    for (int g = c; g < G; g += chunks) {
-      const double v = base[(size_t)g * gs + (size_t)m * ms];
-      acc = kMax ? fmax(acc, v) : acc + v;
-    }
-    s.red[tid] = acc;
-  }
-  __syncthreads();
-  for (int st = 1; st < chunks; st <<= 1) {
-    if (tid < M * chunks) {
-      const int c = tid / M;
-      if ((c % (2 * st)) == 0 && c + st < chunks) {
-        const double o = s.red[tid + st * M];
-        s.red[tid] = kMax ? fmax(s.red[tid], o) : s.red[tid] + o;
-      }
-    }
-    __syncthreads();
-  }
-  if (tid < M) out[tid] = s.red[tid];
-  __syncthreads();
-}
 
 // C13 violation of one user: (1 - kQosTol) - r/Psi where positive, for a
 // streaming user.
@@ -1243,96 +1212,107 @@ __device__ double block_sum(double v, Lds& s) {
   return t;
 }
 
-// Groups of at most this many workgroups reduce a user's partials with one
-// thread per (user, quantity), in workgroup order; larger grids with a tree
-// over the workgroup's threads per user.
+// Reductions over the G workgroups of a grid or group.  Up to this many
+// workgroups, one thread sums an item's G partials in workgroup order; above
+// it a wave does (lane l takes workgroups l, l + 64, ..., then a fixed
+// butterfly, which leaves the same bits in every lane).
 constexpr int kSerialGroups = 32;
+
+// Item i's sum (or maximum, mx) of src[g * stride] over the G workgroups, by
+// this thread (serial mode) or by this wave (every lane returns it).
+__device__ inline double group_item(GLB const double* src, size_t stride, int G, bool mx, bool wave_mode) {
+  double acc = 0.0;
+  if (!wave_mode) {
+    for (int g = 0; g < G; ++g) {
+      const double v = src[(size_t)g * stride];
+      acc = mx ? fmax(acc, v) : acc + v;
+    }
+    return acc;
+  }
+  for (int g = (int)(threadIdx.x & 63); g < G; g += 64) {
+    const double v = src[(size_t)g * stride];
+    acc = mx ? fmax(acc, v) : acc + v;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const double w = __shfl_xor(acc, o, 64);
+    acc = mx ? fmax(acc, w) : acc + w;
+  }
+  return acc;
+}
+
+// Runs f(item) for items 0..n-1: one thread per item, or one wave per item
+// (then only lane 0's call stores).
+template <class F>
+__device__ inline void for_group_items(int n, bool wave_mode, F&& f) {
+  if (!wave_mode) {
+    for (int i = threadIdx.x; i < n; i += blockDim.x) f(i);
+  } else {
+    const int nw = (int)(blockDim.x >> 6);
+    for (int i = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); i < n; i += nw) f(i);
+  }
+}
 
 __device__ void reduce_pass(const Drop& d, const Sched& sc, const Ctrl& c, Lds& s, int b, int G,
                             bool update, double delta_v) {
-  const int M = d.M, K = d.K, tid = threadIdx.x;
+  const int M = d.M, K = d.K, tid = threadIdx.x, nth = blockDim.x;
   const int par = c.pass & 1;
+  const bool wm = G > kSerialGroups;
+  const bool store = !wm || (tid & 63) == 0;
   int changes = 0;
   double vq = 0.0, zr = 0.0;
   if (b == 0 && tid == 0) store_shared(&d.chg_count[par ^ 1], 0);  // next pass's counter
-  if (G <= kSerialGroups) {
-    // this workgroup's users k = b, b + G, ...: each sum of G partials in
-    // workgroup order, one item per (user, quantity), into the accumulators
-    // (the workgroup's own partials are in device memory already)
-    const int nth = blockDim.x;
-    const int nk = b < K ? (K - b + G - 1) / G : 0;
-    const int nq = update ? M + 2 : 2;
-    for (int i = tid; i < nk * nq; i += nth) {
-      const int j = i / nq, f = i - j * nq, k = b + j * G;
-      const int m = f - 2;
-      GLB const double* src = f == 0 ? gl(d.r_part) + k : f == 1 ? gl(d.rh_part) + k : gl(d.S_part) + (size_t)m * K + k;
-      const size_t gs = f < 2 ? (size_t)K : (size_t)M * K;
-      double acc = 0.0;
-      for (int g = 0; g < G; ++g) acc += src[(size_t)g * gs];
+  // this workgroup's users k = b, b + G, ...: each sum of G partials, one
+  // item per (user, quantity), into the accumulators (the workgroup's own
+  // partials are in device memory already)
+  const int nk = b < K ? (K - b + G - 1) / G : 0;
+  const int nq = update ? M + 2 : 2;
+  for_group_items(nk * nq, wm, [&](int i) {
+    const int j = i / nq, f = i - j * nq, k = b + j * G;
+    const int m = f - 2;
+    GLB const double* src = f == 0 ? gl(d.r_part) + k : f == 1 ? gl(d.rh_part) + k : gl(d.S_part) + (size_t)m * K + k;
+    const size_t gs = f < 2 ? (size_t)K : (size_t)M * K;
+    const double acc = group_item(src, gs, G, false, wm);
+    if (store) {
       if (f == 0) s.racc[k] = acc;
       else if (f == 1) s.rhacc[k] = acc;
       else s.Sacc[(size_t)m * K + k] = acc;
     }
-    if (tid == 0) {
-      s.tmp[0] = 0.0;                // largest zeta' step (an integer maximum)
-      *(LDS int*)(s.tmp + 1) = 0;    // association changes
-    }
-    __syncthreads();
-    for (int j = tid; j < nk; j += nth) {
-      const int k = b + j * G;
-      const double r = s.racc[k], rh = s.rhacc[k];
-      gl(d.user_rate)[k] = r;
-      const bool el = gl(d.elastic)[k];
-      if (!el) vq += qos_viol(r, gl(d.psi)[k]);
-      if (update) {
-        const int before = gl(d.A)[(size_t)c.rd * K + k];
-        const int after = assoc_of(M, before, el, [&](int m) { return s.Sacc[(size_t)m * K + k]; });
-        if (sc.tie_rel > 0.0 && assoc_near_tie(M, sc.tie_rel, [&](int m) { return s.Sacc[(size_t)m * K + k]; }))
-          note_tie(d);
-        gl(d.A)[(size_t)c.wr * K + k] = after;
-        if (after != before)
-          __hip_atomic_fetch_add((LDS int*)(s.tmp + 1), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (!el) {
-          double res;
-          gl(d.zeta)[k] = zeta_step(gl(d.zeta)[k], gl(d.psi)[k], rh, delta_v, sc.qos_down, &res);
-          if (res == res)
-            __hip_atomic_fetch_max((LDS unsigned long long*)s.tmp, (unsigned long long)__double_as_longlong(res),
-                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        }
+  });
+  if (tid == 0) {
+    s.tmp[0] = 0.0;              // largest zeta' step (an integer maximum)
+    *(LDS int*)(s.tmp + 1) = 0;  // association changes
+  }
+  __syncthreads();
+  for (int j = tid; j < nk; j += nth) {
+    const int k = b + j * G;
+    const double r = s.racc[k], rh = s.rhacc[k];
+    gl(d.user_rate)[k] = r;
+    const bool el = gl(d.elastic)[k];
+    if (!el) vq += qos_viol(r, gl(d.psi)[k]);
+    if (update) {
+      const int before = gl(d.A)[(size_t)c.rd * K + k];
+      const int after = assoc_of(M, before, el, [&](int m) { return s.Sacc[(size_t)m * K + k]; });
+      if (sc.tie_rel > 0.0 && assoc_near_tie(M, sc.tie_rel, [&](int m) { return s.Sacc[(size_t)m * K + k]; }))
+        note_tie(d);
+      gl(d.A)[(size_t)c.wr * K + k] = after;
+      if (after != before)
+        __hip_atomic_fetch_add((LDS int*)(s.tmp + 1), 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (!el) {
+        double res;
+        gl(d.zeta)[k] = zeta_step(gl(d.zeta)[k], gl(d.psi)[k], rh, delta_v, sc.qos_down, &res);
+        if (res == res)
+          __hip_atomic_fetch_max((LDS unsigned long long*)s.tmp, (unsigned long long)__double_as_longlong(res),
+                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
-    }
-    vq = block_sum(vq, s);  // in a fixed order; thread 0 holds the total
-    if (tid == 0) {
-      zr = s.tmp[0];
-      changes = *(LDS int*)(s.tmp + 1);
-    }
-    __syncthreads();
-  } else {
-    for (int k = b; k < K; k += G) {
-      reduce_groups<false>(s, d.r_part + k, G, 1, K, 0, s.tmp);
-      reduce_groups<false>(s, d.rh_part + k, G, 1, K, 0, s.tmp + 1);
-      if (update) reduce_groups<false>(s, d.S_part + k, G, M, (size_t)M * K, K, s.tmp + 2);
-      if (tid == 0) {
-        const double r = s.tmp[0], rh = s.tmp[1];
-        gl(d.user_rate)[k] = r;
-        const bool el = gl(d.elastic)[k];
-        if (!el) vq += qos_viol(r, gl(d.psi)[k]);
-        if (update) {
-          const int before = gl(d.A)[(size_t)c.rd * K + k];
-          const int after = assoc_of(M, before, el, [&](int m) { return s.tmp[2 + m]; });
-          if (sc.tie_rel > 0.0 && assoc_near_tie(M, sc.tie_rel, [&](int m) { return s.tmp[2 + m]; })) note_tie(d);
-          gl(d.A)[(size_t)c.wr * K + k] = after;
-          if (after != before) ++changes;
-          if (!el) {
-            double res;
-            gl(d.zeta)[k] = zeta_step(gl(d.zeta)[k], gl(d.psi)[k], rh, delta_v, sc.qos_down, &res);
-            zr = fmax(zr, res);
-          }
-        }
-      }
-      __syncthreads();
     }
   }
+  vq = block_sum(vq, s);  // in a fixed order; thread 0 holds the total
+  if (tid == 0) {
+    zr = s.tmp[0];
+    changes = *(LDS int*)(s.tmp + 1);
+  }
+  __syncthreads();
   if (tid == 0) {
     if (changes > 0) __hip_atomic_fetch_add(&d.chg_count[par], changes, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     gl(d.vq_part)[b] = vq;
@@ -1340,36 +1320,22 @@ __device__ void reduce_pass(const Drop& d, const Sched& sc, const Ctrl& c, Lds& 
   }
   if (b == 0) {
     // per-RRH sums, xi' step, R, P, max delta, C12 and C14 violations
-    // (in workgroup order, or fixed-order trees for large grids)
-    if (G <= kSerialGroups) {
-      for (int i = tid; i < 2 * M + 3; i += (int)blockDim.x) {
-        GLB const double* src;
-        int stride;
-        LDS double* dst;
-        if (i < M) {
-          src = gl(d.psum_part) + i, stride = M, dst = s.psacc + i;
-        } else if (i < 2 * M) {
-          src = gl(d.pel_part) + (i - M), stride = M, dst = s.peacc + (i - M);
-        } else {
-          const int q = i - 2 * M;
-          src = q == 0 ? gl(d.R_part) : q == 1 ? gl(d.d_part) : gl(d.sv_part), stride = 1, dst = s.tmp + q;
-        }
-        const bool mx = i == 2 * M + 1;  // the largest power change
-        double acc = 0.0;
-        for (int g = 0; g < G; ++g) {
-          const double v = src[(size_t)g * stride];
-          acc = mx ? fmax(acc, v) : acc + v;
-        }
-        *dst = acc;
+    for_group_items(2 * M + 3, wm, [&](int i) {
+      GLB const double* src;
+      int stride;
+      LDS double* dst;
+      if (i < M) {
+        src = gl(d.psum_part) + i, stride = M, dst = s.psacc + i;
+      } else if (i < 2 * M) {
+        src = gl(d.pel_part) + (i - M), stride = M, dst = s.peacc + (i - M);
+      } else {
+        const int q = i - 2 * M;
+        src = q == 0 ? gl(d.R_part) : q == 1 ? gl(d.d_part) : gl(d.sv_part), stride = 1, dst = s.tmp + q;
       }
-      __syncthreads();
-    } else {
-      reduce_groups<false>(s, d.psum_part, G, M, M, 1, s.psacc);
-      reduce_groups<false>(s, d.pel_part, G, M, M, 1, s.peacc);
-      reduce_groups<false>(s, d.R_part, G, 1, 1, 0, s.tmp);
-      reduce_groups<true>(s, d.d_part, G, 1, 1, 0, s.tmp + 1);
-      reduce_groups<false>(s, d.sv_part, G, 1, 1, 0, s.tmp + 2);
-    }
+      const double acc = group_item(src, stride, G, i == 2 * M + 1, wm);  // the largest power change
+      if (store) *dst = acc;
+    });
+    __syncthreads();
     if (tid == 0) {
       double P = d.pstatic, Vp = 0.0, xr = 0.0;
       for (int m = 0; m < M; ++m) {
@@ -1625,20 +1591,13 @@ __device__ void advance(const Sched& sc, Ctrl& c, const Eval& e) {
 // per-workgroup C13 violations and zeta' steps by fixed-order trees.  The
 // workgroup's copy c sits in LDS; thread 0 advances it.
 __device__ void control(const Drop& d, const Sched& sc, Ctrl& c, Lds& s, int G) {
-  if (G <= kSerialGroups) {  // the workgroups' values in workgroup order
-    if (threadIdx.x == 0) {
-      double vq = 0.0, zr = 0.0;
-      for (int g = 0; g < G; ++g) {
-        vq += load_shared(&d.vq_part[g]);
-        zr = fmax(zr, load_shared(&d.zr_part[g]));
-      }
-      s.tmp[0] = vq;
-      s.tmp[1] = zr;
-    }
+  {  // the workgroups' C13 violations and largest zeta' steps
+    const bool wm = G > kSerialGroups;
+    for_group_items(2, wm, [&](int i) {
+      const double acc = group_item(i == 0 ? gl(d.vq_part) : gl(d.zr_part), 1, G, i == 1, wm);
+      if (!wm || (threadIdx.x & 63) == 0) s.tmp[i] = acc;
+    });
     __syncthreads();
-  } else {
-    reduce_groups<false>(s, d.vq_part, G, 1, 1, 0, s.tmp);
-    reduce_groups<true>(s, d.zr_part, G, 1, 1, 0, s.tmp + 1);
   }
   Eval e;
   e.R = load_shared(&d.red[0]);
