@@ -95,6 +95,7 @@ struct Ctrl {
 
 struct Sched {
   int max_d, sweeps, refit_period, fixed, stall, tile;
+  int sdev;  // grid solver: association sums in S_part's row of the workgroup
   double tol_d, tol_dual, step0, qos_down;
   double tie_rel;  // > 0: count near-tie decisions in Drop::ties
 };
@@ -198,6 +199,8 @@ struct Drop {
   const double* xi0;       //   initial powers [M][N][K], xi' [M], zeta' [K]
   const double* zeta0;
   int start_eval;          // the initial allocation is Dinkelbach's p^0 (warm start)
+  int sdev;                // batched solver: tiles sum the association metric into
+                           // S_part's row of the slot (device memory), not LDS
   int group;               // batched solver: workgroups that solve the drop together
   unsigned* bar;           // [3] their barrier: arrivals, generation, broken
   unsigned* ties;          // near-tie decisions (Sched::tie_rel > 0), zeroed before the solve
@@ -227,6 +230,10 @@ struct Lds {
   LDS float* g;       // [T][M][K] gains
   LDS double* u;      // [T][M][K] (sigma + ICI)/Gamma
   LDS double* Sacc;   // [M][K] association metric summed over my subcarriers
+                      // (with Sg: only the pass's reduced sums, in u's storage)
+  double* Sg;         // [M][K] in device memory, the slot's own row, or null:
+                      // where the tiles sum the association metric when the
+                      // LDS it would take is better spent on subcarriers
   LDS double* mu;     // [K] 1 (elastic) or zeta'
   LDS double* racc;   // [K]
   LDS double* rhacc;  // [K]
@@ -290,8 +297,9 @@ enum LdsPart : int { kShared = 1, kAccum = 2, kTile = 4, kAllParts = 7 };
 // other pointers are left null).  With base == nullptr it only measures
 // (host side).
 __host__ __device__ inline size_t carve_lds(LDS char* base, int M, int K, int L, int T, int nth, Lds* out,
-                                            int parts = kAllParts) {
+                                            int parts = kAllParts, bool sdev = false) {
   Lds s;
+  s.Sg = nullptr;
   size_t o = 0;
   int part = kAllParts;
   auto take = [&](size_t bytes) {
@@ -315,6 +323,9 @@ __host__ __device__ inline size_t carve_lds(LDS char* base, int M, int K, int L,
     s.pic = r ? s.Hc + TK : nullptr;
   }
   s.u = (LDS double*)take(sizeof(double) * TM * K);
+  // with the sums in device memory, the pass's reduced sums (after the
+  // tiles, when u is dead) take u's place: T*M*K >= M*K
+  if (sdev) s.Sacc = s.u;
   {
     LDS char* r = take(std::max(sizeof(double) * 2 * TK, sizeof(double) * 2 * TM * M));
     s.rk = (LDS double*)r;
@@ -331,7 +342,7 @@ __host__ __device__ inline size_t carve_lds(LDS char* base, int M, int K, int L,
   s.uc = (LDS double*)take(sizeof(double) * TK);
   s.gc = (LDS float*)take(sizeof(float) * TK);
   part = kAccum;
-  s.Sacc = (LDS double*)take(sizeof(double) * M * K);
+  if (!sdev) s.Sacc = (LDS double*)take(sizeof(double) * M * K);
   s.racc = (LDS double*)take(sizeof(double) * K);
   s.rhacc = (LDS double*)take(sizeof(double) * K);
   s.psacc = (LDS double*)take(sizeof(double) * M);
@@ -461,7 +472,12 @@ __device__ void begin_pass(const Drop& d, Lds& s, int rd) {
     s.racc[k] = 0.0;
     s.rhacc[k] = 0.0;
   }
-  for (int i = tid; i < M * K; i += nth) s.Sacc[i] = 0.0;
+  // the sums in device memory are cleared (and later summed) by the thread
+  // that owns each item in the tiles' step 6: i = tid, tid + nth, ...
+  if (GLB double* const Sg = gl(s.Sg))
+    for (int i = tid; i < M * K; i += nth) Sg[i] = 0.0;
+  else
+    for (int i = tid; i < M * K; i += nth) s.Sacc[i] = 0.0;
   for (int m = tid; m < M; m += nth) {
     s.xi[m] = gl(d.xi)[m];
     s.eta[m] = gl(d.eta)[m];
@@ -960,14 +976,20 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
     }
     tm.sync();
     // (the selection below runs in the same barrier interval)
-    for (int i = tid; i < M * K; i += nth)
-      s.Sacc[i] += seq_sum(ns, 0.0, [&](int t) { return s.u[t * M * K + i]; });
+    GLB double* const Sg = gl(s.Sg);
+    for (int i = tid; i < M * K; i += nth) {
+      const double Hsum = seq_sum(ns, 0.0, [&](int t) { return s.u[t * M * K + i]; });
+      if (Sg) Sg[i] += Hsum;
+      else s.Sacc[i] += Hsum;
+    }
   } else {
+    GLB double* const Sg = gl(s.Sg);
     for (int i = tid; i < M * K; i += nth) {
       const int m = dv.K.div(i), k = i - mul24(m, K);
       double Hsum = 0.0;
       for (int t = 0; t < ns; ++t) Hsum += h_item(t, m, k, s.u[IX_MK(t, m, k)]);
-      s.Sacc[i] += Hsum;
+      if (Sg) Sg[i] += Hsum;
+      else s.Sacc[i] += Hsum;
     }
     tm.sync();
   }
@@ -1112,7 +1134,8 @@ __device__ void tile(const Team& tm, const Drop& d, const Sched& sc, const PassC
 // Per-workgroup partials after its subcarriers.
 __device__ void write_partials(const Drop& d, const Lds& s, int b) {
   const int M = d.M, K = d.K, tid = threadIdx.x, nth = blockDim.x;
-  for (int i = tid; i < M * K; i += nth) gl(d.S_part)[(size_t)b * M * K + i] = s.Sacc[i];
+  if (!s.Sg)  // else the tiles summed into this row already
+    for (int i = tid; i < M * K; i += nth) gl(d.S_part)[(size_t)b * M * K + i] = s.Sacc[i];
   for (int k = tid; k < K; k += nth) {
     gl(d.r_part)[(size_t)b * K + k] = s.racc[k];
     gl(d.rh_part)[(size_t)b * K + k] = s.rhacc[k];
@@ -1633,7 +1656,8 @@ __global__ void __launch_bounds__(kGridBlock) solve_kernel(Drop d, Sched sc) {
   __shared__ Lds s_tab;
   __shared__ Ctrl c;
   if (threadIdx.x == 0) {
-    carve_lds((LDS char*)smem, d.M, d.K, d.L, sc.tile, blockDim.x, &s_tab);
+    carve_lds((LDS char*)smem, d.M, d.K, d.L, sc.tile, blockDim.x, &s_tab, kAllParts, sc.sdev);
+    if (sc.sdev) s_tab.Sg = d.S_part + (size_t)blockIdx.x * d.M * d.K;
     c = *d.ctrl;
   }
   __syncthreads();
@@ -1674,6 +1698,7 @@ __global__ void __launch_bounds__(kGridBlock) solve_kernel(Drop d, Sched sc) {
 __device__ void block_start(const Drop& d, Lds& s) {
   const int M = d.M, N = d.N, K = d.K, L = d.L, tid = threadIdx.x, nth = blockDim.x;
   GLB const double* p0 = gl(d.p0);
+  GLB double* const Sg = gl(s.Sg);  // (Sacc is u's storage when Sg is set)
   for (int i = tid; i < M * K; i += nth) {
     const int m = i / K, k = i - m * K;
     double acc = 0.0, pacc = 0.0;
@@ -1682,18 +1707,21 @@ __device__ void block_start(const Drop& d, Lds& s) {
       acc += log2_1p((double)gl(d.G)[gi] * gl(d.pmask)[m] / d.sigma);
       if (p0) pacc += p0[gi];
     }
-    s.Sacc[i] = acc;
+    if (Sg) Sg[i] = acc;
+    else s.Sacc[i] = acc;
     s.u[i] = pacc;  // the tile arrays are free before the first pass
   }
   __syncthreads();
   for (int k = tid; k < K; k += nth) {
     int best = 0;
     double bv = -1.0;
-    for (int m = 0; m < M; ++m)
-      if (s.Sacc[m * K + k] > bv) {
-        bv = s.Sacc[m * K + k];
+    for (int m = 0; m < M; ++m) {
+      const double v = Sg ? Sg[m * K + k] : s.Sacc[m * K + k];
+      if (v > bv) {
+        bv = v;
         best = m;
       }
+    }
     if (p0) {
       int wb = -1;
       double wv = 0.0;
@@ -1757,6 +1785,7 @@ __device__ void block_start(const Drop& d, Lds& s) {
 __device__ void block_reduce(const Drop& d, const Sched& sc, int wr, Lds& s, bool update,
                              double delta_v, int* changes, unsigned long long* zres, Eval* e) {
   const int M = d.M, K = d.K, tid = threadIdx.x, nth = blockDim.x;
+  GLB const double* const Sg = gl(s.Sg);  // the tiles' sums, visible after their last barrier
   double vq = 0.0;
   for (int k = tid; k < K; k += nth) {
     gl(d.user_rate)[k] = s.racc[k];
@@ -1764,8 +1793,9 @@ __device__ void block_reduce(const Drop& d, const Sched& sc, int wr, Lds& s, boo
     if (!el) vq += qos_viol(s.racc[k], gl(d.psi)[k]);
     if (!update) continue;
     const int before = s.Al[k];
-    const int after = assoc_of(M, before, el, [&](int m) { return s.Sacc[m * K + k]; });
-    if (sc.tie_rel > 0.0 && assoc_near_tie(M, sc.tie_rel, [&](int m) { return s.Sacc[m * K + k]; })) note_tie(d);
+    const auto S = [&](int m) { return Sg ? Sg[m * K + k] : s.Sacc[m * K + k]; };
+    const int after = assoc_of(M, before, el, S);
+    if (sc.tie_rel > 0.0 && assoc_near_tie(M, sc.tie_rel, S)) note_tie(d);
     gl(d.A)[(size_t)wr * K + k] = after;
     if (after != before) atomicAdd(changes, 1);
     if (!el) {
@@ -2024,7 +2054,8 @@ batch_kernel(const Drop* __restrict__ drops, const int2* __restrict__ slots, int
       if (d.wave > 0)
         carve_waves((LDS char*)smem, d.M, d.K, d.L, d.wave, blockDim.x >> 6, &s_tab, s_wtab);
       else
-        carve_lds((LDS char*)smem, d.M, d.K, d.L, sd.tile, blockDim.x, &s_tab);
+        carve_lds((LDS char*)smem, d.M, d.K, d.L, sd.tile, blockDim.x, &s_tab, kAllParts, d.sdev);
+      if (d.sdev) s_tab.Sg = d.S_part + (size_t)sl.y * d.M * d.K;
     }
     __syncthreads();
     if (d.group <= 1)
@@ -2231,6 +2262,28 @@ int balanced_tile(int nb, int cap, Fits fits) {
   return (nb + tiles - 1) / tiles;
 }
 
+// Subcarriers per tile for a workgroup of nth threads holding nb
+// subcarriers, and whether the tiles sum the association metric in device
+// memory (sdev) instead of LDS: the M*K sums then leave LDS to the tile,
+// taken when that means fewer tiles per pass (each tile pays its barriers
+// and its per-slot phases once), or when without it not even one
+// subcarrier fits.
+struct TileChoice {
+  int T;
+  bool sdev;
+};
+TileChoice choose_tile(int M, int K, int L, int nb, int cap, int nth, size_t budget, bool allow_sdev) {
+  auto fits = [&](bool sd) {
+    return [=](int t) { return carve_lds(nullptr, M, K, L, t, nth, nullptr, kAllParts, sd) <= budget; };
+  };
+  const int T0 = balanced_tile(nb, cap, fits(false));
+  if (!allow_sdev) return {T0, false};
+  const int T1 = balanced_tile(nb, cap, fits(true));
+  const bool lds_fits = fits(false)(1);
+  if (!lds_fits || (nb + T1 - 1) / T1 < (nb + T0 - 1) / T0) return {T1, true};
+  return {T0, false};
+}
+
 struct Layout {
   size_t off[48];
   int n = 0;
@@ -2384,7 +2437,7 @@ int solve_one_ws(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* pr
   if (rc != ALLOC_OK) return rc;
   const int M = pb->M, N = pb->N, K = pb->K, L = pb->l, NP = L * (L - 1) / 2;
   const size_t budget = ctx->lds_max - 1024;  // the kernel's static LDS stays below 1 KB
-  if (carve_lds(nullptr, M, K, L, 1, kGridBlock, nullptr) > budget) return ALLOC_ETOOBIG;
+  if (carve_lds(nullptr, M, K, L, 1, kGridBlock, nullptr, kAllParts, true) > budget) return ALLOC_ETOOBIG;
   if (hipSetDevice(ctx->device) != hipSuccess) return ALLOC_EDEVICE;
   const bool gain_dev = prm->flags & ALLOC_GAIN_ON_DEVICE;
   const bool out_dev = prm->flags & ALLOC_OUT_ON_DEVICE;
@@ -2404,9 +2457,9 @@ int solve_one_ws(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* pr
   if (2 * M * K <= kGridBlock && N >= 2) G = std::min(G, (N + 1) / 2);
   if (prm->max_groups > 0) G = std::min(G, prm->max_groups);
   const int nb = (N + G - 1) / G;
-  const int T = balanced_tile(nb, prm->tile,
-                              [&](int t) { return carve_lds(nullptr, M, K, L, t, kGridBlock, nullptr) <= budget; });
-  const size_t lds = carve_lds(nullptr, M, K, L, T, kGridBlock, nullptr);
+  const TileChoice tc = choose_tile(M, K, L, nb, prm->tile, kGridBlock, budget, true);
+  const int T = tc.T;
+  const size_t lds = carve_lds(nullptr, M, K, L, T, kGridBlock, nullptr, kAllParts, tc.sdev);
   int per_cu = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)solve_kernel, kGridBlock, lds) !=
       hipSuccess)
@@ -2572,6 +2625,7 @@ int solve_one_ws(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* pr
   sc.qos_down = prm->qos_down;
   sc.tie_rel = prm->tie_rel;
   sc.tile = T;
+  sc.sdev = tc.sdev;
   void* args[] = {(void*)&d, (void*)&sc};
   if (ctx->timing && hipEventRecord(ctx->ev0, st) != hipSuccess) return ALLOC_EDEVICE;
   if (hipLaunchCooperativeKernel((const void*)solve_kernel, dim3(G), dim3(kGridBlock), args, lds, st) !=
@@ -2629,7 +2683,7 @@ int solve_one(alloc_ctx* ctx, const alloc_problem* pb, const alloc_params* prm, 
 // inputs, state and outputs, the drop descriptors and the launch shape.
 struct BatchOff {
   size_t G, psi, el, pmax, eta, pmask, w, A, sel, p, al, be, zs, xi, zeta, ur, os, op, oz;
-  size_t Sp, rp, rhp, psp, pep, Rp, dp, svp, vqp, zrp, chg, red, bar;  // group drops only
+  size_t Sp, rp, rhp, psp, pep, Rp, dp, svp, vqp, zrp, chg, red, bar;  // group drops (Sp also for sums in device memory)
   size_t ties;                                          // near-tie count (zeroed with the barriers)
   size_t wp0, wxi, wz;                                  // host warm starts, staged
 };
@@ -2644,6 +2698,8 @@ struct BatchPlan {
   std::vector<Drop> drops;
   std::vector<int2> slots;  // (drop, rank), largest work per slot first
   std::vector<int> group;
+  std::vector<TileChoice> tiles;  // per drop: subcarriers per tile, sums in device memory
+  std::vector<int> waves;         // per drop: subcarriers per wave tile, 0 = workgroup tiles
   std::vector<std::vector<double>> psis;
   std::vector<std::vector<uint8_t>> els;
   std::vector<int> Ms, Ns, Ks, Ls;
@@ -2691,7 +2747,7 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
   size_t need = 0, need_wave = 0;
   for (int b = 0; b < B; ++b) {
     const alloc_problem& pb = probs[b];
-    need = std::max(need, carve_lds(nullptr, pb.M, pb.K, pb.l, 1, nthreads, nullptr));
+    need = std::max(need, carve_lds(nullptr, pb.M, pb.K, pb.l, 1, nthreads, nullptr, kAllParts, true));
     if (prm->wave > 0) {
       const size_t w = carve_waves(nullptr, pb.M, pb.K, pb.l, prm->wave, nwaves, nullptr, nullptr);
       if (w <= full) need_wave = std::max(need_wave, w);
@@ -2730,6 +2786,18 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
     if (w > above * avg)
       P.group[b] = (int)std::min<double>({std::floor(w / avg + 0.5), (double)cap, (double)probs[b].N});
     P.group[b] = std::max(1, P.group[b]);
+  }
+  P.tiles.assign(B, TileChoice{1, false});
+  P.waves.assign(B, 0);
+  for (int b = 0; b < B; ++b) {
+    const alloc_problem& pb = probs[b];
+    const int g = P.group[b];
+    P.waves[b] = (g == 1 && prm->wave > 0 &&
+                  carve_waves(nullptr, pb.M, pb.K, pb.l, prm->wave, nwaves, nullptr, nullptr) <= budget)
+                     ? prm->wave
+                     : 0;
+    const int nb = (pb.N + g - 1) / g;  // subcarriers of one rank
+    P.tiles[b] = choose_tile(pb.M, pb.K, pb.l, nb, prm->tile, nthreads, budget, P.waves[b] == 0);
   }
 
   P.B = B;
@@ -2789,8 +2857,8 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
     P.off[b].zs = add(sizeof(double) * 3 * M * N * L * L);
     P.off[b].G = add(gain_dev ? 0 : sizeof(float) * M * N * K);
     const size_t g = P.group[b];
+    if (g > 1 || P.tiles[b].sdev) P.off[b].Sp = add(sizeof(double) * g * M * K);
     if (g > 1) {
-      P.off[b].Sp = add(sizeof(double) * g * M * K);
       P.off[b].rp = add(sizeof(double) * g * K);
       P.off[b].rhp = add(sizeof(double) * g * K);
       P.off[b].psp = add(sizeof(double) * g * M);
@@ -2881,8 +2949,8 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
     d.ties = (unsigned*)(ws + o.ties);
     const int g = P.group[b];
     d.group = g;
+    if (g > 1 || P.tiles[b].sdev) d.S_part = (double*)(ws + o.Sp);
     if (g > 1) {
-      d.S_part = (double*)(ws + o.Sp);
       d.r_part = (double*)(ws + o.rp);
       d.rh_part = (double*)(ws + o.rhp);
       d.psum_part = (double*)(ws + o.psp);
@@ -2896,14 +2964,9 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
       d.red = (double*)(ws + o.red);
       d.bar = (unsigned*)(ws + o.bar);
     }
-    const int nb = (N + g - 1) / g;  // subcarriers of one rank
-    const int T = balanced_tile(nb, prm->tile,
-                                [&](int t) { return carve_lds(nullptr, M, K, L, t, nthreads, nullptr) <= budget; });
-    d.tile = T;
-    d.wave = (g == 1 && prm->wave > 0 &&
-              carve_waves(nullptr, M, K, L, prm->wave, nwaves, nullptr, nullptr) <= budget)
-                 ? prm->wave
-                 : 0;
+    d.tile = P.tiles[b].T;
+    d.sdev = P.tiles[b].sdev;
+    d.wave = P.waves[b];
   }
   // slots, largest work per slot first; a drop's slots are consecutive
   std::vector<int> order(B);
@@ -2932,6 +2995,7 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
   sc.qos_down = prm->qos_down;
   sc.tie_rel = prm->tie_rel;
   sc.tile = 1;
+  sc.sdev = 0;
   P.lds = budget;
   P.grid = std::min(S, cap);
   return ALLOC_OK;
