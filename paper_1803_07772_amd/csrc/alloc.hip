@@ -283,7 +283,7 @@ struct Lds {
   LDS double* Racc;   // [M]
   LDS double* dmax;   // [M]
   LDS double* svacc;  // [M] C14 violation
-  LDS double* red;    // [threads] scratch for reductions
+  LDS double* red;    // [threads / 64] one value per wave (block_sum)
   LDS double* tmp;    // [M+2] reduction results
 };
 
@@ -362,7 +362,7 @@ __host__ __device__ inline size_t carve_lds(LDS char* base, int M, int K, int L,
   s.xi = (LDS double*)take(sizeof(double) * M);
   s.eta = (LDS double*)take(sizeof(double) * M);
   s.pmask = (LDS double*)take(sizeof(double) * M);
-  s.red = (LDS double*)take(sizeof(double) * nth);
+  s.red = (LDS double*)take(sizeof(double) * (nth / 64));
   s.tmp = (LDS double*)take(sizeof(double) * (M + 2));
   part = kTile;
   s.su = (LDS int*)take(sizeof(int) * TML);

@@ -325,6 +325,35 @@ def test_group_scheduled_large_drop_matches_oracle(ctx):
         assert np.array_equal(x.sel, res[1].sel) and np.array_equal(x.rrh_of_user, res[1].rrh_of_user)
 
 
+def test_association_sums_in_device_memory(ctx):
+    """A 17 x 64 x 256 drop fits one subcarrier per 1024-thread workgroup's
+    tile with its M*K association sums in LDS and two with them in device
+    memory, which the solvers then choose.  Solved by one workgroup and by
+    four (batched solver) and by sixteen (grid solver), with the sums in
+    device memory and, under a tile cap of one, in LDS: every case against
+    the oracle."""
+    import torch
+
+    import paper_1803_07772_amd as pa
+    rc = synth.CFG3.with_sizes(17, 64, 256, 64)
+    rc.l = 3
+    d = synth.make_drop(rc, 7, 0)
+    o = oracle.solve(d, oracle.Params(fixed_count=0, sweeps_per_dinkelbach=60))
+    p = pa.Params(fixed_count=0, sweeps_per_dinkelbach=60, block=1024)
+    g = torch.from_numpy(d.gain).cuda()
+    for where, tile in (("device memory", 0), ("LDS", 1)):
+        for groups in (1, 4, 16):
+            q = dataclasses.replace(p, max_groups=groups, tile=tile)
+            print(f"[gpu case] 17x64x256 l=3, sums in {where}, {groups} workgroups", flush=True)
+            if groups == 16:
+                r = ctx.solve(d, q, gain=g)
+            else:
+                r = ctx.solve_batch([d], q, gains=[g])[0]
+            info = parity.compare(d, r, o, label=f"sums in {where}, {groups} workgroups")
+            parity.check_structure(d, r)
+            print(info, flush=True)
+
+
 def test_group_scheduled_graph_replays(ctx):
     """Group barriers start each replay from zero arrivals."""
     import paper_1803_07772_amd as pa
