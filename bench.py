@@ -62,7 +62,7 @@ def parse():
     ap.add_argument("--eval-drops", type=int, default=64,
                     help="fresh drops of that generator the warm start is evaluated on")
     ap.add_argument("--train-steps", type=int, default=300)
-    ap.add_argument("--warm-cap", type=int, default=6,
+    ap.add_argument("--warm-cap", type=int, default=4,
                     help="Dinkelbach steps of the warm-started attempt before it falls back to the cold solve")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
