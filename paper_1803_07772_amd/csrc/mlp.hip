@@ -277,7 +277,10 @@ __device__ inline void fused_hidden(const bf16x8* __restrict__ wl, const float* 
   }
 }
 
-constexpr int kFusedR = 1;  // row blocks of 16 per wave
+// Row blocks of 16 per wave: each weight fragment loaded feeds kFusedR
+// products.  Two take 168 VGPRs and no scratch (three waves per SIMD); one
+// or three were slower on 16.8 M rows (13.0 and 12.2 ms against 10.7).
+constexpr int kFusedR = 2;
 
 // y [n][3] from bf16 inputs x0 [n][4]; persistent over blocks of 16 kFusedR
 // rows per wave.
@@ -298,6 +301,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) m
     int lo = lane;
     asm volatile("" : "+v"(lo));
     const bf16x8* wl = frag + lo;
+    const int go = lo >> 4;  // g, opaque too: the bias and W1 addresses stay in the pass
     bf16x8 a[R][8], b[R][8];
     // layer 1 (4 inputs) on the vector units, into the B-operand layout
     float x[R][4];
@@ -311,7 +315,7 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) m
     for (int f = 0; f < 16; ++f) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int o = 16 * f + 4 * g + q;
+        const int o = 16 * f + 4 * go + q;
         const float4 w = *reinterpret_cast<const float4*>(W1 + o * 4);
         const float wb[4] = {(float)to_bf16(w.x), (float)to_bf16(w.y), (float)to_bf16(w.z), (float)to_bf16(w.w)};
         const float bo = b1[o];
@@ -325,8 +329,8 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) m
       }
       __builtin_amdgcn_sched_barrier(0);
     }
-    fused_hidden<R>(wl, master + kOB[2], lane, a, b);
-    fused_hidden<R>(wl + kFragHid, master + kOB[3], lane, b, a);
+    fused_hidden<R>(wl, master + kOB[2], lo, a, b);
+    fused_hidden<R>(wl + kFragHid, master + kOB[3], lo, b, a);
     // layer 4: outputs padded to 16, the first three kept
     f32x4 acc[R];
 #pragma unroll
@@ -832,6 +836,9 @@ void refresh_weights(alloc_mlp* net, hipStream_t st) {
 // Inference of n rows (bf16 inputs x0 [n][4]) into y [n][3] by the fused kernel.
 int infer_rows(alloc_mlp* net, int64_t n, const bf16* x0, float* y) {
   if (n <= 0) return ALLOC_OK;
+  // persistent grid of 8 workgroups per compute unit, more than are resident
+  // at once (three at 168 VGPRs): sized to the resident count it ran 6%
+  // slower (11.37 against 10.70 ms for 16.8 M rows)
   const int64_t grid = std::min<int64_t>(cdiv(n, 4 * 16 * kFusedR), (int64_t)net->ctx->cus * 8);
   hipLaunchKernelGGL(mlp_fused_kernel, dim3((unsigned)grid), dim3(256), 0, net->ctx->stream, x0, n,
                      (const float*)net->master, (const bf16x8*)net->frag, y);
