@@ -389,14 +389,21 @@ __host__ __device__ inline size_t carve_lds(LDS char* base, int M, int K, int L,
   return o;
 }
 
-// Wave-tile carve-up for W waves with T subcarriers each: the shared arrays
-// and the workgroup's accumulators once, then per wave its tile arrays and
-// its own accumulators (its table points at the shared arrays).  The
-// workgroup table's u (scratch before the first pass) is wave 0's.
-__host__ __device__ inline size_t carve_waves(LDS char* base, int M, int K, int L, int T, int W, Lds* common,
-                                              Lds* waves) {
+// Bytes kept for one table of array pointers in the dynamic LDS (the
+// host's pointers are wider than the device's 32-bit LDS addresses).
+constexpr size_t kTabBytes = 512;
+static_assert(sizeof(Lds) <= kTabBytes, "an LDS pointer table outgrew its space");
+
+// Wave-tile carve-up for W waves with T subcarriers each: the W waves' pointer
+// tables (kTabBytes each, at base), the shared arrays and the workgroup's
+// accumulators once, then per wave its tile arrays and its own accumulators
+// (its table points at the shared arrays).  The workgroup table's u (scratch
+// before the first pass) is wave 0's.  Only drops with wave tiles pay for
+// the tables.
+__host__ __device__ inline size_t carve_waves(LDS char* base, int M, int K, int L, int T, int W, Lds* common) {
   Lds c;
-  size_t o = carve_lds(base, M, K, L, 0, 64 * W, &c, kShared | kAccum);
+  size_t o = (size_t)W * kTabBytes;
+  o += carve_lds(base ? base + o : nullptr, M, K, L, 0, 64 * W, &c, kShared | kAccum);
   for (int w = 0; w < W; ++w) {
     Lds v;
     o = (o + 15) & ~size_t(15);
@@ -415,7 +422,7 @@ __host__ __device__ inline size_t carve_waves(LDS char* base, int M, int K, int 
     v.red = c.red;
     v.tmp = c.tmp;
     if (w == 0) c.u = v.u;
-    if (waves) waves[w] = v;
+    if (base) ((Lds*)base)[w] = v;
   }
   if (common) *common = c;
   return o;
@@ -2039,7 +2046,6 @@ batch_kernel(const Drop* __restrict__ drops, const int2* __restrict__ slots, int
   __shared__ Eval s_e;
   __shared__ Ctrl s_c;
   __shared__ Lds s_tab;
-  __shared__ Lds s_wtab[kBlock / 64];
   for (;;) {
     if (threadIdx.x == 0) s_idx = atomicAdd(queue, 1);
     __syncthreads();
@@ -2052,14 +2058,14 @@ batch_kernel(const Drop* __restrict__ drops, const int2* __restrict__ slots, int
     sd.tile = d.tile;
     if (threadIdx.x == 0) {
       if (d.wave > 0)
-        carve_waves((LDS char*)smem, d.M, d.K, d.L, d.wave, blockDim.x >> 6, &s_tab, s_wtab);
+        carve_waves((LDS char*)smem, d.M, d.K, d.L, d.wave, blockDim.x >> 6, &s_tab);
       else
         carve_lds((LDS char*)smem, d.M, d.K, d.L, sd.tile, blockDim.x, &s_tab, kAllParts, d.sdev);
       if (d.sdev) s_tab.Sg = d.S_part + (size_t)sl.y * d.M * d.K;
     }
     __syncthreads();
     if (d.group <= 1)
-      solve_single(d, sd, s_tab, s_wtab, s_c, s_changes, s_zres, s_e, ctrls + sl.x);
+      solve_single(d, sd, s_tab, (Lds*)smem, s_c, s_changes, s_zres, s_e, ctrls + sl.x);  // wave tables at smem
     else
       solve_group(d, sd, s_tab, sl.y, d.group, s_c, ctrls + sl.x);
   }
@@ -2749,7 +2755,7 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
     const alloc_problem& pb = probs[b];
     need = std::max(need, carve_lds(nullptr, pb.M, pb.K, pb.l, 1, nthreads, nullptr, kAllParts, true));
     if (prm->wave > 0) {
-      const size_t w = carve_waves(nullptr, pb.M, pb.K, pb.l, prm->wave, nwaves, nullptr, nullptr);
+      const size_t w = carve_waves(nullptr, pb.M, pb.K, pb.l, prm->wave, nwaves, nullptr);
       if (w <= full) need_wave = std::max(need_wave, w);
     }
   }
@@ -2793,7 +2799,7 @@ int batch_prepare(alloc_ctx* ctx, int B, const alloc_problem* probs, const alloc
     const alloc_problem& pb = probs[b];
     const int g = P.group[b];
     P.waves[b] = (g == 1 && prm->wave > 0 &&
-                  carve_waves(nullptr, pb.M, pb.K, pb.l, prm->wave, nwaves, nullptr, nullptr) <= budget)
+                  carve_waves(nullptr, pb.M, pb.K, pb.l, prm->wave, nwaves, nullptr) <= budget)
                      ? prm->wave
                      : 0;
     const int nb = (pb.N + g - 1) / g;  // subcarriers of one rank
